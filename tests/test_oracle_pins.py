@@ -1,0 +1,334 @@
+"""Pins for the FP64 oracle against closed forms, invariants and an
+independent formulation -- so the oracle is checked by something other than
+itself before any GPU result is compared with it.
+
+Each pin is chosen so that a plausible slip in the oracle fails it:
+  * ray directions: unit length, centred-grid middle ray = forward
+    (section 3.1), clockwise azimuth, C = 0 lowest, exact azimuth spacing;
+  * ground plane: t = h / |sin(phi)| and the hit cell from plane geometry;
+  * sphere around the emitter: every ray hits (two-sided test), t bounded by
+    the facet plane distances, t = plane distance / cos(incidence);
+  * box interior: t = the slab exit distance;
+  * Moller-Trumbore vs an independent plane + signed-area formulation;
+  * tiny random scenes vs an independent brute force written here;
+  * flags on planted grazing / tie / range-edge / incidence cases;
+  * pose formulas on transforms with exact results.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2605_10457_amd import synth
+
+
+def _sensor(origin=(0, 0, 0), yaw=0.0, elev=None, rays=64, fov=360.0, rmin=0.05, rmax=1000.0):
+    if elev is None:
+        elev = synth.elevations_uniform(-15, 15, 8)
+    return synth.sensor(origin, yaw, elev, rays, fov, rmin, rmax)
+
+
+def _dir_closed(s, C, R):
+    """Section 3.1 Eq. ray_dir written with the sensor's basis."""
+    chi = s["rays_per_channel"]
+    th = (R - chi // 2) * (float(s["fov"]) / chi)
+    ph = float(s["elevation"][C])
+    d = (math.cos(th) * math.cos(ph) * s["forward"].astype(np.float64)
+         + math.sin(th) * math.cos(ph) * s["right"].astype(np.float64)
+         + math.sin(ph) * s["up"].astype(np.float64))
+    return d / np.linalg.norm(d)
+
+
+# ---------------------------------------------------------------- directions
+def test_direction_unit_and_centred_forward():
+    s = _sensor(elev=synth.elevations_full_sphere(16), rays=32)
+    d = O.ray_direction(s, 8, 16)       # middle channel, middle ray
+    assert np.allclose(d, s["forward"].astype(np.float64), atol=1e-7)
+    for C in (0, 3, 15):
+        for R in (0, 5, 31):
+            assert abs(np.linalg.norm(O.ray_direction(s, C, R)) - 1.0) < 1e-14
+
+
+def test_direction_clockwise_and_channel_order():
+    s = _sensor(elev=synth.elevations_uniform(-10, 10, 5), rays=16)
+    # f = +x, r = -y: rays after the centre ray turn toward -y (clockwise from above)
+    d_c = O.ray_direction(s, 2, 8)
+    d_n = O.ray_direction(s, 2, 9)
+    assert d_n[1] < 0 and d_c[1] == pytest.approx(0.0, abs=1e-12)
+    zs = [O.ray_direction(s, C, 3)[2] for C in range(5)]
+    assert all(a < b for a, b in zip(zs, zs[1:]))
+
+
+def test_direction_spacing_matches_grid():
+    s = _sensor(elev=synth.elevations_uniform(-20, 20, 4), rays=100, fov=90.0)
+    for C in range(4):
+        ph = float(s["elevation"][C])
+        dth = float(s["fov"]) / 100
+        for R in (0, 10, 98):
+            a = O.ray_direction(s, C, R)
+            b = O.ray_direction(s, C, R + 1)
+            # angle between neighbours on a cone of elevation phi
+            expect = math.cos(ph) ** 2 * math.cos(dth) + math.sin(ph) ** 2
+            assert float(a @ b) == pytest.approx(expect, abs=1e-14)
+            assert np.allclose(a, _dir_closed(s, C, R), atol=1e-15)
+
+
+# ---------------------------------------------------------------- ground plane
+def _ground_scene(n=20, size=40.0, seed=3):
+    rng = np.random.default_rng(seed)
+    b = synth._Builder()
+    g = synth._ground(b, size, n, rng)
+    v, f = b.build()
+    return v, f, g
+
+
+def _ground_cell(g, x, y):
+    c = g["cell"]
+    fx = (x - g["x0"]) / c
+    fy = (y - g["y0"]) / c
+    i, j = math.floor(fx), math.floor(fy)
+    if not (0 <= i < g["n"] and 0 <= j < g["n"]):
+        return None, 1.0
+    a, b = fx - i, fy - j
+    near = min(a, 1 - a, b, 1 - b, abs(a - b))
+    return 2 * (j * g["n"] + i) + (0 if a >= b else 1), near
+
+
+@pytest.mark.parametrize("yaw", [0.0, 0.7, -2.3])
+def test_ground_plane_closed_form(yaw):
+    v, f, g = _ground_scene()
+    h = 1.8
+    s = _sensor(origin=(0.3, -0.2, h), yaw=yaw, elev=synth.elevations_uniform(-40, 5, 10),
+                rays=48, rmax=60.0)
+    out = O.cast(s, v, f)
+    chi = 48
+    checked = 0
+    for gidx in range(10 * chi):
+        C, R = divmod(gidx, chi)
+        ph = float(s["elevation"][C])
+        d = _dir_closed(s, C, R)
+        t_o, k_o = out["t"][gidx], int(out["tri"][gidx])
+        if ph >= 0:
+            assert k_o == O.MISS
+            continue
+        ox, oy, oz = (float(c) for c in s["origin"])
+        t = oz / -d[2]          # plane z = 0 met by the unit ray
+        x, y = ox + t * d[0], oy + t * d[1]
+        k, near = _ground_cell(g, x, y)
+        if t > 60.0 or k is None:
+            if near > 1e-6:
+                assert k_o == O.MISS
+            continue
+        if near < 1e-9:
+            continue
+        assert k_o == k, (gidx, k_o, k)
+        assert abs(t_o - t) <= 1e-12 * t
+        checked += 1
+    assert checked > 100
+
+
+# ---------------------------------------------------------------- sphere
+def test_sphere_around_emitter_two_sided():
+    o = np.array([1.5, -2.0, 3.0])
+    R = 7.0
+    sv, sf = synth.icosphere(3)
+    v = (sv * R + o).astype(np.float32)
+    s = _sensor(origin=o, elev=synth.elevations_full_sphere(12), rays=24)
+    out = O.cast(s, v, sf)
+    assert np.all(out["tri"] != O.MISS), "every ray from inside must hit"
+    vv = v.astype(np.float64) - o
+    tri = vv[sf.astype(np.int64)]
+    n = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    hplane = np.abs(np.einsum("ij,ij->i", n, tri[:, 0]))
+    assert np.all(out["t"] >= hplane.min() * (1 - 1e-12)) and np.all(out["t"] <= R * (1 + 1e-6))
+    for gidx in range(0, 12 * 24, 7):
+        k = int(out["tri"][gidx])
+        d = _dir_closed(s, gidx // 24, gidx % 24)
+        # distance = plane distance / cos(incidence), by plane geometry
+        t_plane = hplane[k] / abs(float(d @ n[k]))
+        assert out["t"][gidx] == pytest.approx(t_plane, rel=1e-12)
+        # direction lies in the facet's cone: signed volumes all of one sign
+        a, b, c = tri[k]
+        vols = [np.linalg.det(np.stack([a, b, d])), np.linalg.det(np.stack([b, c, d])),
+                np.linalg.det(np.stack([c, a, d]))]
+        assert min(vols) >= -1e-12 or max(vols) <= 1e-12
+
+
+# ---------------------------------------------------------------- box interior
+def test_box_interior_slab_exit():
+    lo = np.array([-3.0, -2.0, -1.0])
+    hi = np.array([4.0, 5.0, 2.5])
+    bv, bf = synth.unit_box()
+    v = ((bv + 0.5) * (hi - lo) + lo).astype(np.float32)
+    o = np.array([0.4, 1.1, 0.3])
+    s = _sensor(origin=o, yaw=0.3, elev=synth.elevations_full_sphere(9), rays=20)
+    out = O.cast(s, v, bf)
+    o = s["origin"].astype(np.float64)
+    for gidx in range(9 * 20):
+        d = _dir_closed(s, gidx // 20, gidx % 20)
+        with np.errstate(divide="ignore"):
+            ex = np.where(d > 0, (hi - o) / d, np.where(d < 0, (lo - o) / d, np.inf))
+        t = ex.min()
+        axis = int(np.argmin(ex))
+        assert out["t"][gidx] == pytest.approx(t, rel=1e-12)
+        # the hit triangle belongs to the exit face
+        k = int(out["tri"][gidx])
+        face = {(2, -1): 0, (2, 1): 1, (1, -1): 2, (1, 1): 3, (0, -1): 4, (0, 1): 5}
+        assert k // 2 == face[(axis, 1 if d[axis] > 0 else -1)]
+
+
+# ---------------------------------------------------------------- MT formulation
+def _plane_area_hit(o, d, a, b, c):
+    """Independent formulation: plane intersection + signed-area barycentrics."""
+    n = np.cross(b - a, c - a)
+    dn = float(d @ n)
+    if dn == 0:
+        return None
+    t = float((a - o) @ n) / dn
+    P = o + t * d
+    A = float(n @ n)
+    wa = float(np.cross(b - P, c - P) @ n) / A
+    wb = float(np.cross(c - P, a - P) @ n) / A
+    wc = float(np.cross(a - P, b - P) @ n) / A
+    return t, (wa, wb, wc)
+
+
+def test_mt_matches_plane_area_formulation():
+    rng = np.random.default_rng(11)
+    s = _sensor(origin=(0.0, 0.0, 0.0), elev=synth.elevations_full_sphere(16), rays=32)
+    o = np.zeros(3)
+    n_inside = n_outside = 0
+    for trial in range(300):
+        g = int(rng.integers(0, 16 * 32))
+        d = O.ray_direction(s, g // 32, g % 32)
+        # a triangle around a point on the ray (inside) or beside it (outside)
+        center = d * rng.uniform(2, 50)
+        basis = np.linalg.svd(np.stack([d, d, d]))[2][1:]
+        pts = center + rng.normal(0, 1.0, (3, 2)) @ basis + rng.normal(0, 0.3, (3, 1)) * d
+        a, b, c = pts
+        w = rng.dirichlet([1, 1, 1])
+        inside = rng.uniform() < 0.6
+        if not inside:
+            w = np.array([w[0] + 0.4, w[1], w[2] - 0.4])
+        P = w[0] * a + w[1] * b + w[2] * c
+        # move the triangle so the ray meets its plane at P
+        shift = P - d * float(d @ P)
+        a, b, c = a - shift, b - shift, c - shift
+        v = np.stack([a, b, c]).astype(np.float32)
+        f = np.array([[0, 1, 2]], np.uint32)
+        av, bv_, cv = v.astype(np.float64)
+        ref = _plane_area_hit(o, d, av, bv_, cv)
+        pr = O.pair(s, v, f, g, 0)
+        if ref is None:
+            continue
+        t, ws = ref
+        if min(abs(x) for x in ws) < 1e-6:
+            continue
+        assert pr["hit"] == (min(ws) >= 0), (trial, ws)
+        if pr["hit"]:
+            assert pr["t"] == pytest.approx(t, rel=1e-11)
+            n_inside += 1
+        else:
+            n_outside += 1
+    assert n_inside > 50 and n_outside > 50
+
+
+def test_tiny_random_scenes_vs_independent_brute_force():
+    for seed in range(4):
+        v, f = synth.small_random_scene(seed, n_tris=40)
+        s = _sensor(origin=(0.1, 0.2, 0.05), yaw=0.4, elev=synth.elevations_full_sphere(10),
+                    rays=24, rmin=0.05, rmax=30.0)
+        out = O.cast(s, v, f)
+        vv = v.astype(np.float64)
+        o = s["origin"].astype(np.float64)
+        for gidx in range(10 * 24):
+            if out["flags"][gidx] & (O.GRAZING | O.NEAR_TIE | O.RANGE_EDGE):
+                continue
+            d = O.ray_direction(s, gidx // 24, gidx % 24)
+            best = (math.inf, O.MISS)
+            for k in range(f.shape[0]):
+                a, b, c = vv[f[k].astype(np.int64)]
+                r = _plane_area_hit(o, d, a, b, c)
+                if r is None:
+                    continue
+                t, ws = r
+                if min(ws) >= 0 and 0.05 <= t <= 30.0 and (t, k) < best:
+                    best = (t, k)
+            assert int(out["tri"][gidx]) == best[1], (seed, gidx)
+            if best[1] != O.MISS:
+                assert out["t"][gidx] == pytest.approx(best[0], rel=1e-10)
+
+
+# ---------------------------------------------------------------- flags
+def test_flags_planted_cases():
+    s = _sensor(origin=(0, 0, 0), elev=np.array([0.0], np.float32), rays=4, fov=360.0,
+                rmin=0.05, rmax=10.0)
+    # ray R=2 points along +x (theta = 0).  Wall at x = 5 split along the ray.
+    wall = np.array([[5, 0, -1], [5, 3, -1], [5, 0, 1],     # shares the edge y=0 ... z
+                     [5, 0, -1], [5, 0, 1], [5, -3, 1]], np.float32)
+    f = np.array([[0, 1, 2], [3, 4, 5]], np.uint32)
+    out = O.cast(s, wall, f, rays=np.array([2], np.uint32))
+    assert out["flags"][0] & O.GRAZING
+    # duplicated triangle: near tie, smaller id wins
+    dup = np.array([[5, -1, -1], [5, 1, -1], [5, 0, 1]] * 2, np.float32)
+    f2 = np.array([[0, 1, 2], [3, 4, 5]], np.uint32)
+    out = O.cast(s, dup, f2, rays=np.array([2], np.uint32))
+    assert out["tri"][0] == 0 and out["flags"][0] & O.NEAR_TIE
+    assert not (out["flags"][0] & O.GRAZING)
+    # wall exactly at range_max
+    far = np.array([[10, -1, -1], [10, 1, -1], [10, 0, 1]], np.float32)
+    out = O.cast(s, far, np.array([[0, 1, 2]], np.uint32), rays=np.array([2], np.uint32))
+    assert out["flags"][0] & O.RANGE_EDGE
+    # nearly edge-on wall: grazing incidence
+    tilt = np.array([[2, -0.05, -1], [8, 0.05, -1], [5, 0.0, 1]], np.float32)
+    out = O.cast(s, tilt, np.array([[0, 1, 2]], np.uint32), rays=np.array([2], np.uint32))
+    assert out["tri"][0] == 0 and out["flags"][0] & O.GRAZING_INCIDENCE
+    # clean hit: no flags
+    clean = np.array([[5, -1, -1], [5, 1, -1], [5, 0, 1]], np.float32)
+    out = O.cast(s, clean, np.array([[0, 1, 2]], np.uint32), rays=np.array([2], np.uint32))
+    assert out["tri"][0] == 0 and out["flags"][0] == 0
+    assert out["t"][0] == pytest.approx(5.0, rel=1e-15)
+
+
+def test_single_sided_mode():
+    s = _sensor(origin=(0, 0, 0), elev=np.array([0.0], np.float32), rays=4)
+    ccw_facing = np.array([[5, -1, -1], [5, 0, 1], [5, 1, -1]], np.float32)  # normal -x: faces o
+    cw = ccw_facing[[0, 2, 1]]
+    f = np.array([[0, 1, 2]], np.uint32)
+    s1 = dict(s, oracle_flags=1)
+    n1 = np.cross(ccw_facing[1] - ccw_facing[0], ccw_facing[2] - ccw_facing[0])
+    assert n1[0] < 0
+    assert O.cast(s1, ccw_facing, f, rays=np.array([2], np.uint32))["tri"][0] == 0
+    assert O.cast(s1, cw, f, rays=np.array([2], np.uint32))["tri"][0] == O.MISS
+    assert O.cast(s, cw, f, rays=np.array([2], np.uint32))["tri"][0] == 0
+
+
+# ---------------------------------------------------------------- pose
+def test_pose_rigid_exact_cases():
+    rng = np.random.default_rng(5)
+    rest = rng.uniform(-10, 10, (100, 3)).astype(np.float32)
+    I = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0]], np.float32)
+    assert np.array_equal(O.pose_rigid(rest, I), rest)
+    T = I.copy()
+    T[:, 3] = [3, -4, 5]
+    assert np.array_equal(O.pose_rigid(rest, T), (rest.astype(np.float64) + [3, -4, 5]).astype(np.float32))
+    Rz = np.array([[0, -1, 0, 1], [1, 0, 0, 2], [0, 0, 2, 0]], np.float32)
+    out = O.pose_rigid(rest, Rz)
+    assert np.array_equal(out[:, 0], (-rest[:, 1].astype(np.float64) + 1).astype(np.float32))
+    assert np.array_equal(out[:, 1], (rest[:, 0].astype(np.float64) + 2).astype(np.float32))
+    assert np.array_equal(out[:, 2], rest[:, 2] * 2)
+
+
+def test_pose_deform_phases():
+    rng = np.random.default_rng(6)
+    rest = rng.uniform(-10, 10, (50, 3)).astype(np.float32)
+    nrm = rng.normal(0, 1, (50, 3))
+    nrm = (nrm / np.linalg.norm(nrm, axis=1, keepdims=True)).astype(np.float32)
+    zero = np.zeros(50, np.float32)
+    assert np.array_equal(O.pose_deform(rest, nrm, zero, 0.1, 2 * math.pi, 0.0), rest)
+    half = np.full(50, np.float32(math.pi / 2))
+    out = O.pose_deform(rest, nrm, half, 0.5, 1.0, 0.0)
+    ref = rest.astype(np.float64) + 0.5 * math.sin(float(np.float32(math.pi / 2))) * nrm.astype(np.float64)
+    assert np.array_equal(out, ref.astype(np.float32))
