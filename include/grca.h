@@ -1,0 +1,253 @@
+/*
+ * grca.h -- C ABI of the MI355X (gfx950) emitter-centric closest-hit LiDAR
+ * ray caster.
+ *
+ * The problem (section 1.1, "Problem Statement"): a LiDAR fires many rays into
+ * a scene of triangles; for every ray find the closest triangle it intersects
+ * and the distance to it.  No acceleration structure is built.  For every
+ * (triangle, origin) pair the library computes the triangle's apparent
+ * angular extent as seen from the emitter (sections 3.2-3.8: the channel cones
+ * of section 3.2, channel and ray indexing of sections 3.3-3.4) and turns it
+ * into the candidate channels and, within each channel, the candidate azimuth
+ * rays (Observation 1).  Only those candidate pairs are run through a
+ * ray-triangle test, and each ray keeps its closest (distance, triangle id)
+ * through a 64-bit atomic minimum on a packed key (appendix "Per-Ray Distance
+ * Encoding", extended by the triangle id).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Units are metres and radians.  Vertex coordinates are FP32.
+ *  - Status codes only; no C++ exception crosses this boundary.  On any
+ *    non-OK status, grca_last_error() describes the failure and the prior
+ *    state is left untouched unless stated otherwise.
+ *  - A context binds one HIP device and is NOT thread-safe: callers serialise
+ *    calls on one context.  Different contexts are independent.
+ *  - `hip_stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued on it in order.
+ *  - Pointers flagged GRCA_MEM_DEVICE are device pointers on the context's
+ *    device; otherwise they are host pointers.  Input buffers are copied into
+ *    library-owned device memory (in stream order for device pointers): the
+ *    caller may reuse or free them once the call returns (host) or once the
+ *    stream reaches the copy (device).
+ */
+#ifndef GRCA_H
+#define GRCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct grca_context grca_context;
+typedef struct grca_frame grca_frame;
+typedef struct grca_workspace grca_workspace;
+
+typedef enum {
+  GRCA_OK = 0,
+  GRCA_ERR_INVALID_ARG = 1, /* bad pointer, size, index, non-finite value, ...    */
+  GRCA_ERR_OUT_OF_MEMORY = 2,
+  GRCA_ERR_DEVICE = 3,      /* a HIP call failed (message carries the HIP error)   */
+  GRCA_ERR_CAPACITY = 4,    /* a work queue overflowed and could not be regrown    */
+  GRCA_ERR_NOT_FOUND = 5    /* unknown scene or sensor id                          */
+} grca_status;
+
+/* Triangle id written for rays that hit nothing (their distance is +inf,
+ * the miss sentinel of appendix "Pipeline Overview"). */
+#define GRCA_MISS_TRI 0xFFFFFFFFu
+
+/* flags (bitwise OR) */
+#define GRCA_MEM_HOST 0u             /* caller pointers are host memory                  */
+#define GRCA_MEM_DEVICE 1u           /* caller pointers are device memory                */
+#define GRCA_UPDATE_VERTICES_ONLY 2u /* scene_update: keep topology, indices may be NULL */
+#define GRCA_CAST_ALL_PAIRS 8u       /* cast: test every ray against every triangle (no
+                                        culling; the reference for "culling never drops
+                                        a hit").  Same per-pair arithmetic, so culled and
+                                        all-pairs outputs are bitwise equal.            */
+
+/* ---- context ------------------------------------------------------------- */
+
+/* Create a context on HIP device `hip_device`.  *out receives the handle. */
+grca_status grca_create(int hip_device, grca_context** out);
+/* Destroy a context and free every device buffer it owns (waits for its work). */
+void grca_destroy(grca_context* ctx);
+/* Message for the last non-OK status returned on `ctx` ("" if none).  The
+ * string is owned by the context and valid until its next call. */
+const char* grca_last_error(const grca_context* ctx);
+
+/* ---- scenes ---------------------------------------------------------------- */
+
+/* Create or replace scene `scene_id` (any 32-bit id; one context holds many
+ * scenes, e.g. one per serving client).
+ *  vertices_xyz: num_vertices * 3 FP32, xyz-interleaved.  Stored on the device
+ *                as structure-of-arrays x[], y[], z[].
+ *  indices:      num_triangles * 3 uint32; triangle k uses vertices
+ *                indices[3k..3k+2] and is reported as id k.
+ *  flags:        GRCA_MEM_DEVICE for device pointers; GRCA_UPDATE_VERTICES_ONLY
+ *                rewrites positions only (num_vertices must equal the scene's).
+ * Errors: INVALID_ARG for an index >= num_vertices, a non-finite coordinate
+ * (host inputs are validated on the host; device inputs by a device pass
+ * before the scene is replaced), num_triangles >= 2^31.  Synchronous with
+ * respect to `hip_stream` for host inputs. */
+grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id, const float* vertices_xyz,
+                              uint32_t num_vertices, const uint32_t* indices,
+                              uint32_t num_triangles, uint32_t flags, void* hip_stream);
+/* Free scene `scene_id` and its dynamic-geometry tables. */
+grca_status grca_scene_release(grca_context* ctx, uint32_t scene_id);
+
+/* Dynamic geometry (the per-frame re-posing of dynamic meshes, section 5
+ * "Dynamic meshes"; evaluated on the device in FP64 and rounded once to FP32).
+ *
+ * grca_scene_set_rigid: declare `num_instances` rigid instances; instance i
+ * owns vertices [vertex_start[i], vertex_start[i] + vertex_count[i]).  The
+ * scene's current positions of those ranges become the instances' rest
+ * positions.  Ranges must be disjoint and inside the scene (host arrays). */
+grca_status grca_scene_set_rigid(grca_context* ctx, uint32_t scene_id, uint32_t num_instances,
+                                 const uint32_t* vertex_start, const uint32_t* vertex_count,
+                                 void* hip_stream);
+
+/* One deformable vertex range: v = v_rest + amplitude * sin(omega * t + phase_v) * n_v. */
+typedef struct {
+  uint32_t vertex_start;
+  uint32_t vertex_count;
+  float amplitude; /* metres  */
+  float omega;     /* rad / s */
+} grca_deform_group;
+
+/* grca_scene_set_deform: declare deformable ranges.  normals_xyz and phases
+ * (host arrays) hold sum(vertex_count) entries in group order.  The current
+ * positions of those ranges become the rest positions. */
+grca_status grca_scene_set_deform(grca_context* ctx, uint32_t scene_id, uint32_t num_groups,
+                                  const grca_deform_group* groups, const float* normals_xyz,
+                                  const float* phases, void* hip_stream);
+
+/* Re-pose the dynamic geometry: rigid instance i gets v = M_i[:, 0:3] v_rest +
+ * M_i[:, 3] (instance_matrices: num_instances row-major 3x4 FP32, host or
+ * device per flags; may be NULL if the scene has no rigid instances), and the
+ * deformable ranges are evaluated at time `time_s`.  Asynchronous on
+ * hip_stream. */
+grca_status grca_scene_pose(grca_context* ctx, uint32_t scene_id, const float* instance_matrices,
+                            double time_s, uint32_t flags, void* hip_stream);
+
+/* ---- sensors ---------------------------------------------------------------- */
+
+/* A spinning LiDAR (section 3.1).  Ray (C, R) has elevation
+ * phi_C = channel_elevation_rad[C] and azimuth
+ * theta_R = (R - floor(rays_per_channel / 2)) * fov_rad / rays_per_channel,
+ * and direction d = cos(theta) cos(phi) f + sin(theta) cos(phi) r + sin(phi) u
+ * (Eq. ray_dir).  theta grows from `forward` toward `right`. */
+typedef struct {
+  uint32_t scene_id;                  /* scene this sensor observes                        */
+  float origin[3];                    /* o                                                 */
+  float forward[3], right[3], up[3];  /* f, r, u: orthonormal within 1e-6                  */
+  uint32_t num_channels;              /* gamma in [1, 65535]                               */
+  const float* channel_elevation_rad; /* gamma host values, strictly ascending, in
+                                         [-pi/2 - 1e-6, pi/2 + 1e-6]; C = 0 is the lowest   */
+  uint32_t rays_per_channel;          /* chi in [1, 65535]                                 */
+  float fov_rad;                      /* (0, 2 pi]; |fov - 2 pi| <= 1e-6 means a full spin
+                                         whose azimuth index wraps                          */
+  float range_min, range_max;         /* a hit counts iff t in [range_min, range_max];
+                                         0 < range_min <= range_max < +inf                  */
+} grca_sensor_desc;
+
+/* Create or replace sensor `sensor_id`.  Builds the per-sensor channel and
+ * azimuth tables on the device.  Errors: INVALID_ARG (see field comments),
+ * NOT_FOUND is NOT raised here: the scene is looked up at cast time. */
+grca_status grca_sensor_config(grca_context* ctx, uint32_t sensor_id, const grca_sensor_desc* s);
+grca_status grca_sensor_release(grca_context* ctx, uint32_t sensor_id);
+
+/* ---- casting -------------------------------------------------------------- */
+
+/* Cast every ray of the listed sensors in one batched pass (one bounds pass
+ * over each referenced scene for all its listed sensors, one device work
+ * queue for all of them).  Sensors may observe different scenes.
+ *
+ * Output layout (appendix, early pass step 5, g(j, i)): the result for list
+ * position n, channel C, ray R is at O_n + C * chi_n + R with
+ * O_n = sum_{m < n} gamma_m * chi_m.
+ *  out_distance: metres along the unit ray, +INFINITY on a miss.
+ *  out_tri:      triangle id, GRCA_MISS_TRI on a miss.  Either output may be
+ *                NULL.  Host or device per GRCA_MEM_DEVICE.
+ * With device outputs the call is asynchronous on hip_stream; with host
+ * outputs it returns after the results are copied.  Equal FP32 distances
+ * resolve to the smaller triangle id, so results are bitwise reproducible and
+ * independent of batch composition.  A work-queue overflow is detected on
+ * the device; the library grows the queue and recasts (at once for host
+ * outputs, at grca_synchronize for device outputs). */
+grca_status grca_cast(grca_context* ctx, const uint32_t* sensor_ids, uint32_t num_sensors,
+                      float* out_distance, uint32_t* out_tri, uint32_t flags, void* hip_stream);
+
+/* Wait for the context's work on hip_stream, surface asynchronous errors and
+ * complete any recast an overflow requires. */
+grca_status grca_synchronize(grca_context* ctx, void* hip_stream);
+
+/* Counters of the most recent cast (waits for it). */
+typedef struct {
+  uint64_t rays;          /* rays cast                                               */
+  uint64_t pairs_tested;  /* (triangle, origin) pairs the bounds pass examined       */
+  uint64_t rect_items;    /* small-class (rectangle) work items                      */
+  uint64_t large_records; /* large-class (triangle, origin) records                  */
+  uint64_t row_items;     /* per-channel work items expanded from large records      */
+  uint64_t rtic;          /* ray-triangle intersection checks executed               */
+  uint32_t recasts;       /* overflow-driven recasts                                 */
+} grca_stats;
+grca_status grca_last_stats(grca_context* ctx, grca_stats* out);
+
+/* ---- options ----------------------------------------------------------------- */
+
+/* Tunables.  The split between the small (rectangle) and large (per-channel)
+ * classes follows Eq. sat_cond: a (triangle, origin) pair is small iff its
+ * azimuth arc does not cover the full circle, gamma_span <= small_channels and
+ * chi_span <= small_rays (the paper's default is (64, 64), Table
+ * tunable_params). */
+typedef struct {
+  uint32_t small_channels;   /* gamma_T, 1..255                                        */
+  uint32_t small_rays;       /* chi_T, 1..65535                                        */
+  uint32_t row_chunk;        /* max rays per per-channel work item (W), 1..65535       */
+  uint32_t bounds_block;     /* threads per block of the bounds pass: 64..1024, x64    */
+  uint32_t persist_waves_cu; /* resident waves per CU of the persistent kernels, 1..32 */
+  uint64_t item_capacity;    /* initial work-queue capacity (items)                    */
+  uint64_t large_capacity;   /* initial large-record queue capacity                    */
+} grca_options;
+grca_status grca_get_options(const grca_context* ctx, grca_options* out);
+grca_status grca_set_options(grca_context* ctx, const grca_options* opt);
+
+/* ---- frames: a hipGraph-captured pose + batched cast --------------------------- */
+
+/* Capture "pose the scene's dynamic geometry, then cast the listed sensors"
+ * into a HIP graph with its own work buffers.  Outputs are device pointers
+ * that the graph writes on every launch; they must stay valid for the
+ * frame's lifetime.  All sensors must observe `scene_id`. */
+grca_status grca_frame_create(grca_context* ctx, uint32_t scene_id, const uint32_t* sensor_ids,
+                              uint32_t num_sensors, float* out_distance_dev,
+                              uint32_t* out_tri_dev, grca_frame** out);
+/* Launch one frame: copy the instance matrices (host, may be NULL) and time
+ * into the frame's pose block, then replay the graph on hip_stream. */
+grca_status grca_frame_launch(grca_frame* frame, const float* instance_matrices, double time_s,
+                              void* hip_stream);
+/* Check the frame's last launch for a queue overflow (waits for it); on
+ * overflow the frame's buffers are grown, the graph is re-captured and the
+ * frame is re-run. */
+grca_status grca_frame_synchronize(grca_frame* frame, void* hip_stream);
+void grca_frame_destroy(grca_frame* frame);
+
+/* ---- workspaces: concurrent casts (serving) ------------------------------------ */
+
+/* A workspace owns the transient buffers of one cast in flight (ray keys,
+ * work queues, counters).  Casts on different workspaces may overlap on
+ * different streams.  `max_rays` bounds the rays of one cast on it.
+ * *bytes_out (optional) receives the device memory it holds. */
+grca_status grca_workspace_create(grca_context* ctx, uint64_t max_rays, uint64_t item_capacity,
+                                  grca_workspace** out, uint64_t* bytes_out);
+void grca_workspace_destroy(grca_workspace* ws);
+/* As grca_cast, on workspace `ws`; device outputs only (asynchronous). */
+grca_status grca_cast_ws(grca_context* ctx, grca_workspace* ws, const uint32_t* sensor_ids,
+                         uint32_t num_sensors, float* out_distance_dev, uint32_t* out_tri_dev,
+                         void* hip_stream);
+/* As grca_synchronize for one workspace: waits for its cast and recasts on overflow. */
+grca_status grca_workspace_synchronize(grca_context* ctx, grca_workspace* ws, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRCA_H */

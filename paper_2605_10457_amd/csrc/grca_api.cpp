@@ -1,0 +1,1288 @@
+// grca_api.cpp -- host runtime behind the C ABI of include/grca.h.
+//
+// Owns the device-resident scenes (SoA vertices + indices, rest geometry of
+// dynamic ranges), the sensor tables, the per-cast workspaces (ray keys, work
+// queues, counters) and the hipGraph frames.  Every step of a cast runs in
+// the HIP kernels of grca_kernels.hip; this file validates inputs, sizes
+// buffers, enqueues launches and handles queue overflow by growing and
+// recasting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "grca.h"
+#include "grca_launch.hpp"
+
+using namespace grca;
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+struct SceneData {
+  uint32_t nv = 0, ntri = 0;
+  float *x = nullptr, *y = nullptr, *z = nullptr;
+  uint32_t* idx = nullptr;
+  // rigid instances
+  uint32_t n_inst = 0;
+  std::vector<uint32_t> inst_start, inst_count;
+  float *rr_x = nullptr, *rr_y = nullptr, *rr_z = nullptr;  // rigid rest SoA
+  PoseBlock* rigid_blocks = nullptr;
+  uint32_t n_rigid_blocks = 0;
+  // deform groups
+  uint32_t n_groups = 0;
+  std::vector<grca_deform_group> groups;
+  float *dr_x = nullptr, *dr_y = nullptr, *dr_z = nullptr;  // deform rest SoA
+  float *dn_x = nullptr, *dn_y = nullptr, *dn_z = nullptr, *dphase = nullptr;
+  PoseBlock* deform_blocks = nullptr;
+  uint32_t n_deform_blocks = 0;
+  DeformParam* dparams = nullptr;
+  // pose inputs: [time (double)][n_inst * 12 floats]
+  double* pose_in = nullptr;
+  unsigned char* pose_stage = nullptr;  // pinned
+  size_t pose_bytes = 0;
+  hipEvent_t pose_ev = nullptr;
+};
+
+struct SensorData {
+  grca_sensor_desc desc{};
+  std::vector<float> elev;
+  float2* chan = nullptr;
+  double2* chan_d = nullptr;
+  float* sin_tab = nullptr;
+  uint16_t* lut = nullptr;
+  float2* az = nullptr;
+  uint32_t lut_size = 0;
+  double dtheta = 0.0;
+  bool wrap = false;
+};
+
+template <typename T>
+hipError_t dmalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) return hipSuccess;
+  return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+}
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void free_scene(SceneData& s) {
+  dfree(s.x); dfree(s.y); dfree(s.z); dfree(s.idx);
+  dfree(s.rr_x); dfree(s.rr_y); dfree(s.rr_z); dfree(s.rigid_blocks);
+  dfree(s.dr_x); dfree(s.dr_y); dfree(s.dr_z);
+  dfree(s.dn_x); dfree(s.dn_y); dfree(s.dn_z); dfree(s.dphase);
+  dfree(s.deform_blocks); dfree(s.dparams); dfree(s.pose_in);
+  if (s.pose_stage) (void)hipHostFree(s.pose_stage);
+  s.pose_stage = nullptr;
+  if (s.pose_ev) (void)hipEventDestroy(s.pose_ev);
+  s.pose_ev = nullptr;
+}
+
+void free_sensor(SensorData& s) {
+  dfree(s.chan); dfree(s.chan_d); dfree(s.sin_tab); dfree(s.lut); dfree(s.az);
+}
+
+}  // namespace
+
+constexpr int RING = 32;
+
+struct CastRecord {
+  bool live = false;
+  std::vector<uint32_t> ids;
+  float* dist = nullptr;
+  uint32_t* tri = nullptr;
+  uint32_t flags = 0;
+  hipStream_t st = nullptr;
+  uint64_t rays = 0, pairs = 0;
+  uint32_t recasts = 0;
+};
+
+struct grca_workspace {
+  grca_context* ctx = nullptr;
+  unsigned long long* keys = nullptr;
+  uint64_t key_cap = 0;
+  Item* items = nullptr;
+  uint64_t item_cap = 0;
+  Item* large = nullptr;
+  uint64_t large_cap = 0;
+  Counters* cnt = nullptr;       // device counters (cleared by every cast's init kernel)
+  Counters* cnt_host = nullptr;  // pinned, RING slots
+  hipEvent_t ev[RING] = {};
+  CastRecord rec[RING];
+  uint32_t next_slot = 0;
+  int last_slot = -1;
+  hipStream_t last_stream = nullptr;
+  // per-slot staging of the cast's sensor / scene tables
+  DevSensor* dsens = nullptr;        // device, RING * sens_cap
+  DevSensor* dsens_host = nullptr;   // pinned, RING * sens_cap
+  uint32_t sens_cap = 0;
+  DevScene* dscenes = nullptr;
+  DevScene* dscenes_host = nullptr;
+  uint32_t scene_cap = 0;
+  Statics* scratch = nullptr;
+  uint64_t scratch_cap = 0;
+  float* out_dist = nullptr;     // device staging for host outputs
+  uint32_t* out_tri = nullptr;
+  uint64_t out_cap = 0;
+  bool fixed = false;            // capacity set by the user (serving)
+  uint64_t bytes = 0;
+};
+
+struct grca_frame {
+  grca_context* ctx = nullptr;
+  uint32_t scene_id = 0;
+  std::vector<uint32_t> ids;
+  float* out_dist = nullptr;
+  uint32_t* out_tri = nullptr;
+  grca_workspace* ws = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct grca_context {
+  int device = 0;
+  int num_cu = 0;
+  std::map<uint32_t, SceneData> scenes;
+  std::map<uint32_t, SensorData> sensors;
+  grca_options opt{};
+  grca_workspace* def_ws = nullptr;
+  grca_workspace* last_ws = nullptr;
+  std::string err;
+};
+
+namespace {
+
+grca_status fail(const grca_context* ctx, grca_status code, const std::string& msg) {
+  if (ctx) const_cast<grca_context*>(ctx)->err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? GRCA_ERR_OUT_OF_MEMORY : GRCA_ERR_DEVICE, \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                       \
+  } while (0)
+
+#define GUARD(...)                                                       \
+  try {                                                                  \
+    __VA_ARGS__                                                          \
+  } catch (const std::bad_alloc&) {                                      \
+    return fail(ctx, GRCA_ERR_OUT_OF_MEMORY, "host allocation failed"); \
+  } catch (...) {                                                        \
+    return fail(ctx, GRCA_ERR_DEVICE, "unexpected exception");          \
+  }
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Grow the workspace buffers.  Only called while no cast is in flight on it.
+grca_status ws_reserve(grca_context* ctx, grca_workspace* ws, uint64_t rays, uint64_t items,
+                       uint64_t large, uint32_t nsens, uint32_t nscenes, uint64_t scratch,
+                       uint64_t outs) {
+  if (rays > ws->key_cap) {
+    dfree(ws->keys);
+    ws->key_cap = 0;
+    HIPCHK(dmalloc(&ws->keys, rays));
+    ws->key_cap = rays;
+  }
+  if (items > ws->item_cap) {
+    dfree(ws->items);
+    ws->item_cap = 0;
+    HIPCHK(dmalloc(&ws->items, items));
+    ws->item_cap = items;
+  }
+  if (large > ws->large_cap) {
+    dfree(ws->large);
+    ws->large_cap = 0;
+    HIPCHK(dmalloc(&ws->large, large));
+    ws->large_cap = large;
+  }
+  if (nsens > ws->sens_cap) {
+    dfree(ws->dsens);
+    if (ws->dsens_host) (void)hipHostFree(ws->dsens_host);
+    ws->dsens_host = nullptr;
+    ws->sens_cap = 0;
+    HIPCHK(dmalloc(&ws->dsens, (size_t)RING * nsens));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&ws->dsens_host),
+                         (size_t)RING * nsens * sizeof(DevSensor)));
+    ws->sens_cap = nsens;
+  }
+  if (nscenes > ws->scene_cap) {
+    dfree(ws->dscenes);
+    if (ws->dscenes_host) (void)hipHostFree(ws->dscenes_host);
+    ws->dscenes_host = nullptr;
+    ws->scene_cap = 0;
+    HIPCHK(dmalloc(&ws->dscenes, (size_t)RING * nscenes));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&ws->dscenes_host),
+                         (size_t)RING * nscenes * sizeof(DevScene)));
+    ws->scene_cap = nscenes;
+  }
+  if (scratch > ws->scratch_cap) {
+    dfree(ws->scratch);
+    ws->scratch_cap = 0;
+    HIPCHK(dmalloc(&ws->scratch, scratch));
+    ws->scratch_cap = scratch;
+  }
+  if (outs > ws->out_cap) {
+    dfree(ws->out_dist);
+    dfree(ws->out_tri);
+    ws->out_cap = 0;
+    HIPCHK(dmalloc(&ws->out_dist, outs));
+    HIPCHK(dmalloc(&ws->out_tri, outs));
+    ws->out_cap = outs;
+  }
+  ws->bytes = ws->key_cap * 8 + (ws->item_cap + ws->large_cap) * sizeof(Item) +
+              (uint64_t)RING * (ws->sens_cap * sizeof(DevSensor) + ws->scene_cap * sizeof(DevScene)) +
+              ws->scratch_cap * sizeof(Statics) + ws->out_cap * 8 + sizeof(Counters);
+  return GRCA_OK;
+}
+
+grca_status ws_init(grca_context* ctx, grca_workspace* ws) {
+  ws->ctx = ctx;
+  HIPCHK(dmalloc(&ws->cnt, 1));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&ws->cnt_host), RING * sizeof(Counters)));
+  std::memset(ws->cnt_host, 0, RING * sizeof(Counters));
+  for (int i = 0; i < RING; ++i) HIPCHK(hipEventCreateWithFlags(&ws->ev[i], hipEventDisableTiming));
+  return GRCA_OK;
+}
+
+void ws_free(grca_workspace* ws) {
+  if (!ws) return;
+  for (int i = 0; i < RING; ++i)
+    if (ws->ev[i]) (void)hipEventSynchronize(ws->ev[i]);
+  dfree(ws->keys); dfree(ws->items); dfree(ws->large); dfree(ws->cnt);
+  dfree(ws->dsens); dfree(ws->dscenes); dfree(ws->scratch);
+  dfree(ws->out_dist); dfree(ws->out_tri);
+  if (ws->cnt_host) (void)hipHostFree(ws->cnt_host);
+  if (ws->dsens_host) (void)hipHostFree(ws->dsens_host);
+  if (ws->dscenes_host) (void)hipHostFree(ws->dscenes_host);
+  for (int i = 0; i < RING; ++i)
+    if (ws->ev[i]) (void)hipEventDestroy(ws->ev[i]);
+  delete ws;
+}
+
+// The plan of one cast: sensors grouped by scene, key offsets in caller order.
+struct Plan {
+  std::vector<DevSensor> sens;
+  std::vector<DevScene> scenes;
+  uint32_t total_blocks = 0;
+  uint64_t rays = 0;
+  uint64_t pairs = 0;
+};
+
+grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32_t block,
+                      Plan& P) {
+  if (n == 0) return fail(ctx, GRCA_ERR_INVALID_ARG, "num_sensors must be >= 1");
+  if (n > 4096) return fail(ctx, GRCA_ERR_INVALID_ARG, "at most 4096 sensors per cast");
+  std::vector<const SensorData*> sd(n);
+  std::vector<uint64_t> offs(n);
+  uint64_t off = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    auto it = ctx->sensors.find(ids[i]);
+    if (it == ctx->sensors.end())
+      return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown sensor id " + std::to_string(ids[i]));
+    sd[i] = &it->second;
+    if (!ctx->scenes.count(sd[i]->desc.scene_id))
+      return fail(ctx, GRCA_ERR_NOT_FOUND,
+                  "sensor " + std::to_string(ids[i]) + " observes unknown scene " +
+                      std::to_string(sd[i]->desc.scene_id));
+    offs[i] = off;
+    off += (uint64_t)sd[i]->desc.num_channels * sd[i]->desc.rays_per_channel;
+  }
+  if (off >= (1ull << 32)) return fail(ctx, GRCA_ERR_INVALID_ARG, "more than 2^32 rays in one cast");
+  P.rays = off;
+  std::vector<uint32_t> order(n);
+  for (uint32_t i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+    return sd[a]->desc.scene_id < sd[b]->desc.scene_id;
+  });
+  P.sens.resize(n);
+  P.scenes.clear();
+  uint32_t blocks = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t i = order[k];
+    const SensorData& S = *sd[i];
+    const uint32_t sid = S.desc.scene_id;
+    if (k == 0 || sd[order[k - 1]]->desc.scene_id != sid) {
+      const SceneData& sc = ctx->scenes.at(sid);
+      DevScene ds{};
+      ds.x = sc.x; ds.y = sc.y; ds.z = sc.z; ds.idx = sc.idx; ds.ntri = sc.ntri;
+      ds.block_start = blocks;
+      ds.sensor_begin = k;
+      ds.sensor_end = k;
+      blocks += (sc.ntri + block - 1) / block;
+      P.scenes.push_back(ds);
+    }
+    DevScene& cur = P.scenes.back();
+    cur.sensor_end = k + 1;
+    P.pairs += cur.ntri;
+    DevSensor d{};
+    for (int c = 0; c < 3; ++c) {
+      d.o[c] = S.desc.origin[c]; d.f[c] = S.desc.forward[c];
+      d.r[c] = S.desc.right[c]; d.u[c] = S.desc.up[c];
+    }
+    d.dmin = S.desc.range_min;
+    d.dmax = S.desc.range_max;
+    d.gamma = S.desc.num_channels;
+    d.chi = S.desc.rays_per_channel;
+    d.key_offset = (uint32_t)offs[i];
+    d.wrap = S.wrap ? 1u : 0u;
+    d.scene = (uint32_t)(P.scenes.size() - 1);
+    d.lut_size = S.lut_size;
+    const double theta0 = -std::floor(d.chi / 2.0) * S.dtheta;
+    d.theta_start = (float)theta0;
+    d.inv_dtheta = (float)(1.0 / S.dtheta);
+    d.period_idx = (float)(kTwoPi / S.dtheta);
+    d.theta_start_d = theta0;
+    d.inv_dtheta_d = 1.0 / S.dtheta;
+    d.period_idx_d = kTwoPi / S.dtheta;
+    d.chan = S.chan; d.chan_d = S.chan_d; d.sin_tab = S.sin_tab; d.lut = S.lut; d.az = S.az;
+    P.sens[k] = d;
+  }
+  P.total_blocks = blocks;
+  return GRCA_OK;
+}
+
+uint32_t persist_blocks(const grca_context* ctx) {
+  const uint32_t waves = (uint32_t)std::max(1, ctx->num_cu) * ctx->opt.persist_waves_cu;
+  return std::max(1u, waves / 4u);
+}
+
+// Enqueue the kernels of one cast into ring slot `slot` (the slot is free and
+// the workspace buffers are large enough).
+grca_status enqueue_kernels(grca_context* ctx, grca_workspace* ws, uint32_t slot, const Plan& P,
+                            float* dist, uint32_t* tri, uint32_t flags, hipStream_t st) {
+  const grca_options& o = ctx->opt;
+  DevSensor* dsens = ws->dsens + (size_t)slot * ws->sens_cap;
+  DevScene* dscenes = ws->dscenes + (size_t)slot * ws->scene_cap;
+  std::memcpy(ws->dsens_host + (size_t)slot * ws->sens_cap, P.sens.data(),
+              P.sens.size() * sizeof(DevSensor));
+  std::memcpy(ws->dscenes_host + (size_t)slot * ws->scene_cap, P.scenes.data(),
+              P.scenes.size() * sizeof(DevScene));
+  HIPCHK(hipMemcpyAsync(dsens, ws->dsens_host + (size_t)slot * ws->sens_cap,
+                        P.sens.size() * sizeof(DevSensor), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(dscenes, ws->dscenes_host + (size_t)slot * ws->scene_cap,
+                        P.scenes.size() * sizeof(DevScene), hipMemcpyHostToDevice, st));
+  const uint32_t n = (uint32_t)P.rays;
+  const uint32_t icap = (uint32_t)std::min<uint64_t>(ws->item_cap, 0xFFFFFFFFull);
+  const uint32_t lcap = (uint32_t)std::min<uint64_t>(ws->large_cap, 0xFFFFFFFFull);
+  HIPCHK(launch_init(ws->keys, n, ws->cnt, st));
+  if (flags & GRCA_CAST_ALL_PAIRS) {
+    for (uint32_t k = 0; k < P.sens.size(); ++k) {
+      const DevSensor& d = P.sens[k];
+      HIPCHK(launch_allpairs(dscenes, dsens, k, P.scenes[d.scene].ntri, d.gamma * d.chi,
+                             ws->scratch, ws->keys, st));
+    }
+  } else {
+    HIPCHK(launch_bounds(dscenes, (uint32_t)P.scenes.size(), P.total_blocks, o.bounds_block,
+                         dsens, o.small_channels, o.small_rays, ws->items, icap, ws->large, lcap,
+                         ws->cnt, st));
+    const uint32_t pb = persist_blocks(ctx);
+    HIPCHK(launch_expand(dscenes, dsens, ws->large, ws->items, icap, lcap, o.row_chunk, ws->cnt,
+                         pb, st));
+    HIPCHK(launch_isect(dscenes, dsens, ws->items, icap, ws->cnt, ws->keys, pb, st));
+  }
+  HIPCHK(launch_resolve(ws->keys, n, dist, tri, st));
+  HIPCHK(hipMemcpyAsync(ws->cnt_host + slot, ws->cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipEventRecord(ws->ev[slot], st));
+  return GRCA_OK;
+}
+
+// New queue capacities after an overflow, from the requested counts.
+grca_status grown_caps(grca_context* ctx, const Counters& c, uint64_t& items, uint64_t& large) {
+  if (c.overflow & 2u) {
+    large = std::max<uint64_t>(large * 2, (uint64_t)c.n_large + c.n_large / 4 + 1024);
+    items = std::max<uint64_t>(items * 2, (uint64_t)c.n_items + c.n_items / 4 + 65536);
+  }
+  if (c.overflow & 1u) items = std::max<uint64_t>(items * 2, (uint64_t)c.n_items + c.n_items / 4 + 65536);
+  if (items > 0xFFFFFFF0ull || large > 0xFFFFFFF0ull)
+    return fail(ctx, GRCA_ERR_CAPACITY, "work queue would exceed 2^32 entries");
+  return GRCA_OK;
+}
+
+grca_status ws_quiesce(grca_context* ctx, grca_workspace* ws) {
+  for (int i = 0; i < RING; ++i)
+    if (ws->rec[i].live) HIPCHK(hipEventSynchronize(ws->ev[i]));
+  return GRCA_OK;
+}
+
+// Wait for every cast in flight on `ws`; recast (synchronously, with grown
+// queues) every one whose queues overflowed.
+grca_status ws_drain(grca_context* ctx, grca_workspace* ws) {
+  grca_status rc = ws_quiesce(ctx, ws);
+  if (rc != GRCA_OK) return rc;
+  for (uint32_t k = 0; k < (uint32_t)RING; ++k) {
+    const uint32_t slot = (ws->next_slot + k) % RING;  // oldest first
+    CastRecord& R = ws->rec[slot];
+    if (!R.live) continue;
+    int attempt = 0;
+    while (ws->cnt_host[slot].overflow) {
+      if (++attempt > 6) {
+        R.live = false;
+        return fail(ctx, GRCA_ERR_CAPACITY, "work queue kept overflowing after regrowth");
+      }
+      uint64_t items = ws->item_cap, large = ws->large_cap;
+      rc = grown_caps(ctx, ws->cnt_host[slot], items, large);
+      if (rc != GRCA_OK) { R.live = false; return rc; }
+      dfree(ws->items); ws->item_cap = 0;
+      dfree(ws->large); ws->large_cap = 0;
+      rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
+      if (rc != GRCA_OK) { R.live = false; return rc; }
+      Plan P;
+      rc = make_plan(ctx, R.ids.data(), (uint32_t)R.ids.size(), ctx->opt.bounds_block, P);
+      if (rc != GRCA_OK) { R.live = false; return rc; }
+      rc = enqueue_kernels(ctx, ws, slot, P, R.dist, R.tri, R.flags, R.st);
+      if (rc != GRCA_OK) { R.live = false; return rc; }
+      R.recasts++;
+      HIPCHK(hipEventSynchronize(ws->ev[slot]));
+    }
+    R.live = false;
+  }
+  return GRCA_OK;
+}
+
+grca_status check_vec(const float* v, const char* name, const grca_context* ctx) {
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(v[k])) return fail(ctx, GRCA_ERR_INVALID_ARG, std::string(name) + " not finite");
+  return GRCA_OK;
+}
+
+}  // namespace
+
+// =============================================================== context
+extern "C" grca_status grca_create(int hip_device, grca_context** out) {
+  grca_context* ctx = nullptr;
+  if (!out) return GRCA_ERR_INVALID_ARG;
+  *out = nullptr;
+  try {
+    ctx = new grca_context();
+  } catch (...) {
+    return GRCA_ERR_OUT_OF_MEMORY;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+    delete ctx;
+    return GRCA_ERR_DEVICE;
+  }
+  if (hipSetDevice(hip_device) != hipSuccess) { delete ctx; return GRCA_ERR_DEVICE; }
+  ctx->device = hip_device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) { delete ctx; return GRCA_ERR_DEVICE; }
+  ctx->num_cu = prop.multiProcessorCount;
+  ctx->opt.small_channels = 8;
+  ctx->opt.small_rays = 64;
+  ctx->opt.row_chunk = 256;
+  ctx->opt.bounds_block = 256;
+  ctx->opt.persist_waves_cu = 16;
+  ctx->opt.item_capacity = 1u << 20;
+  ctx->opt.large_capacity = 1u << 16;
+  ctx->def_ws = new grca_workspace();
+  if (ws_init(ctx, ctx->def_ws) != GRCA_OK) {
+    ws_free(ctx->def_ws);
+    delete ctx;
+    return GRCA_ERR_DEVICE;
+  }
+  *out = ctx;
+  return GRCA_OK;
+}
+
+extern "C" void grca_destroy(grca_context* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ws_free(ctx->def_ws);
+  for (auto& kv : ctx->scenes) free_scene(kv.second);
+  for (auto& kv : ctx->sensors) free_sensor(kv.second);
+  delete ctx;
+}
+
+extern "C" const char* grca_last_error(const grca_context* ctx) {
+  return ctx ? ctx->err.c_str() : "null context";
+}
+
+// =============================================================== scenes
+extern "C" grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id,
+                                         const float* vertices_xyz, uint32_t num_vertices,
+                                         const uint32_t* indices, uint32_t num_triangles,
+                                         uint32_t flags, void* hip_stream) {
+  if (!ctx) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(hip_stream);
+    const bool dev = flags & GRCA_MEM_DEVICE;
+    const bool vonly = flags & GRCA_UPDATE_VERTICES_ONLY;
+    if (num_vertices > 0 && !vertices_xyz) return fail(ctx, GRCA_ERR_INVALID_ARG, "vertices is NULL");
+    if (num_triangles >= (1u << 31)) return fail(ctx, GRCA_ERR_INVALID_ARG, "too many triangles");
+    auto it = ctx->scenes.find(scene_id);
+    if (vonly) {
+      if (it == ctx->scenes.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown scene");
+      if (it->second.nv != num_vertices)
+        return fail(ctx, GRCA_ERR_INVALID_ARG, "vertex count differs from the scene's");
+    } else if (num_triangles > 0 && !indices) {
+      return fail(ctx, GRCA_ERR_INVALID_ARG, "indices is NULL");
+    }
+    // validate before touching the stored scene
+    if (!dev) {
+      for (uint64_t i = 0; i < 3ull * num_vertices; ++i)
+        if (!std::isfinite(vertices_xyz[i]))
+          return fail(ctx, GRCA_ERR_INVALID_ARG, "non-finite vertex coordinate");
+      if (!vonly)
+        for (uint64_t i = 0; i < 3ull * num_triangles; ++i)
+          if (indices[i] >= num_vertices)
+            return fail(ctx, GRCA_ERR_INVALID_ARG, "index out of range");
+    } else {
+      uint32_t* bad = nullptr;
+      HIPCHK(dmalloc(&bad, 1));
+      uint32_t zero = 0, hbad = 0;
+      HIPCHK(hipMemcpyAsync(bad, &zero, 4, hipMemcpyHostToDevice, st));
+      HIPCHK(launch_validate(vertices_xyz, num_vertices, vonly ? nullptr : indices,
+                             vonly ? 0 : 3ull * num_triangles, bad, st));
+      HIPCHK(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      dfree(bad);
+      if (hbad & 1u) return fail(ctx, GRCA_ERR_INVALID_ARG, "non-finite vertex coordinate");
+      if (hbad & 2u) return fail(ctx, GRCA_ERR_INVALID_ARG, "index out of range");
+    }
+    SceneData fresh;
+    SceneData& sc = (it == ctx->scenes.end()) ? fresh : it->second;
+    const bool realloc_v = sc.nv != num_vertices || !sc.x;
+    if (!vonly && it != ctx->scenes.end()) {
+      // topology change drops dynamic-geometry declarations
+      HIPCHK(hipStreamSynchronize(st));
+      SceneData keep;
+      keep.x = sc.x; keep.y = sc.y; keep.z = sc.z; keep.idx = sc.idx;
+      keep.nv = sc.nv; keep.ntri = sc.ntri;
+      sc.x = sc.y = sc.z = nullptr; sc.idx = nullptr;
+      free_scene(sc);
+      sc = SceneData();
+      sc.x = keep.x; sc.y = keep.y; sc.z = keep.z; sc.idx = keep.idx;
+      sc.nv = keep.nv; sc.ntri = keep.ntri;
+    }
+    if (realloc_v) {
+      HIPCHK(hipStreamSynchronize(st));
+      dfree(sc.x); dfree(sc.y); dfree(sc.z);
+      HIPCHK(dmalloc(&sc.x, std::max(1u, num_vertices)));
+      HIPCHK(dmalloc(&sc.y, std::max(1u, num_vertices)));
+      HIPCHK(dmalloc(&sc.z, std::max(1u, num_vertices)));
+    }
+    float* tmp = nullptr;
+    if (num_vertices) {
+      const float* src = vertices_xyz;
+      if (!dev) {
+        HIPCHK(dmalloc(&tmp, 3ull * num_vertices));
+        HIPCHK(hipMemcpyAsync(tmp, vertices_xyz, 12ull * num_vertices, hipMemcpyHostToDevice, st));
+        src = tmp;
+      }
+      HIPCHK(launch_soa(src, num_vertices, sc.x, sc.y, sc.z, st));
+    }
+    if (!vonly) {
+      if (sc.ntri != num_triangles || !sc.idx) {
+        HIPCHK(hipStreamSynchronize(st));
+        dfree(sc.idx);
+        HIPCHK(dmalloc(&sc.idx, 3ull * std::max(1u, num_triangles)));
+      }
+      if (num_triangles)
+        HIPCHK(hipMemcpyAsync(sc.idx, indices, 12ull * num_triangles,
+                              dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+      sc.ntri = num_triangles;
+    }
+    sc.nv = num_vertices;
+    if (tmp) {
+      HIPCHK(hipStreamSynchronize(st));
+      dfree(tmp);
+    }
+    if (it == ctx->scenes.end()) ctx->scenes.emplace(scene_id, fresh);
+    return GRCA_OK;
+  })
+}
+
+extern "C" grca_status grca_scene_release(grca_context* ctx, uint32_t scene_id) {
+  if (!ctx) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    auto it = ctx->scenes.find(scene_id);
+    if (it == ctx->scenes.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown scene");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    free_scene(it->second);
+    ctx->scenes.erase(it);
+    return GRCA_OK;
+  })
+}
+
+namespace {
+grca_status check_ranges(grca_context* ctx, const SceneData& sc, uint32_t n, const uint32_t* st,
+                         const uint32_t* ct) {
+  std::vector<std::pair<uint64_t, uint64_t>> r(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    if ((uint64_t)st[i] + ct[i] > sc.nv)
+      return fail(ctx, GRCA_ERR_INVALID_ARG, "vertex range outside the scene");
+    r[i] = {st[i], (uint64_t)st[i] + ct[i]};
+  }
+  std::sort(r.begin(), r.end());
+  for (uint32_t i = 1; i < n; ++i)
+    if (r[i].first < r[i - 1].second) return fail(ctx, GRCA_ERR_INVALID_ARG, "vertex ranges overlap");
+  return GRCA_OK;
+}
+
+grca_status ensure_pose_block(grca_context* ctx, SceneData& sc) {
+  const size_t bytes = 8 + 48ull * sc.n_inst;
+  if (bytes == sc.pose_bytes && sc.pose_in) return GRCA_OK;
+  dfree(sc.pose_in);
+  if (sc.pose_stage) (void)hipHostFree(sc.pose_stage);
+  sc.pose_stage = nullptr;
+  HIPCHK(dmalloc(&sc.pose_in, (bytes + 7) / 8));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&sc.pose_stage), bytes));
+  std::memset(sc.pose_stage, 0, bytes);
+  if (!sc.pose_ev) HIPCHK(hipEventCreateWithFlags(&sc.pose_ev, hipEventDisableTiming));
+  sc.pose_bytes = bytes;
+  return GRCA_OK;
+}
+
+std::vector<PoseBlock> pose_blocks(uint32_t kind, const std::vector<uint32_t>& starts,
+                                   const std::vector<uint32_t>& counts) {
+  std::vector<PoseBlock> out;
+  uint32_t rest = 0;
+  for (size_t g = 0; g < starts.size(); ++g) {
+    for (uint32_t o = 0; o < counts[g]; o += 256) {
+      PoseBlock b{};
+      b.kind = kind;
+      b.group = (uint32_t)g;
+      b.v_begin = starts[g] + o;
+      b.count = std::min(256u, counts[g] - o);
+      b.rest_begin = rest + o;
+      out.push_back(b);
+    }
+    rest += counts[g];
+  }
+  return out;
+}
+}  // namespace
+
+extern "C" grca_status grca_scene_set_rigid(grca_context* ctx, uint32_t scene_id,
+                                            uint32_t num_instances, const uint32_t* vertex_start,
+                                            const uint32_t* vertex_count, void* hip_stream) {
+  if (!ctx) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    auto it = ctx->scenes.find(scene_id);
+    if (it == ctx->scenes.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown scene");
+    if (num_instances && (!vertex_start || !vertex_count))
+      return fail(ctx, GRCA_ERR_INVALID_ARG, "NULL instance arrays");
+    SceneData& sc = it->second;
+    grca_status rc = check_ranges(ctx, sc, num_instances, vertex_start, vertex_count);
+    if (rc != GRCA_OK) return rc;
+    hipStream_t st = as_stream(hip_stream);
+    HIPCHK(hipStreamSynchronize(st));
+    dfree(sc.rr_x); dfree(sc.rr_y); dfree(sc.rr_z); dfree(sc.rigid_blocks);
+    sc.inst_start.assign(vertex_start, vertex_start + num_instances);
+    sc.inst_count.assign(vertex_count, vertex_count + num_instances);
+    sc.n_inst = num_instances;
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < num_instances; ++i) total += vertex_count[i];
+    HIPCHK(dmalloc(&sc.rr_x, std::max<uint64_t>(total, 1)));
+    HIPCHK(dmalloc(&sc.rr_y, std::max<uint64_t>(total, 1)));
+    HIPCHK(dmalloc(&sc.rr_z, std::max<uint64_t>(total, 1)));
+    uint64_t r = 0;
+    for (uint32_t i = 0; i < num_instances; ++i) {
+      HIPCHK(launch_copy(sc.x + vertex_start[i], sc.rr_x + r, vertex_count[i], st));
+      HIPCHK(launch_copy(sc.y + vertex_start[i], sc.rr_y + r, vertex_count[i], st));
+      HIPCHK(launch_copy(sc.z + vertex_start[i], sc.rr_z + r, vertex_count[i], st));
+      r += vertex_count[i];
+    }
+    std::vector<PoseBlock> pb = pose_blocks(0, sc.inst_start, sc.inst_count);
+    sc.n_rigid_blocks = (uint32_t)pb.size();
+    HIPCHK(dmalloc(&sc.rigid_blocks, std::max<size_t>(pb.size(), 1)));
+    if (!pb.empty())
+      HIPCHK(hipMemcpy(sc.rigid_blocks, pb.data(), pb.size() * sizeof(PoseBlock), hipMemcpyHostToDevice));
+    rc = ensure_pose_block(ctx, sc);
+    if (rc != GRCA_OK) return rc;
+    HIPCHK(hipStreamSynchronize(st));
+    return GRCA_OK;
+  })
+}
+
+extern "C" grca_status grca_scene_set_deform(grca_context* ctx, uint32_t scene_id,
+                                             uint32_t num_groups, const grca_deform_group* groups,
+                                             const float* normals_xyz, const float* phases,
+                                             void* hip_stream) {
+  if (!ctx) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    auto it = ctx->scenes.find(scene_id);
+    if (it == ctx->scenes.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown scene");
+    if (num_groups && (!groups || !normals_xyz || !phases))
+      return fail(ctx, GRCA_ERR_INVALID_ARG, "NULL deform arrays");
+    SceneData& sc = it->second;
+    std::vector<uint32_t> st_v(num_groups), ct_v(num_groups);
+    uint64_t total = 0;
+    for (uint32_t g = 0; g < num_groups; ++g) {
+      st_v[g] = groups[g].vertex_start;
+      ct_v[g] = groups[g].vertex_count;
+      if (!std::isfinite(groups[g].amplitude) || !std::isfinite(groups[g].omega))
+        return fail(ctx, GRCA_ERR_INVALID_ARG, "non-finite deform parameter");
+      total += ct_v[g];
+    }
+    grca_status rc = check_ranges(ctx, sc, num_groups, st_v.data(), ct_v.data());
+    if (rc != GRCA_OK) return rc;
+    for (uint64_t i = 0; i < 3 * total; ++i)
+      if (!std::isfinite(normals_xyz[i])) return fail(ctx, GRCA_ERR_INVALID_ARG, "non-finite normal");
+    for (uint64_t i = 0; i < total; ++i)
+      if (!std::isfinite(phases[i])) return fail(ctx, GRCA_ERR_INVALID_ARG, "non-finite phase");
+    hipStream_t st = as_stream(hip_stream);
+    HIPCHK(hipStreamSynchronize(st));
+    dfree(sc.dr_x); dfree(sc.dr_y); dfree(sc.dr_z);
+    dfree(sc.dn_x); dfree(sc.dn_y); dfree(sc.dn_z); dfree(sc.dphase);
+    dfree(sc.deform_blocks); dfree(sc.dparams);
+    sc.groups.assign(groups, groups + num_groups);
+    sc.n_groups = num_groups;
+    const uint64_t nt = std::max<uint64_t>(total, 1);
+    HIPCHK(dmalloc(&sc.dr_x, nt)); HIPCHK(dmalloc(&sc.dr_y, nt)); HIPCHK(dmalloc(&sc.dr_z, nt));
+    HIPCHK(dmalloc(&sc.dn_x, nt)); HIPCHK(dmalloc(&sc.dn_y, nt)); HIPCHK(dmalloc(&sc.dn_z, nt));
+    HIPCHK(dmalloc(&sc.dphase, nt));
+    std::vector<float> nx(total), ny(total), nz(total);
+    for (uint64_t i = 0; i < total; ++i) {
+      nx[i] = normals_xyz[3 * i]; ny[i] = normals_xyz[3 * i + 1]; nz[i] = normals_xyz[3 * i + 2];
+    }
+    if (total) {
+      HIPCHK(hipMemcpy(sc.dn_x, nx.data(), 4 * total, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(sc.dn_y, ny.data(), 4 * total, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(sc.dn_z, nz.data(), 4 * total, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(sc.dphase, phases, 4 * total, hipMemcpyHostToDevice));
+    }
+    uint64_t r = 0;
+    for (uint32_t g = 0; g < num_groups; ++g) {
+      HIPCHK(launch_copy(sc.x + st_v[g], sc.dr_x + r, ct_v[g], st));
+      HIPCHK(launch_copy(sc.y + st_v[g], sc.dr_y + r, ct_v[g], st));
+      HIPCHK(launch_copy(sc.z + st_v[g], sc.dr_z + r, ct_v[g], st));
+      r += ct_v[g];
+    }
+    std::vector<PoseBlock> pb = pose_blocks(1, st_v, ct_v);
+    sc.n_deform_blocks = (uint32_t)pb.size();
+    HIPCHK(dmalloc(&sc.deform_blocks, std::max<size_t>(pb.size(), 1)));
+    if (!pb.empty())
+      HIPCHK(hipMemcpy(sc.deform_blocks, pb.data(), pb.size() * sizeof(PoseBlock), hipMemcpyHostToDevice));
+    std::vector<DeformParam> dp(num_groups);
+    for (uint32_t g = 0; g < num_groups; ++g) dp[g] = DeformParam{groups[g].amplitude, groups[g].omega};
+    HIPCHK(dmalloc(&sc.dparams, std::max<size_t>(dp.size(), 1)));
+    if (!dp.empty())
+      HIPCHK(hipMemcpy(sc.dparams, dp.data(), dp.size() * sizeof(DeformParam), hipMemcpyHostToDevice));
+    rc = ensure_pose_block(ctx, sc);
+    if (rc != GRCA_OK) return rc;
+    HIPCHK(hipStreamSynchronize(st));
+    return GRCA_OK;
+  })
+}
+
+namespace {
+grca_status enqueue_pose_kernels(grca_context* ctx, SceneData& sc, hipStream_t st) {
+  HIPCHK(launch_pose(sc.rigid_blocks, sc.n_rigid_blocks, sc.rr_x, sc.rr_y, sc.rr_z, nullptr,
+                     nullptr, nullptr, nullptr, nullptr, sc.pose_in, sc.x, sc.y, sc.z, st));
+  HIPCHK(launch_pose(sc.deform_blocks, sc.n_deform_blocks, sc.dr_x, sc.dr_y, sc.dr_z, sc.dn_x,
+                     sc.dn_y, sc.dn_z, sc.dphase, sc.dparams, sc.pose_in, sc.x, sc.y, sc.z, st));
+  return GRCA_OK;
+}
+
+grca_status stage_pose(grca_context* ctx, SceneData& sc, const float* mats, double time,
+                       bool dev_mats, hipStream_t st) {
+  if (!sc.pose_in) return GRCA_OK;
+  if (sc.n_inst && !mats) return fail(ctx, GRCA_ERR_INVALID_ARG, "instance matrices required");
+  HIPCHK(hipEventSynchronize(sc.pose_ev));
+  std::memcpy(sc.pose_stage, &time, 8);
+  if (sc.n_inst && !dev_mats) {
+    for (uint64_t i = 0; i < 12ull * sc.n_inst; ++i)
+      if (!std::isfinite(mats[i])) return fail(ctx, GRCA_ERR_INVALID_ARG, "non-finite matrix");
+    std::memcpy(sc.pose_stage + 8, mats, 48ull * sc.n_inst);
+    HIPCHK(hipMemcpyAsync(sc.pose_in, sc.pose_stage, sc.pose_bytes, hipMemcpyHostToDevice, st));
+  } else {
+    HIPCHK(hipMemcpyAsync(sc.pose_in, sc.pose_stage, 8, hipMemcpyHostToDevice, st));
+    if (sc.n_inst)
+      HIPCHK(hipMemcpyAsync(reinterpret_cast<unsigned char*>(sc.pose_in) + 8, mats,
+                            48ull * sc.n_inst, hipMemcpyDeviceToDevice, st));
+  }
+  HIPCHK(hipEventRecord(sc.pose_ev, st));
+  return GRCA_OK;
+}
+}  // namespace
+
+extern "C" grca_status grca_scene_pose(grca_context* ctx, uint32_t scene_id,
+                                       const float* instance_matrices, double time_s,
+                                       uint32_t flags, void* hip_stream) {
+  if (!ctx) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    auto it = ctx->scenes.find(scene_id);
+    if (it == ctx->scenes.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown scene");
+    if (!std::isfinite(time_s)) return fail(ctx, GRCA_ERR_INVALID_ARG, "time not finite");
+    SceneData& sc = it->second;
+    hipStream_t st = as_stream(hip_stream);
+    grca_status rc = stage_pose(ctx, sc, instance_matrices, time_s, flags & GRCA_MEM_DEVICE, st);
+    if (rc != GRCA_OK) return rc;
+    return enqueue_pose_kernels(ctx, sc, st);
+  })
+}
+
+// =============================================================== sensors
+extern "C" grca_status grca_sensor_config(grca_context* ctx, uint32_t sensor_id,
+                                          const grca_sensor_desc* s) {
+  if (!ctx) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    if (!s) return fail(ctx, GRCA_ERR_INVALID_ARG, "NULL descriptor");
+    grca_status rc;
+    if ((rc = check_vec(s->origin, "origin", ctx)) != GRCA_OK) return rc;
+    if ((rc = check_vec(s->forward, "forward", ctx)) != GRCA_OK) return rc;
+    if ((rc = check_vec(s->right, "right", ctx)) != GRCA_OK) return rc;
+    if ((rc = check_vec(s->up, "up", ctx)) != GRCA_OK) return rc;
+    const float* B[3] = {s->forward, s->right, s->up};
+    for (int a = 0; a < 3; ++a)
+      for (int b = a; b < 3; ++b) {
+        const double d = (double)B[a][0] * B[b][0] + (double)B[a][1] * B[b][1] +
+                         (double)B[a][2] * B[b][2];
+        if (std::fabs(d - (a == b ? 1.0 : 0.0)) > 1e-6)
+          return fail(ctx, GRCA_ERR_INVALID_ARG, "basis not orthonormal within 1e-6");
+      }
+    if (s->num_channels < 1 || s->num_channels > 65535)
+      return fail(ctx, GRCA_ERR_INVALID_ARG, "num_channels outside [1, 65535]");
+    if (s->rays_per_channel < 1 || s->rays_per_channel > 65535)
+      return fail(ctx, GRCA_ERR_INVALID_ARG, "rays_per_channel outside [1, 65535]");
+    if (!s->channel_elevation_rad) return fail(ctx, GRCA_ERR_INVALID_ARG, "NULL elevation table");
+    const double half_pi = 1.5707963267948966;
+    for (uint32_t j = 0; j < s->num_channels; ++j) {
+      const float e = s->channel_elevation_rad[j];
+      if (!std::isfinite(e) || std::fabs((double)e) > half_pi + 1e-6)
+        return fail(ctx, GRCA_ERR_INVALID_ARG, "elevation outside [-pi/2, pi/2]");
+      if (j && !(e > s->channel_elevation_rad[j - 1]))
+        return fail(ctx, GRCA_ERR_INVALID_ARG, "elevations not strictly ascending");
+    }
+    if (!(s->fov_rad > 0.0f) || (double)s->fov_rad > kTwoPi + 1e-6)
+      return fail(ctx, GRCA_ERR_INVALID_ARG, "fov outside (0, 2 pi]");
+    if (!(s->range_min > 0.0f) || !(s->range_max >= s->range_min) || !std::isfinite(s->range_max))
+      return fail(ctx, GRCA_ERR_INVALID_ARG, "need 0 < range_min <= range_max < inf");
+    HIPCHK(hipSetDevice(ctx->device));
+    SensorData sd;
+    sd.desc = *s;
+    sd.elev.assign(s->channel_elevation_rad, s->channel_elevation_rad + s->num_channels);
+    sd.desc.channel_elevation_rad = nullptr;
+    sd.dtheta = (double)s->fov_rad / (double)s->rays_per_channel;
+    sd.wrap = std::fabs((double)s->fov_rad - kTwoPi) <= 1e-6;
+    uint32_t lut = std::max<uint32_t>(512, 4 * s->num_channels);
+    sd.lut_size = std::min<uint32_t>(lut, 1u << 16);
+    const uint32_t g = s->num_channels, c = s->rays_per_channel;
+    auto cleanup = [&]() { free_sensor(sd); };
+    hipError_t e = hipSuccess;
+    float* elev_d = nullptr;
+    if ((e = dmalloc(&sd.chan, g)) != hipSuccess || (e = dmalloc(&sd.chan_d, g)) != hipSuccess ||
+        (e = dmalloc(&sd.sin_tab, g)) != hipSuccess || (e = dmalloc(&sd.az, c)) != hipSuccess ||
+        (e = dmalloc(&sd.lut, sd.lut_size)) != hipSuccess || (e = dmalloc(&elev_d, g)) != hipSuccess) {
+      cleanup();
+      dfree(elev_d);
+      return fail(ctx, GRCA_ERR_OUT_OF_MEMORY, std::string("sensor tables: ") + hipGetErrorString(e));
+    }
+    e = hipMemcpy(elev_d, sd.elev.data(), 4ull * g, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = launch_sensor_tables(elev_d, g, c, sd.dtheta, sd.chan, sd.chan_d, sd.sin_tab, sd.az,
+                               sd.lut_size, sd.lut, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    dfree(elev_d);
+    if (e != hipSuccess) {
+      cleanup();
+      return fail(ctx, GRCA_ERR_DEVICE, std::string("sensor tables: ") + hipGetErrorString(e));
+    }
+    auto it = ctx->sensors.find(sensor_id);
+    if (it != ctx->sensors.end()) {
+      HIPCHK(hipDeviceSynchronize());
+      free_sensor(it->second);
+      it->second = sd;
+    } else {
+      ctx->sensors.emplace(sensor_id, sd);
+    }
+    return GRCA_OK;
+  })
+}
+
+extern "C" grca_status grca_sensor_release(grca_context* ctx, uint32_t sensor_id) {
+  if (!ctx) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    auto it = ctx->sensors.find(sensor_id);
+    if (it == ctx->sensors.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown sensor");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    free_sensor(it->second);
+    ctx->sensors.erase(it);
+    return GRCA_OK;
+  })
+}
+
+// =============================================================== casting
+namespace {
+grca_status cast_on(grca_context* ctx, grca_workspace* ws, const uint32_t* ids, uint32_t n,
+                    float* out_dist, uint32_t* out_tri, uint32_t flags, hipStream_t st) {
+  if (n && !ids) return fail(ctx, GRCA_ERR_INVALID_ARG, "NULL sensor id list");
+  Plan P;
+  grca_status rc = make_plan(ctx, ids, n, ctx->opt.bounds_block, P);
+  if (rc != GRCA_OK) return rc;
+  if (ws->fixed && P.rays > ws->key_cap)
+    return fail(ctx, GRCA_ERR_CAPACITY, "cast has more rays than the workspace holds");
+  const bool dev = flags & GRCA_MEM_DEVICE;
+  uint64_t scratch = 0;
+  if (flags & GRCA_CAST_ALL_PAIRS)
+    for (const DevScene& s : P.scenes) scratch = std::max<uint64_t>(scratch, s.ntri);
+  const uint64_t want_items = ws->item_cap ? ws->item_cap : ctx->opt.item_capacity;
+  const uint64_t want_large = ws->large_cap ? ws->large_cap : ctx->opt.large_capacity;
+  const bool grow = P.rays > ws->key_cap || want_items > ws->item_cap ||
+                    want_large > ws->large_cap || P.sens.size() > ws->sens_cap ||
+                    P.scenes.size() > ws->scene_cap || scratch > ws->scratch_cap ||
+                    (!dev && P.rays > ws->out_cap);
+  const uint32_t slot = ws->next_slot;
+  if (grow || ws->rec[slot].live) {
+    // buffers are about to change, or the ring wrapped: finish everything in flight
+    rc = ws_drain(ctx, ws);
+    if (rc != GRCA_OK) return rc;
+    rc = ws_reserve(ctx, ws, std::max<uint64_t>(P.rays, 1), want_items, want_large,
+                    (uint32_t)P.sens.size(), (uint32_t)P.scenes.size(), scratch,
+                    dev ? 0 : P.rays);
+    if (rc != GRCA_OK) return rc;
+  } else if (ws->last_slot >= 0 && ws->rec[ws->last_slot].live && ws->last_stream != st) {
+    // another stream used these buffers last: order after it on the device
+    HIPCHK(hipStreamWaitEvent(st, ws->ev[ws->last_slot], 0));
+  }
+  float* dist = dev ? out_dist : (out_dist ? ws->out_dist : nullptr);
+  uint32_t* tri = dev ? out_tri : (out_tri ? ws->out_tri : nullptr);
+  CastRecord& R = ws->rec[slot];
+  R.ids.assign(ids, ids + n);
+  R.dist = dist;
+  R.tri = tri;
+  R.flags = flags;
+  R.st = st;
+  R.rays = P.rays;
+  R.pairs = P.pairs;
+  R.recasts = 0;
+  rc = enqueue_kernels(ctx, ws, slot, P, dist, tri, flags, st);
+  if (rc != GRCA_OK) return rc;
+  R.live = true;
+  ws->last_slot = (int)slot;
+  ws->last_stream = st;
+  ws->next_slot = (slot + 1) % RING;
+  ctx->last_ws = ws;
+  if (!dev) {
+    rc = ws_drain(ctx, ws);
+    if (rc != GRCA_OK) return rc;
+    if (out_dist) HIPCHK(hipMemcpyAsync(out_dist, ws->out_dist, 4 * P.rays, hipMemcpyDeviceToHost, st));
+    if (out_tri) HIPCHK(hipMemcpyAsync(out_tri, ws->out_tri, 4 * P.rays, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return GRCA_OK;
+}
+}  // namespace
+
+extern "C" grca_status grca_cast(grca_context* ctx, const uint32_t* sensor_ids,
+                                 uint32_t num_sensors, float* out_distance, uint32_t* out_tri,
+                                 uint32_t flags, void* hip_stream) {
+  if (!ctx) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    return cast_on(ctx, ctx->def_ws, sensor_ids, num_sensors, out_distance, out_tri, flags,
+                   as_stream(hip_stream));
+  })
+}
+
+extern "C" grca_status grca_synchronize(grca_context* ctx, void* hip_stream) {
+  if (!ctx) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    grca_status rc = ws_drain(ctx, ctx->def_ws);
+    if (rc != GRCA_OK) return rc;
+    HIPCHK(hipStreamSynchronize(as_stream(hip_stream)));
+    return GRCA_OK;
+  })
+}
+
+extern "C" grca_status grca_last_stats(grca_context* ctx, grca_stats* out) {
+  if (!ctx || !out) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    std::memset(out, 0, sizeof(*out));
+    grca_workspace* ws = ctx->last_ws;
+    if (!ws || ws->last_slot < 0) return GRCA_OK;
+    HIPCHK(hipSetDevice(ctx->device));
+    const int slot = ws->last_slot;
+    const bool was_live = ws->rec[slot].live;
+    grca_status rc = ws_drain(ctx, ws);
+    if (rc != GRCA_OK) return rc;
+    if (!was_live) HIPCHK(hipEventSynchronize(ws->ev[slot]));
+    const Counters& c = ws->cnt_host[slot];
+    const CastRecord& R = ws->rec[slot];
+    out->rays = R.rays;
+    out->pairs_tested = R.pairs;
+    out->rect_items = c.n_rect;
+    out->large_records = c.n_large;
+    out->row_items = c.n_rows;
+    out->rtic = c.rtic;
+    out->recasts = R.recasts;
+    return GRCA_OK;
+  })
+}
+
+// =============================================================== options
+extern "C" grca_status grca_get_options(const grca_context* ctx, grca_options* out) {
+  if (!ctx || !out) return GRCA_ERR_INVALID_ARG;
+  *out = ctx->opt;
+  return GRCA_OK;
+}
+
+extern "C" grca_status grca_set_options(grca_context* ctx, const grca_options* o) {
+  if (!ctx || !o) return GRCA_ERR_INVALID_ARG;
+  if (o->small_channels < 1 || o->small_channels > 255)
+    return fail(ctx, GRCA_ERR_INVALID_ARG, "small_channels outside [1, 255]");
+  if (o->small_rays < 1 || o->small_rays > 65535)
+    return fail(ctx, GRCA_ERR_INVALID_ARG, "small_rays outside [1, 65535]");
+  if (o->row_chunk < 1 || o->row_chunk > 65535)
+    return fail(ctx, GRCA_ERR_INVALID_ARG, "row_chunk outside [1, 65535]");
+  const uint32_t b = o->bounds_block;
+  if (b != 64 && b != 128 && b != 256 && b != 512 && b != 1024)
+    return fail(ctx, GRCA_ERR_INVALID_ARG, "bounds_block must be 64, 128, 256, 512 or 1024");
+  if (o->persist_waves_cu < 1 || o->persist_waves_cu > 32)
+    return fail(ctx, GRCA_ERR_INVALID_ARG, "persist_waves_cu outside [1, 32]");
+  if (o->item_capacity < 64 || o->item_capacity > 0xFFFFFFF0ull ||
+      o->large_capacity < 64 || o->large_capacity > 0xFFFFFFF0ull)
+    return fail(ctx, GRCA_ERR_INVALID_ARG, "queue capacities outside [64, 2^32)");
+  ctx->opt = *o;
+  return GRCA_OK;
+}
+
+// =============================================================== workspaces
+extern "C" grca_status grca_workspace_create(grca_context* ctx, uint64_t max_rays,
+                                             uint64_t item_capacity, grca_workspace** out,
+                                             uint64_t* bytes_out) {
+  if (!ctx || !out) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    *out = nullptr;
+    if (max_rays == 0 || max_rays >= (1ull << 32))
+      return fail(ctx, GRCA_ERR_INVALID_ARG, "max_rays outside [1, 2^32)");
+    if (item_capacity < 64 || item_capacity > 0xFFFFFFF0ull)
+      return fail(ctx, GRCA_ERR_INVALID_ARG, "item_capacity outside [64, 2^32)");
+    HIPCHK(hipSetDevice(ctx->device));
+    grca_workspace* ws = new grca_workspace();
+    grca_status rc = ws_init(ctx, ws);
+    if (rc == GRCA_OK)
+      rc = ws_reserve(ctx, ws, max_rays, item_capacity,
+                      std::max<uint64_t>(item_capacity / 16, 4096), 64, 16, 0, 0);
+    if (rc != GRCA_OK) {
+      ws_free(ws);
+      return rc;
+    }
+    ws->fixed = true;
+    *out = ws;
+    if (bytes_out) *bytes_out = ws->bytes;
+    return GRCA_OK;
+  })
+}
+
+extern "C" void grca_workspace_destroy(grca_workspace* ws) {
+  if (!ws) return;
+  if (ws->ctx) {
+    if (ws->ctx->last_ws == ws) ws->ctx->last_ws = nullptr;
+    (void)hipSetDevice(ws->ctx->device);
+  }
+  ws_free(ws);
+}
+
+extern "C" grca_status grca_cast_ws(grca_context* ctx, grca_workspace* ws,
+                                    const uint32_t* sensor_ids, uint32_t num_sensors,
+                                    float* out_distance_dev, uint32_t* out_tri_dev,
+                                    void* hip_stream) {
+  if (!ctx || !ws || ws->ctx != ctx) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    return cast_on(ctx, ws, sensor_ids, num_sensors, out_distance_dev, out_tri_dev,
+                   GRCA_MEM_DEVICE, as_stream(hip_stream));
+  })
+}
+
+extern "C" grca_status grca_workspace_synchronize(grca_context* ctx, grca_workspace* ws,
+                                                  void* hip_stream) {
+  if (!ctx || !ws || ws->ctx != ctx) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    (void)hip_stream;
+    return ws_drain(ctx, ws);
+  })
+}
+
+// =============================================================== frames
+namespace {
+grca_status capture_frame(grca_context* ctx, grca_frame* fr) {
+  if (fr->exec) { (void)hipGraphExecDestroy(fr->exec); fr->exec = nullptr; }
+  if (fr->graph) { (void)hipGraphDestroy(fr->graph); fr->graph = nullptr; }
+  Plan P;
+  grca_status rc = make_plan(ctx, fr->ids.data(), (uint32_t)fr->ids.size(), ctx->opt.bounds_block, P);
+  if (rc != GRCA_OK) return rc;
+  SceneData& sc = ctx->scenes.at(fr->scene_id);
+  grca_workspace* ws = fr->ws;
+  rc = ws_quiesce(ctx, ws);
+  if (rc != GRCA_OK) return rc;
+  // size every buffer before capture (no allocation inside the graph)
+  rc = ws_reserve(ctx, ws, P.rays, ws->item_cap ? ws->item_cap : ctx->opt.item_capacity,
+                  ws->large_cap ? ws->large_cap : ctx->opt.large_capacity,
+                  (uint32_t)P.sens.size(), (uint32_t)P.scenes.size(), 0, 0);
+  if (rc != GRCA_OK) return rc;
+  // the frame's tables live in ring slot 0 and never change
+  std::memcpy(ws->dsens_host, P.sens.data(), P.sens.size() * sizeof(DevSensor));
+  std::memcpy(ws->dscenes_host, P.scenes.data(), P.scenes.size() * sizeof(DevScene));
+  HIPCHK(hipMemcpy(ws->dsens, ws->dsens_host, P.sens.size() * sizeof(DevSensor), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(ws->dscenes, ws->dscenes_host, P.scenes.size() * sizeof(DevScene), hipMemcpyHostToDevice));
+  hipStream_t st = fr->cap_stream;
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  grca_status erc = GRCA_OK;
+  if (sc.pose_in) erc = enqueue_pose_kernels(ctx, sc, st);
+  const grca_options& o = ctx->opt;
+  const uint32_t n = (uint32_t)P.rays;
+  const uint32_t icap = (uint32_t)std::min<uint64_t>(ws->item_cap, 0xFFFFFFFFull);
+  const uint32_t lcap = (uint32_t)std::min<uint64_t>(ws->large_cap, 0xFFFFFFFFull);
+  const uint32_t pb = persist_blocks(ctx);
+  hipError_t e = hipSuccess;
+  if (erc == GRCA_OK) e = launch_init(ws->keys, n, ws->cnt, st);
+  if (e == hipSuccess && erc == GRCA_OK)
+    e = launch_bounds(ws->dscenes, (uint32_t)P.scenes.size(), P.total_blocks, o.bounds_block,
+                      ws->dsens, o.small_channels, o.small_rays, ws->items, icap, ws->large,
+                      lcap, ws->cnt, st);
+  if (e == hipSuccess && erc == GRCA_OK)
+    e = launch_expand(ws->dscenes, ws->dsens, ws->large, ws->items, icap, lcap, o.row_chunk,
+                      ws->cnt, pb, st);
+  if (e == hipSuccess && erc == GRCA_OK)
+    e = launch_isect(ws->dscenes, ws->dsens, ws->items, icap, ws->cnt, ws->keys, pb, st);
+  if (e == hipSuccess && erc == GRCA_OK) e = launch_resolve(ws->keys, n, fr->out_dist, fr->out_tri, st);
+  if (e == hipSuccess && erc == GRCA_OK)
+    e = hipMemcpyAsync(ws->cnt_host, ws->cnt, sizeof(Counters), hipMemcpyDeviceToHost, st);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(st, &g);
+  if (erc != GRCA_OK) { if (g) (void)hipGraphDestroy(g); return erc; }
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(ctx, GRCA_ERR_DEVICE, std::string("frame capture: ") +
+                                          hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  fr->graph = g;
+  HIPCHK(hipGraphInstantiate(&fr->exec, g, nullptr, nullptr, 0));
+  CastRecord& R = ws->rec[0];
+  R.ids = fr->ids;
+  R.rays = P.rays;
+  R.pairs = P.pairs;
+  R.dist = fr->out_dist;
+  R.tri = fr->out_tri;
+  R.flags = GRCA_MEM_DEVICE;
+  return GRCA_OK;
+}
+}  // namespace
+
+extern "C" grca_status grca_frame_create(grca_context* ctx, uint32_t scene_id,
+                                         const uint32_t* sensor_ids, uint32_t num_sensors,
+                                         float* out_distance_dev, uint32_t* out_tri_dev,
+                                         grca_frame** out) {
+  if (!ctx || !out) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    *out = nullptr;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!ctx->scenes.count(scene_id)) return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown scene");
+    if (num_sensors == 0 || !sensor_ids) return fail(ctx, GRCA_ERR_INVALID_ARG, "no sensors");
+    for (uint32_t i = 0; i < num_sensors; ++i) {
+      auto it = ctx->sensors.find(sensor_ids[i]);
+      if (it == ctx->sensors.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown sensor");
+      if (it->second.desc.scene_id != scene_id)
+        return fail(ctx, GRCA_ERR_INVALID_ARG, "frame sensors must observe the frame's scene");
+    }
+    grca_frame* fr = new grca_frame();
+    fr->ctx = ctx;
+    fr->scene_id = scene_id;
+    fr->ids.assign(sensor_ids, sensor_ids + num_sensors);
+    fr->out_dist = out_distance_dev;
+    fr->out_tri = out_tri_dev;
+    fr->ws = new grca_workspace();
+    grca_status rc = ws_init(ctx, fr->ws);
+    if (rc == GRCA_OK && hipStreamCreateWithFlags(&fr->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      rc = fail(ctx, GRCA_ERR_DEVICE, "stream creation failed");
+    if (rc == GRCA_OK) rc = capture_frame(ctx, fr);
+    if (rc != GRCA_OK) {
+      grca_frame_destroy(fr);
+      return rc;
+    }
+    *out = fr;
+    return GRCA_OK;
+  })
+}
+
+extern "C" grca_status grca_frame_launch(grca_frame* fr, const float* instance_matrices,
+                                         double time_s, void* hip_stream) {
+  if (!fr || !fr->ctx) return GRCA_ERR_INVALID_ARG;
+  grca_context* ctx = fr->ctx;
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    auto it = ctx->scenes.find(fr->scene_id);
+    if (it == ctx->scenes.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "frame scene was released");
+    if (!std::isfinite(time_s)) return fail(ctx, GRCA_ERR_INVALID_ARG, "time not finite");
+    hipStream_t st = as_stream(hip_stream);
+    grca_workspace* ws = fr->ws;
+    if (ws->rec[0].live && ws->rec[0].st != st) HIPCHK(hipStreamWaitEvent(st, ws->ev[0], 0));
+    grca_status rc = stage_pose(ctx, it->second, instance_matrices, time_s, false, st);
+    if (rc != GRCA_OK) return rc;
+    HIPCHK(hipGraphLaunch(fr->exec, st));
+    HIPCHK(hipEventRecord(ws->ev[0], st));
+    ws->rec[0].live = true;
+    ws->rec[0].st = st;
+    ws->last_slot = 0;
+    ctx->last_ws = ws;
+    return GRCA_OK;
+  })
+}
+
+extern "C" grca_status grca_frame_synchronize(grca_frame* fr, void* hip_stream) {
+  if (!fr || !fr->ctx) return GRCA_ERR_INVALID_ARG;
+  grca_context* ctx = fr->ctx;
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(hip_stream);
+    grca_workspace* ws = fr->ws;
+    for (int attempt = 0; attempt < 7; ++attempt) {
+      HIPCHK(hipEventSynchronize(ws->ev[0]));
+      const Counters c = ws->cnt_host[0];
+      if (!c.overflow) {
+        ws->rec[0].live = false;
+        return GRCA_OK;
+      }
+      uint64_t items = ws->item_cap, large = ws->large_cap;
+      grca_status rc = grown_caps(ctx, c, items, large);
+      if (rc != GRCA_OK) return rc;
+      dfree(ws->items); ws->item_cap = 0;
+      dfree(ws->large); ws->large_cap = 0;
+      rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
+      if (rc != GRCA_OK) return rc;
+      rc = capture_frame(ctx, fr);
+      if (rc != GRCA_OK) return rc;
+      ws->rec[0].recasts++;
+      HIPCHK(hipGraphLaunch(fr->exec, st));
+      HIPCHK(hipEventRecord(ws->ev[0], st));
+    }
+    return fail(ctx, GRCA_ERR_CAPACITY, "frame queue kept overflowing after regrowth");
+  })
+}
+
+extern "C" void grca_frame_destroy(grca_frame* fr) {
+  if (!fr) return;
+  if (fr->ctx) (void)hipSetDevice(fr->ctx->device);
+  if (fr->exec) (void)hipGraphExecDestroy(fr->exec);
+  if (fr->graph) (void)hipGraphDestroy(fr->graph);
+  if (fr->cap_stream) (void)hipStreamDestroy(fr->cap_stream);
+  if (fr->ctx && fr->ctx->last_ws == fr->ws) fr->ctx->last_ws = nullptr;
+  ws_free(fr->ws);
+  delete fr;
+}

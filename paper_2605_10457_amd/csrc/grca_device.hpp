@@ -1,0 +1,183 @@
+// grca_device.hpp -- device-side data layout and per-pair arithmetic shared by
+// every kernel of the caster (bounds/binning, large-class expansion,
+// cooperative intersection, all-pairs reference).
+//
+// All paths evaluate a (ray, triangle) pair with the same two functions
+// (make_statics + ray_test), so the culled cast and the all-pairs reference
+// are bitwise comparable.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace grca {
+
+// (f_sort(+inf) << 32) | miss id: the initial key of every ray.  f_sort is the
+// order-preserving float -> uint32 map of appendix "Per-Ray Distance
+// Encoding"; the low word carries the triangle id so that a 64-bit minimum
+// selects the closest hit and, at equal FP32 distance, the smaller id.
+constexpr unsigned long long KEY_INIT = 0xFF800000FFFFFFFFull;
+constexpr uint32_t MISS = 0xFFFFFFFFu;
+
+// Work-item record (16 B).  A rectangle of candidate rays of one
+// (triangle, sensor) pair: channels [c_from, c_from + c_count) x rays
+// [r_start, r_start + r_count) (ray index mod chi on full-spin sensors).
+// Large-class records use the same layout with r_count = 0 (rays are
+// computed per channel by the expansion kernel).
+struct Item {
+  uint32_t tri;
+  uint32_t chan;   // c_from | c_count << 16
+  uint32_t rays;   // r_start | r_count << 16
+  uint32_t sensor; // sensor slot of the cast
+};
+
+// Per-cast sensor descriptor (device memory, read with wave-uniform indices).
+struct DevSensor {
+  float o[3], f[3], r[3], u[3];
+  float dmin, dmax;
+  uint32_t gamma, chi;
+  uint32_t key_offset; // O_n: first output slot of this sensor
+  uint32_t wrap;       // 1: full spin, azimuth index wraps mod chi
+  uint32_t scene;      // scene slot of the cast
+  uint32_t lut_size;   // bins of the sine -> channel lookup
+  float theta_start;   // theta_0 = -floor(chi/2) * dtheta (FP32 copy for the bounds pass)
+  float inv_dtheta;    // chi / fov
+  float period_idx;    // 2 pi / dtheta: one full turn in ray-index units
+  float pad0;
+  double theta_start_d, inv_dtheta_d, period_idx_d;
+  const float2* chan;   // (cos phi_j, sin phi_j), FP32
+  const double2* chan_d; // (cos phi_j, sin phi_j), FP64
+  const float* sin_tab; // sin phi_j (FP32, equal to chan[j].y), ascending
+  const uint16_t* lut;  // lut[b] = first j with sin_tab[j] >= -1 + 2b/lut_size
+  const float2* az;     // (cos theta_R, sin theta_R), FP32
+};
+
+struct DevScene {
+  const float* x;
+  const float* y;
+  const float* z;
+  const uint32_t* idx;
+  uint32_t ntri;
+  uint32_t block_start;  // first bounds-pass block of this scene
+  uint32_t sensor_begin; // sensor slots [sensor_begin, sensor_end) observe it
+  uint32_t sensor_end;
+};
+
+// Device counters of one cast, cleared by the init kernel.
+struct Counters {
+  uint32_t n_items;   // reserved item slots (may exceed capacity: overflow)
+  uint32_t n_large;   // reserved large-record slots
+  uint32_t tk_large;  // ticket of the persistent expansion kernel
+  uint32_t tk_items;  // ticket of the persistent intersection kernel
+  uint32_t n_rect;    // rectangle items written by the bounds pass
+  uint32_t n_rows;    // row items written by the expansion
+  uint32_t overflow;  // bit 0: item queue, bit 1: large queue
+  uint32_t pad;
+  unsigned long long rtic;  // candidate pairs executed
+};
+
+// Per-(triangle, origin) statics of the ray test, all in the sensor's local
+// frame (x = forward, y = right, z = up): unit normals of the three planes
+// through the origin and each edge, oriented so the triangle's forward cone
+// is their positive side; the unit face normal oriented away from the
+// origin; and the origin-to-plane distance h.  With d the unit ray and
+// w_k = d . n_k, Moller-Trumbore's barycentrics are (w_2, w_0, w_1) / (d . N)
+// and its distance is h / (d . N_hat): the test below is the MT test with
+// every ray-independent product precomputed once per pair.
+struct Statics {
+  float n0x, n0y, n0z, n1x;
+  float n1y, n1z, n2x, n2y;
+  float n2z, Nx, Ny, Nz;
+  float h, pad0, pad1, pad2;
+};
+
+__device__ inline bool make_statics(float ax, float ay, float az_, float bx, float by, float bz,
+                                    float cx, float cy, float cz, const DevSensor& s,
+                                    Statics& st, double (*nrm_out)[3] = nullptr) {
+  // FP64 throughout, rounded once to FP32 at the end.
+  const double ox = s.o[0], oy = s.o[1], oz = s.o[2];
+  const double fx = s.f[0], fy = s.f[1], fz = s.f[2];
+  const double rx = s.r[0], ry = s.r[1], rz = s.r[2];
+  const double ux = s.u[0], uy = s.u[1], uz = s.u[2];
+  double P[3][3];
+  const double wx[3] = {(double)ax - ox, (double)bx - ox, (double)cx - ox};
+  const double wy[3] = {(double)ay - oy, (double)by - oy, (double)cy - oy};
+  const double wz[3] = {(double)az_ - oz, (double)bz - oz, (double)cz - oz};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    P[k][0] = wx[k] * fx + wy[k] * fy + wz[k] * fz;
+    P[k][1] = wx[k] * rx + wy[k] * ry + wz[k] * rz;
+    P[k][2] = wx[k] * ux + wy[k] * uy + wz[k] * uz;
+  }
+  const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+  const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+  const double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                       e1[0] * e2[1] - e1[1] * e2[0]};
+  const double g = P[0][0] * N[0] + P[0][1] * N[1] + P[0][2] * N[2];
+  const double nN2 = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
+  if (!(nN2 > 0.0) || g == 0.0 || !(g == g)) return false;
+  const double sg = g > 0.0 ? 1.0 : -1.0;
+  double n[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int k1 = (k + 1) % 3;
+    const double E[3] = {P[k1][0] - P[k][0], P[k1][1] - P[k][1], P[k1][2] - P[k][2]};
+    const double c0 = P[k][1] * E[2] - P[k][2] * E[1];
+    const double c1 = P[k][2] * E[0] - P[k][0] * E[2];
+    const double c2 = P[k][0] * E[1] - P[k][1] * E[0];
+    const double l2 = c0 * c0 + c1 * c1 + c2 * c2;
+    if (!(l2 > 0.0)) return false;
+    const double il = sg / sqrt(l2);
+    n[k][0] = c0 * il;
+    n[k][1] = c1 * il;
+    n[k][2] = c2 * il;
+  }
+  const double iN = sg / sqrt(nN2);
+  st.n0x = (float)n[0][0]; st.n0y = (float)n[0][1]; st.n0z = (float)n[0][2];
+  st.n1x = (float)n[1][0]; st.n1y = (float)n[1][1]; st.n1z = (float)n[1][2];
+  st.n2x = (float)n[2][0]; st.n2y = (float)n[2][1]; st.n2z = (float)n[2][2];
+  st.Nx = (float)(N[0] * iN); st.Ny = (float)(N[1] * iN); st.Nz = (float)(N[2] * iN);
+  st.h = (float)(g * sg / sqrt(nN2));
+  st.pad0 = st.pad1 = st.pad2 = 0.0f;
+  if (nrm_out) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      nrm_out[k][0] = n[k][0];
+      nrm_out[k][1] = n[k][1];
+      nrm_out[k][2] = n[k][2];
+    }
+  }
+  return true;
+}
+
+// FP32 ray test with fixed evaluation order (no contraction beyond the
+// explicit fmaf calls), so every call site rounds identically.
+// Returns the packed key of a hit, or KEY_INIT.
+__device__ inline unsigned long long ray_test(const Statics& st, float cphi, float sphi,
+                                              float cth, float sth, float dmin, float dmax,
+                                              uint32_t tri) {
+#pragma clang fp contract(off)
+  const float dx = cphi * cth;
+  const float dy = cphi * sth;
+  const float dz = sphi;
+  const float w0 = fmaf(st.n0x, dx, fmaf(st.n0y, dy, st.n0z * dz));
+  const float w1 = fmaf(st.n1x, dx, fmaf(st.n1y, dy, st.n1z * dz));
+  const float w2 = fmaf(st.n2x, dx, fmaf(st.n2y, dy, st.n2z * dz));
+  const float c = fmaf(st.Nx, dx, fmaf(st.Ny, dy, st.Nz * dz));
+  if (w0 >= 0.0f && w1 >= 0.0f && w2 >= 0.0f && c > 0.0f) {
+    const float t = st.h / c;
+    if (t >= dmin && t <= dmax) {
+      // f_sort(t) for t > 0 sets the sign bit; the miss key stays larger.
+      const uint32_t u = __float_as_uint(t);
+      const uint32_t m = (uint32_t)(-(int32_t)(u >> 31)) | 0x80000000u;
+      return ((unsigned long long)(u ^ m) << 32) | (unsigned long long)tri;
+    }
+  }
+  return KEY_INIT;
+}
+
+__device__ inline void key_min(unsigned long long* keys, uint32_t g, unsigned long long key) {
+  atomicMin(keys + g, key);
+}
+
+}  // namespace grca

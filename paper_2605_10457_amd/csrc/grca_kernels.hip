@@ -1,0 +1,835 @@
+// grca_kernels.hip -- HIP kernels of the emitter-centric caster for gfx950
+// (wave64, CDNA4).  No MFMA: nothing on this path is a dense contraction.
+//
+// Per cast:
+//   init_kernel      keys = KEY_INIT, counters cleared            (bookend pass)
+//   bounds_kernel    per triangle, per observing sensor: range prefilter,
+//                    elevation extent -> channel span, azimuth arc -> ray span,
+//                    small/large classification, wave-aggregated queue append
+//   expand_kernel    persistent: per large record, per channel, the exact
+//                    azimuth arc(s) of the channel cone inside the triangle
+//                    -> per-channel row items
+//   isect_kernel     persistent: 64 items per wave, flattened candidates,
+//                    FP32 ray test, 64-bit atomic minimum on packed keys
+//   resolve_kernel   keys -> (distance, triangle id)                (bookend)
+// plus the all-pairs reference, the pose (dynamic geometry) kernel and the
+// sensor-table builder.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "grca_device.hpp"
+#include "grca_launch.hpp"
+
+namespace grca {
+
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+constexpr float TWO_PI_F = 6.28318530717958647692f;
+constexpr float PI_F = 3.14159265358979323846f;
+
+// Conservative margins of the FP32 bounds pass (see the design doc for the error
+// budget): elevation margin in sine units, azimuth margin in radians, and
+// the |sin(elevation)| beyond which the azimuth arc is taken as the full turn.
+constexpr float ETA_SIN = 4e-6f;
+constexpr float MARGIN_AZ = 1e-5f;
+constexpr float MARGIN_AZ_POLE = 1e-6f;
+constexpr float S_POLE = 0.9999f;
+// Angular margin (sine) of the per-channel arcs of the large class.
+constexpr double SIN_M = 4e-6;
+
+__device__ inline uint32_t lane_id() { return __lane_id(); }
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= (uint32_t)o) v += t;
+  }
+  return v;
+}
+
+// Append one record per lane with `want` set, one atomic per wave.
+__device__ inline void wave_push(bool want, const Item& rec, Item* q, uint32_t cap,
+                                 uint32_t* counter, uint32_t* overflow, uint32_t ovf_bit,
+                                 uint32_t* stat) {
+  const unsigned long long mask = __ballot(want);
+  if (mask == 0ull) return;
+  const uint32_t n = (uint32_t)__popcll(mask);
+  const int leader = __ffsll((long long)mask) - 1;
+  uint32_t base = 0;
+  if ((int)lane_id() == leader) {
+    base = atomicAdd(counter, n);
+    if (stat) atomicAdd(stat, n);
+  }
+  base = __shfl(base, leader, 64);
+  if (want) {
+    const uint32_t rank = (uint32_t)__popcll(mask & __lanemask_lt());
+    const uint32_t slot = base + rank;
+    if (slot < cap) {
+      q[slot] = rec;
+    } else {
+      atomicOr(overflow, ovf_bit);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ init
+__global__ void init_kernel(unsigned long long* __restrict__ keys, uint32_t n,
+                            Counters* __restrict__ cnt) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) keys[g] = KEY_INIT;
+  if (g == 0) {
+    cnt->n_items = 0; cnt->n_large = 0; cnt->tk_large = 0; cnt->tk_items = 0;
+    cnt->n_rect = 0; cnt->n_rows = 0; cnt->overflow = 0; cnt->pad = 0; cnt->rtic = 0ull;
+  }
+}
+
+// ------------------------------------------------------------------ bounds
+struct Span {
+  uint32_t c_from, c_count;
+  uint32_t r0_start, r0_count, r1_start, r1_count;
+  bool large;
+};
+
+// first j with sin_tab[j] >= x (strict = false) or > x (strict = true)
+__device__ inline uint32_t chan_search(const DevSensor& s, float x, bool strict) {
+  const float fb = (x + 1.0f) * (0.5f * (float)s.lut_size);
+  int b = (fb > 0.0f) ? (int)fminf(fb, (float)(s.lut_size - 1)) : 0;
+  b = b > 0 ? b - 1 : 0;  // one bin early: the FP32 bin index may round up
+  uint32_t j = s.lut[b];
+  if (strict) {
+    while (j < s.gamma && s.sin_tab[j] <= x) ++j;
+  } else {
+    while (j < s.gamma && s.sin_tab[j] < x) ++j;
+  }
+  return j;
+}
+
+// Conservative candidate span of one (triangle, sensor) pair, FP32.
+// Returns false when no ray of the sensor can reach the triangle.
+__device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const float (&vz)[3],
+                               const DevSensor& s, uint32_t small_c, uint32_t small_r,
+                               Span& sp) {
+  float x[3], y[3], z[3], r2[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float dx = vx[k] - s.o[0], dy = vy[k] - s.o[1], dz = vz[k] - s.o[2];
+    x[k] = fmaf(dx, s.f[0], fmaf(dy, s.f[1], dz * s.f[2]));
+    y[k] = fmaf(dx, s.r[0], fmaf(dy, s.r[1], dz * s.r[2]));
+    z[k] = fmaf(dx, s.u[0], fmaf(dy, s.u[1], dz * s.u[2]));
+    r2[k] = fmaf(x[k], x[k], fmaf(y[k], y[k], z[k] * z[k]));
+  }
+  // range prefilter: the triangle lies inside the blind ball (convex), or its
+  // bounding sphere lies beyond range_max.
+  const float r2max = fmaxf(r2[0], fmaxf(r2[1], r2[2]));
+  const float dmin = s.dmin, dmax = s.dmax;
+  if (r2max < dmin * dmin * (1.0f - 1e-5f)) return false;
+  {
+    const float cx = (x[0] + x[1] + x[2]) * (1.0f / 3.0f);
+    const float cy = (y[0] + y[1] + y[2]) * (1.0f / 3.0f);
+    const float cz = (z[0] + z[1] + z[2]) * (1.0f / 3.0f);
+    float rc2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float ex = x[k] - cx, ey = y[k] - cy, ez = z[k] - cz;
+      rc2 = fmaxf(rc2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+    }
+    const float dc = sqrtf(fmaf(cx, cx, fmaf(cy, cy, cz * cz)));
+    if (dc - sqrtf(rc2) * 1.0001f > dmax * (1.0f + 1e-5f) + 1e-6f) return false;
+  }
+  const float r2min = fminf(r2[0], fminf(r2[1], r2[2]));
+  float s_lo, s_hi;
+  bool full = false;
+  if (!(r2min > 1e-24f)) {
+    // a vertex (numerically) at the origin: no usable extent, take everything
+    s_lo = -1.0f; s_hi = 1.0f; full = true;
+  } else {
+    float inv[3], sn[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      inv[k] = rsqrtf(r2[k]);
+      sn[k] = z[k] * inv[k];
+    }
+    s_lo = fminf(sn[0], fminf(sn[1], sn[2]));
+    s_hi = fmaxf(sn[0], fmaxf(sn[1], sn[2]));
+    // Edge bulge: along a great-circle arc of angle L between unit endpoints
+    // a, b every point is c/|c| with c on the chord and |c| >= cos(L/2), so
+    // the arc's sine-elevation stays within [min(m, m/cos), max(M, M/cos)].
+    float cmin = 1.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int k1 = (k + 1) % 3;
+      const float c = fmaf(x[k], x[k1], fmaf(y[k], y[k1], z[k] * z[k1])) * inv[k] * inv[k1];
+      cmin = fminf(cmin, c);
+    }
+    const float kb = rsqrtf(fmaxf(0.5f * (1.0f + cmin), 1e-12f)) * (1.0f + 1e-6f);
+    if (s_hi > 0.0f) s_hi = fminf(s_hi * kb, 1.0f);
+    if (s_lo < 0.0f) s_lo = fmaxf(s_lo * kb, -1.0f);
+    // Vertical axis through the origin vs the triangle's horizontal projection.
+    float e[3], tol[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int k1 = (k + 1) % 3;
+      e[k] = x[k] * y[k1] - x[k1] * y[k];
+      tol[k] = 1e-5f * (fabsf(x[k]) + fabsf(y[k])) * (fabsf(x[k1]) + fabsf(y[k1]));
+    }
+    const bool in_pos = e[0] >= -tol[0] && e[1] >= -tol[1] && e[2] >= -tol[2];
+    const bool in_neg = e[0] <= tol[0] && e[1] <= tol[1] && e[2] <= tol[2];
+    if (in_pos || in_neg) {
+      full = true;
+      const bool up = z[0] > 0.0f && z[1] > 0.0f && z[2] > 0.0f;
+      const bool dn = z[0] < 0.0f && z[1] < 0.0f && z[2] < 0.0f;
+      if (!dn) s_hi = 1.0f;
+      if (!up) s_lo = -1.0f;
+    }
+  }
+  const float smax_abs = fmaxf(fabsf(s_lo), fabsf(s_hi));
+  s_lo -= ETA_SIN;
+  s_hi += ETA_SIN;
+  const uint32_t c_from = chan_search(s, s_lo, false);
+  const uint32_t c_end = chan_search(s, s_hi, true);
+  if (c_from >= c_end) return false;
+  sp.c_from = c_from;
+  sp.c_count = c_end - c_from;
+  if (smax_abs > S_POLE) full = true;
+
+  const uint32_t chi = s.chi;
+  sp.r1_start = 0; sp.r1_count = 0;
+  if (!full) {
+    const float t0 = atan2f(y[0], x[0]);
+    float d1 = atan2f(y[1], x[1]) - t0;
+    float d2 = atan2f(y[2], x[2]) - t0;
+    if (d1 > PI_F) d1 -= TWO_PI_F;
+    if (d1 < -PI_F) d1 += TWO_PI_F;
+    if (d2 > PI_F) d2 -= TWO_PI_F;
+    if (d2 < -PI_F) d2 += TWO_PI_F;
+    const float lo = fminf(0.0f, fminf(d1, d2));
+    const float hi = fmaxf(0.0f, fmaxf(d1, d2));
+    if (hi - lo > PI_F - 1e-3f) {
+      full = true;
+    } else {
+      const float cmin_el = sqrtf(fmaxf(1.0f - smax_abs * smax_abs, 0.0f));
+      const float m = MARGIN_AZ + MARGIN_AZ_POLE / fmaxf(cmin_el, 1e-3f);
+      float a = t0 + lo - m - s.theta_start;
+      a -= TWO_PI_F * floorf(a * (1.0f / TWO_PI_F));
+      if (a < 0.0f) a = 0.0f;
+      const float w = (hi - lo) + 2.0f * m;
+      const float fa = a * s.inv_dtheta;
+      const float fb = (a + w) * s.inv_dtheta;
+      const int ra = (int)ceilf(fa);
+      const int rb = (int)floorf(fb);
+      if (s.wrap) {
+        int cnt = rb - ra + 1;
+        if (cnt <= 0) return false;
+        if (cnt > (int)chi) cnt = (int)chi;
+        sp.r0_start = (uint32_t)ra % chi;
+        sp.r0_count = (uint32_t)cnt;
+      } else {
+        sp.r0_count = 0;
+        if (ra <= (int)chi - 1 && rb >= ra) {
+          const int e0 = rb < (int)chi - 1 ? rb : (int)chi - 1;
+          sp.r0_start = (uint32_t)ra;
+          sp.r0_count = (uint32_t)(e0 - ra + 1);
+        }
+        const float fb2 = (a + w - TWO_PI_F) * s.inv_dtheta;
+        if (fb2 >= 0.0f) {
+          int e1 = (int)floorf(fb2);
+          if (e1 > (int)chi - 1) e1 = (int)chi - 1;
+          sp.r1_start = 0;
+          sp.r1_count = (uint32_t)(e1 + 1);
+          if (sp.r0_count && sp.r0_start <= (uint32_t)e1) {  // overlap: merge
+            sp.r1_count = 0;
+            sp.r0_start = 0;
+            sp.r0_count = chi;
+          }
+        }
+        if (sp.r0_count == 0 && sp.r1_count == 0) return false;
+        if (sp.r0_count == 0) {
+          sp.r0_start = sp.r1_start; sp.r0_count = sp.r1_count; sp.r1_count = 0;
+        }
+      }
+    }
+  }
+  if (full) {
+    sp.r0_start = 0;
+    sp.r0_count = chi;
+    sp.r1_count = 0;
+  }
+  sp.large = full || sp.c_count > small_c || sp.r0_count > small_r ||
+             (sp.r1_count > small_r);
+  return true;
+}
+
+__device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
+  // Blocks are handed to the 8 XCDs round robin; give each XCD a contiguous
+  // run of triangles so that shared vertices stay in one XCD's L2.
+  const uint32_t q = nb / 8u, rem = nb % 8u;
+  const uint32_t x = b % 8u, local = b / 8u;
+  return x * q + (x < rem ? x : rem) + local;
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void bounds_kernel(
+    const DevScene* __restrict__ scenes, uint32_t nscenes, const DevSensor* __restrict__ sens,
+    uint32_t small_c, uint32_t small_r, Item* __restrict__ items, uint32_t item_cap,
+    Item* __restrict__ large, uint32_t large_cap, Counters* __restrict__ cnt) {
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  uint32_t sc = 0;
+  while (sc + 1 < nscenes && b >= scenes[sc + 1].block_start) ++sc;
+  const DevScene& S = scenes[sc];
+  const uint32_t tri = (b - S.block_start) * BLOCK + threadIdx.x;
+  const bool active = tri < S.ntri;
+  float vx[3] = {0, 0, 0}, vy[3] = {0, 0, 0}, vz[3] = {0, 0, 0};
+  if (active) {
+    const uint32_t i0 = S.idx[3ull * tri], i1 = S.idx[3ull * tri + 1], i2 = S.idx[3ull * tri + 2];
+    vx[0] = S.x[i0]; vy[0] = S.y[i0]; vz[0] = S.z[i0];
+    vx[1] = S.x[i1]; vy[1] = S.y[i1]; vz[1] = S.z[i1];
+    vx[2] = S.x[i2]; vy[2] = S.y[i2]; vz[2] = S.z[i2];
+  }
+  for (uint32_t n = S.sensor_begin; n < S.sensor_end; ++n) {
+    const DevSensor& s = sens[n];
+    Span sp;
+    const bool ok = active && span_of(vx, vy, vz, s, small_c, small_r, sp);
+    const uint32_t chan = ok ? (sp.c_from | (sp.c_count << 16)) : 0u;
+    const bool is_large = ok && sp.large;
+    const bool rect0 = ok && !sp.large;
+    const bool rect1 = rect0 && sp.r1_count > 0;
+    Item r0{tri, chan, rect0 ? (sp.r0_start | (sp.r0_count << 16)) : 0u, n};
+    wave_push(rect0, r0, items, item_cap, &cnt->n_items, &cnt->overflow, 1u, &cnt->n_rect);
+    Item r1{tri, chan, rect1 ? (sp.r1_start | (sp.r1_count << 16)) : 0u, n};
+    wave_push(rect1, r1, items, item_cap, &cnt->n_items, &cnt->overflow, 1u, &cnt->n_rect);
+    Item lg{tri, chan, 0u, n};
+    wave_push(is_large, lg, large, large_cap, &cnt->n_large, &cnt->overflow, 2u, nullptr);
+  }
+}
+
+// ------------------------------------------------------------------ expansion
+// Per channel j (cone of elevation phi_j), the candidate azimuths are those
+// whose direction x(theta) = (cos phi cos theta, cos phi sin theta, sin phi)
+// lies on the positive side of all three edge planes, each moved outward by
+// the angular margin SIN_M:  A_k cos(theta - beta_k) >= -SIN_M - sin(phi) n_kz,
+// A_k = cos(phi) |n_k,xy|.  Each edge gives an arc (or everything / nothing);
+// their intersection is the channel's exact span, with no seam or CW/CCW
+// ambiguity.  Computed in FP64.
+struct ArcSet {
+  int n;
+  double lo[6], hi[6];
+};
+
+__device__ inline void arc_intersect(ArcSet& A, double xl, double xh) {
+  ArcSet out;
+  out.n = 0;
+  for (int i = 0; i < A.n; ++i) {
+    const double p0 = A.lo[i], p1 = A.hi[i];
+    // shift the arc so that its start lies in (p0 - 2 pi, p0]
+    const double k = ceil((xl - p0) / TWO_PI);
+    const double s0 = xl - k * TWO_PI, s1 = xh - k * TWO_PI;
+    for (int c = 0; c < 2; ++c) {
+      const double q0 = s0 + c * TWO_PI, q1 = s1 + c * TWO_PI;
+      const double l = fmax(p0, q0), h = fmin(p1, q1);
+      if (l <= h) {
+        if (out.n < 6) {
+          out.lo[out.n] = l; out.hi[out.n] = h; ++out.n;
+        } else {  // cannot happen geometrically (at most 3 pieces); stay conservative
+          out.lo[5] = fmin(out.lo[5], l); out.hi[5] = fmax(out.hi[5], h);
+        }
+      }
+    }
+  }
+  A = out;
+}
+
+// Ray-index ranges [start, start + count) of one angular piece.
+__device__ inline int piece_ranges(const DevSensor& s, double lo, double hi, uint32_t* st,
+                                   uint32_t* ct) {
+  double a = lo - s.theta_start_d;
+  a -= TWO_PI * floor(a / TWO_PI);
+  if (a < 0.0) a = 0.0;
+  const double w = hi - lo;
+  const double fa = a * s.inv_dtheta_d, fb = (a + w) * s.inv_dtheta_d;
+  const long ra = (long)ceil(fa), rb = (long)floor(fb);
+  const long chi = (long)s.chi;
+  int n = 0;
+  if (s.wrap) {
+    long c = rb - ra + 1;
+    if (c > 0) {
+      if (c > chi) c = chi;
+      st[0] = (uint32_t)(ra % chi);
+      ct[0] = (uint32_t)c;
+      n = 1;
+    }
+  } else {
+    if (ra <= chi - 1 && rb >= ra) {
+      const long e0 = rb < chi - 1 ? rb : chi - 1;
+      st[n] = (uint32_t)ra; ct[n] = (uint32_t)(e0 - ra + 1); ++n;
+    }
+    const double fb2 = (a + w - TWO_PI) * s.inv_dtheta_d;
+    if (fb2 >= 0.0) {
+      long e1 = (long)floor(fb2);
+      if (e1 > chi - 1) e1 = chi - 1;
+      st[n] = 0; ct[n] = (uint32_t)(e1 + 1); ++n;
+    }
+  }
+  return n;
+}
+
+template <int WPB>
+__global__ __launch_bounds__(WPB * 64) void expand_kernel(
+    const DevScene* __restrict__ scenes, const DevSensor* __restrict__ sens,
+    const Item* __restrict__ large, Item* __restrict__ items, uint32_t item_cap,
+    uint32_t large_cap, uint32_t row_chunk, Counters* __restrict__ cnt) {
+  const uint32_t lane = lane_id();
+  const uint32_t n_large = min(cnt->n_large, large_cap);
+  for (;;) {
+    uint32_t rec = 0;
+    if (lane == 0) rec = atomicAdd(&cnt->tk_large, 1u);
+    rec = __shfl(rec, 0, 64);
+    if (rec >= n_large) break;
+    const Item L = large[rec];
+    const DevSensor& s = sens[L.sensor];
+    const DevScene& S = scenes[s.scene];
+    const uint32_t t = L.tri;
+    const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
+    Statics st;
+    double nrm[3][3];
+    if (!make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
+                      S.z[i2], s, st, nrm))
+      continue;
+    double beta[3], hxy[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      beta[k] = atan2(nrm[k][1], nrm[k][0]);
+      hxy[k] = sqrt(nrm[k][0] * nrm[k][0] + nrm[k][1] * nrm[k][1]);
+    }
+    const uint32_t c_from = L.chan & 0xFFFFu, c_count = L.chan >> 16;
+    for (uint32_t base = 0; base < c_count; base += 64) {
+      const uint32_t j = c_from + base + lane;
+      const bool act = base + lane < c_count;
+      uint32_t rs[12], rc[12];
+      int nr = 0;
+      if (act) {
+        const double2 cs = s.chan_d[j];
+        const double cj = cs.x, sj = cs.y;
+        ArcSet A;
+        A.n = 0;
+        bool empty = false, restricted = false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const double Ak = fabs(cj) * hxy[k];
+          const double rhs = -SIN_M - sj * nrm[k][2];
+          if (rhs <= -Ak) continue;  // the whole circle satisfies this edge
+          if (rhs > Ak) { empty = true; continue; }
+          double rho = rhs / Ak;
+          rho = fmin(1.0, fmax(-1.0, rho));
+          const double w = acos(rho);
+          // cos phi < 0 (a channel rounded past the pole) mirrors the azimuth
+          const double b = cj >= 0.0 ? beta[k] : beta[k] + 3.14159265358979323846;
+          if (!restricted) {
+            A.n = 1; A.lo[0] = b - w; A.hi[0] = b + w; restricted = true;
+          } else {
+            arc_intersect(A, b - w, b + w);
+          }
+        }
+        if (!empty) {
+          if (!restricted) {
+            rs[0] = 0; rc[0] = s.chi; nr = 1;
+          } else {
+            for (int i = 0; i < A.n && nr < 11; ++i) nr += piece_ranges(s, A.lo[i], A.hi[i], rs + nr, rc + nr);
+          }
+        }
+      }
+      // count row items (ranges chopped into row_chunk rays)
+      uint32_t nitems = 0;
+      for (int i = 0; i < nr; ++i) nitems += (rc[i] + row_chunk - 1) / row_chunk;
+      const uint32_t incl = wave_incl_scan(nitems);
+      const uint32_t total = __shfl(incl, 63, 64);
+      if (total == 0) continue;
+      uint32_t wbase = 0;
+      if (lane == 63) {
+        wbase = atomicAdd(&cnt->n_items, total);
+        atomicAdd(&cnt->n_rows, total);
+      }
+      wbase = __shfl(wbase, 63, 64);
+      uint32_t slot = wbase + incl - nitems;
+      bool ovf = false;
+      for (int i = 0; i < nr; ++i) {
+        for (uint32_t o = 0; o < rc[i]; o += row_chunk) {
+          const uint32_t c = min(row_chunk, rc[i] - o);
+          uint32_t r0 = rs[i] + o;
+          if (r0 >= s.chi) r0 -= s.chi;
+          if (slot < item_cap) {
+            items[slot] = Item{t, j | (1u << 16), r0 | (c << 16), L.sensor};
+          } else {
+            ovf = true;
+          }
+          ++slot;
+        }
+      }
+      if (ovf) atomicOr(&cnt->overflow, 1u);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ intersection
+struct ItemInfo {
+  uint32_t tri, c_from, r_start, r_count;
+  uint32_t chi, key_offset;
+  float dmin, dmax;
+  const float2* chan;
+  const float2* az;
+  float inv_rc;
+  uint32_t pad;
+};
+
+template <int WPB>
+__global__ __launch_bounds__(WPB * 64) void isect_kernel(
+    const DevScene* __restrict__ scenes, const DevSensor* __restrict__ sens,
+    const Item* __restrict__ items, uint32_t item_cap, Counters* __restrict__ cnt,
+    unsigned long long* __restrict__ keys) {
+  __shared__ Statics st_s[WPB][64];
+  __shared__ ItemInfo in_s[WPB][64];
+  __shared__ uint32_t pre_s[WPB][65];
+  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  const uint32_t n_items = min(cnt->n_items, item_cap);
+  for (;;) {
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&cnt->tk_items, 64u);
+    base = __shfl(base, 0, 64);
+    if (base >= n_items) break;
+    const uint32_t i = base + lane;
+    uint32_t count = 0;
+    if (i < n_items) {
+      const Item it = items[i];
+      const DevSensor& s = sens[it.sensor];
+      const DevScene& S = scenes[s.scene];
+      const uint32_t t = it.tri;
+      const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
+      Statics st;
+      if (make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
+                       S.z[i2], s, st)) {
+        const uint32_t cc = it.chan >> 16, rc = it.rays >> 16;
+        count = cc * rc;
+        st_s[w][lane] = st;
+        ItemInfo inf;
+        inf.tri = t;
+        inf.c_from = it.chan & 0xFFFFu;
+        inf.r_start = it.rays & 0xFFFFu;
+        inf.r_count = rc;
+        inf.chi = s.chi;
+        inf.key_offset = s.key_offset;
+        inf.dmin = s.dmin;
+        inf.dmax = s.dmax;
+        inf.chan = s.chan;
+        inf.az = s.az;
+        inf.inv_rc = 1.0f / (float)rc;
+        inf.pad = 0;
+        in_s[w][lane] = inf;
+      }
+    }
+    const uint32_t incl = wave_incl_scan(count);
+    pre_s[w][lane + 1] = incl;
+    if (lane == 0) pre_s[w][0] = 0;
+    const uint32_t total = __shfl(incl, 63, 64);
+    if (lane == 0 && total) atomicAdd(&cnt->rtic, (unsigned long long)total);
+    wave_sync();
+    int cur = -1;
+    Statics st;
+    ItemInfo inf;
+    for (uint32_t f = lane; f < total; f += 64) {
+      // owner = last item whose prefix start <= f
+      uint32_t lo = 0, hi = 64;
+#pragma unroll
+      for (int it = 0; it < 6; ++it) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre_s[w][mid] <= f) lo = mid; else hi = mid;
+      }
+      if ((int)lo != cur) {
+        cur = (int)lo;
+        st = st_s[w][lo];
+        inf = in_s[w][lo];
+      }
+      const uint32_t local = f - pre_s[w][lo];
+      uint32_t c = (uint32_t)((float)local * inf.inv_rc);
+      if (c * inf.r_count > local) --c;
+      else if ((c + 1) * inf.r_count <= local) ++c;
+      const uint32_t r = local - c * inf.r_count;
+      const uint32_t ch = inf.c_from + c;
+      uint32_t ray = inf.r_start + r;
+      if (ray >= inf.chi) ray -= inf.chi;
+      const float2 cp = inf.chan[ch];
+      const float2 ca = inf.az[ray];
+      const unsigned long long key = ray_test(st, cp.x, cp.y, ca.x, ca.y, inf.dmin, inf.dmax,
+                                              inf.tri);
+      if (key != KEY_INIT) key_min(keys, inf.key_offset + ch * inf.chi + ray, key);
+    }
+    wave_sync();
+  }
+}
+
+// ------------------------------------------------------------------ all pairs
+__global__ void statics_kernel(const DevScene* __restrict__ scenes, const DevSensor* __restrict__ sens,
+                               uint32_t sensor, Statics* __restrict__ out) {
+  const DevSensor& s = sens[sensor];
+  const DevScene& S = scenes[s.scene];
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= S.ntri) return;
+  const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
+  Statics st;
+  if (!make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
+                    S.z[i2], s, st)) {
+    st = Statics{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1.0f, 0, 0, 0};
+  }
+  out[t] = st;
+}
+
+// One thread per ray, loop over a chunk of triangles; every ray is tested
+// against every triangle of the chunk.
+__global__ __launch_bounds__(256) void allpairs_kernel(const DevSensor* __restrict__ sens,
+                                                       uint32_t sensor, const Statics* __restrict__ st_all,
+                                                       uint32_t ntri, uint32_t chunk,
+                                                       unsigned long long* __restrict__ keys) {
+  __shared__ Statics tile[256];
+  const DevSensor& s = sens[sensor];
+  const uint32_t nrays = s.gamma * s.chi;
+  const uint32_t g = blockIdx.x * 256 + threadIdx.x;
+  const bool act = g < nrays;
+  const uint32_t ch = act ? g / s.chi : 0, ray = act ? g % s.chi : 0;
+  const float2 cp = s.chan[ch];
+  const float2 ca = s.az[ray];
+  unsigned long long best = KEY_INIT;
+  const uint32_t t_begin = blockIdx.y * chunk;
+  const uint32_t t_end = min(ntri, t_begin + chunk);
+  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 256) {
+    __syncthreads();
+    if (t0 + threadIdx.x < t_end) tile[threadIdx.x] = st_all[t0 + threadIdx.x];
+    __syncthreads();
+    const uint32_t n = min(256u, t_end - t0);
+    if (act) {
+      for (uint32_t k = 0; k < n; ++k) {
+        const unsigned long long key =
+            ray_test(tile[k], cp.x, cp.y, ca.x, ca.y, s.dmin, s.dmax, t0 + k);
+        best = key < best ? key : best;
+      }
+    }
+  }
+  if (act && best != KEY_INIT) key_min(keys, s.key_offset + g, best);
+}
+
+// ------------------------------------------------------------------ resolve
+__global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint32_t n,
+                               float* __restrict__ dist, uint32_t* __restrict__ tri) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const unsigned long long k = keys[g];
+  const uint32_t hi = (uint32_t)(k >> 32);
+  // inverse of f_sort: m = ((u >> 31) - 1) | 2^31
+  const uint32_t m = ((hi >> 31) - 1u) | 0x80000000u;
+  if (dist) dist[g] = __uint_as_float(hi ^ m);
+  if (tri) tri[g] = (uint32_t)k;
+}
+
+// ------------------------------------------------------------------ pose
+// Each block handles up to 256 vertices of one rigid instance or deform group.
+__global__ __launch_bounds__(256) void pose_kernel(
+    const PoseBlock* __restrict__ blocks, const float* __restrict__ rx,
+    const float* __restrict__ ry, const float* __restrict__ rz, const float* __restrict__ nx,
+    const float* __restrict__ ny, const float* __restrict__ nz, const float* __restrict__ phase,
+    const DeformParam* __restrict__ groups, const double* __restrict__ pose_in,
+    float* __restrict__ x, float* __restrict__ y, float* __restrict__ z) {
+  const PoseBlock pb = blocks[blockIdx.x];
+  const uint32_t i = threadIdx.x;
+  if (i >= pb.count) return;
+  const uint32_t v = pb.v_begin + i;
+  const uint32_t r = pb.rest_begin + i;
+  const double px = rx[r], py = ry[r], pz = rz[r];
+  if (pb.kind == 0) {
+    const float* M = reinterpret_cast<const float*>(pose_in + 1) + 12ull * pb.group;
+    x[v] = (float)((double)M[0] * px + (double)M[1] * py + (double)M[2] * pz + (double)M[3]);
+    y[v] = (float)((double)M[4] * px + (double)M[5] * py + (double)M[6] * pz + (double)M[7]);
+    z[v] = (float)((double)M[8] * px + (double)M[9] * py + (double)M[10] * pz + (double)M[11]);
+  } else {
+    const DeformParam g = groups[pb.group];
+    const double time = pose_in[0];
+    const double wv = (double)g.amplitude * sin((double)g.omega * time + (double)phase[r]);
+    x[v] = (float)(px + wv * (double)nx[r]);
+    y[v] = (float)(py + wv * (double)ny[r]);
+    z[v] = (float)(pz + wv * (double)nz[r]);
+  }
+}
+
+// ------------------------------------------------------------------ sensor tables
+__global__ void sensor_tables_kernel(const float* __restrict__ elev, uint32_t gamma, uint32_t chi,
+                                     double dtheta, float2* __restrict__ chan,
+                                     double2* __restrict__ chan_d, float* __restrict__ sin_tab,
+                                     float2* __restrict__ az) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < gamma) {
+    const double p = (double)elev[i];
+    const double c = cos(p), s = sin(p);
+    chan[i] = make_float2((float)c, (float)s);
+    chan_d[i] = make_double2(c, s);
+    sin_tab[i] = (float)s;
+  }
+  if (i < chi) {
+    // theta_R = (R - floor(chi / 2)) * dtheta (section 3.1, centred start)
+    const double th = ((double)i - (double)(chi / 2)) * dtheta;
+    az[i] = make_float2((float)cos(th), (float)sin(th));
+  }
+}
+
+__global__ void sensor_lut_kernel(const float* __restrict__ sin_tab, uint32_t gamma,
+                                  uint32_t lut_size, uint16_t* __restrict__ lut) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= lut_size) return;
+  const float edge = -1.0f + 2.0f * (float)b / (float)lut_size;
+  uint32_t lo = 0, hi = gamma;  // first j with sin_tab[j] >= edge
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (sin_tab[mid] < edge) lo = mid + 1; else hi = mid;
+  }
+  lut[b] = (uint16_t)lo;
+}
+
+// ------------------------------------------------------------------ input checks
+__global__ void validate_kernel(const float* __restrict__ xyz, uint32_t nv,
+                                const uint32_t* __restrict__ idx, uint64_t nidx,
+                                uint32_t* __restrict__ bad) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3ull * nv && !isfinite(xyz[i])) atomicOr(bad, 1u);
+  if (idx && i < nidx && idx[i] >= nv) atomicOr(bad, 2u);
+}
+
+__global__ void soa_kernel(const float* __restrict__ xyz, uint32_t nv, float* __restrict__ x,
+                           float* __restrict__ y, float* __restrict__ z) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  x[i] = xyz[3ull * i];
+  y[i] = xyz[3ull * i + 1];
+  z[i] = xyz[3ull * i + 2];
+}
+
+__global__ void copy_range_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                  uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// ================================================================== launchers
+static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+hipError_t launch_init(unsigned long long* keys, uint32_t n, Counters* cnt, hipStream_t st) {
+  const uint32_t nb = cdiv(n > 0 ? n : 1, 256);
+  hipLaunchKernelGGL(init_kernel, dim3(nb), dim3(256), 0, st, keys, n, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t total_blocks,
+                         uint32_t block, const DevSensor* sens, uint32_t small_c,
+                         uint32_t small_r, Item* items, uint32_t item_cap, Item* large,
+                         uint32_t large_cap, Counters* cnt, hipStream_t st) {
+  if (total_blocks == 0) return hipSuccess;
+#define GRCA_BOUNDS_CASE(B)                                                                   \
+  case B:                                                                                     \
+    hipLaunchKernelGGL(bounds_kernel<B>, dim3(total_blocks), dim3(B), 0, st, scenes, nscenes, \
+                       sens, small_c, small_r, items, item_cap, large, large_cap, cnt);       \
+    break;
+  switch (block) {
+    GRCA_BOUNDS_CASE(64)
+    GRCA_BOUNDS_CASE(128)
+    GRCA_BOUNDS_CASE(256)
+    GRCA_BOUNDS_CASE(512)
+    GRCA_BOUNDS_CASE(1024)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef GRCA_BOUNDS_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const DevScene* scenes, const DevSensor* sens, const Item* large,
+                         Item* items, uint32_t item_cap, uint32_t large_cap, uint32_t row_chunk,
+                         Counters* cnt, uint32_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(expand_kernel<4>, dim3(nblocks), dim3(256), 0, st, scenes, sens, large,
+                     items, item_cap, large_cap, row_chunk, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, const Item* items,
+                        uint32_t item_cap, Counters* cnt, unsigned long long* keys,
+                        uint32_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(isect_kernel<4>, dim3(nblocks), dim3(256), 0, st, scenes, sens, items,
+                     item_cap, cnt, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_allpairs(const DevScene* scenes, const DevSensor* sens, uint32_t sensor,
+                           uint32_t ntri, uint32_t nrays, Statics* scratch,
+                           unsigned long long* keys, hipStream_t st) {
+  if (ntri == 0 || nrays == 0) return hipSuccess;
+  hipLaunchKernelGGL(statics_kernel, dim3(cdiv(ntri, 256)), dim3(256), 0, st, scenes, sens,
+                     sensor, scratch);
+  const uint32_t chunk = 4096;
+  hipLaunchKernelGGL(allpairs_kernel, dim3(cdiv(nrays, 256), cdiv(ntri, chunk)), dim3(256), 0,
+                     st, sens, sensor, scratch, ntri, chunk, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve(const unsigned long long* keys, uint32_t n, float* dist, uint32_t* tri,
+                          hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(resolve_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, keys, n, dist, tri);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* rx, const float* ry,
+                       const float* rz, const float* nx, const float* ny, const float* nz,
+                       const float* phase, const DeformParam* groups, const double* pose_in,
+                       float* x, float* y, float* z, hipStream_t st) {
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(pose_kernel, dim3(nblocks), dim3(256), 0, st, blocks, rx, ry, rz, nx, ny,
+                     nz, phase, groups, pose_in, x, y, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_sensor_tables(const float* elev, uint32_t gamma, uint32_t chi, double dtheta,
+                                float2* chan, double2* chan_d, float* sin_tab, float2* az,
+                                uint32_t lut_size, uint16_t* lut, hipStream_t st) {
+  const uint32_t n = gamma > chi ? gamma : chi;
+  hipLaunchKernelGGL(sensor_tables_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, elev, gamma,
+                     chi, dtheta, chan, chan_d, sin_tab, az);
+  hipLaunchKernelGGL(sensor_lut_kernel, dim3(cdiv(lut_size, 256)), dim3(256), 0, st, sin_tab,
+                     gamma, lut_size, lut);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const float* xyz, uint32_t nv, const uint32_t* idx, uint64_t nidx,
+                           uint32_t* bad, hipStream_t st) {
+  const uint64_t n = 3ull * nv > nidx ? 3ull * nv : nidx;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(validate_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, xyz, nv, idx, nidx,
+                     bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_soa(const float* xyz, uint32_t nv, float* x, float* y, float* z,
+                      hipStream_t st) {
+  if (nv == 0) return hipSuccess;
+  hipLaunchKernelGGL(soa_kernel, dim3(cdiv(nv, 256)), dim3(256), 0, st, xyz, nv, x, y, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const float* src, float* dst, uint32_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_range_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace grca

@@ -1,0 +1,56 @@
+// grca_launch.hpp -- host-callable launchers of the caster's kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grca_device.hpp"
+
+namespace grca {
+
+// One block of the pose kernel: up to 256 vertices of one rigid instance
+// (kind 0, `group` = instance index) or one deform group (kind 1).
+struct PoseBlock {
+  uint32_t kind;
+  uint32_t group;
+  uint32_t v_begin;    // first scene vertex of this block
+  uint32_t count;      // vertices in this block (<= 256)
+  uint32_t rest_begin; // first entry in the rest / normal / phase arrays
+  uint32_t pad[3];
+};
+
+struct DeformParam {
+  float amplitude;
+  float omega;
+};
+
+hipError_t launch_init(unsigned long long* keys, uint32_t n, Counters* cnt, hipStream_t st);
+hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t total_blocks,
+                         uint32_t block, const DevSensor* sens, uint32_t small_c,
+                         uint32_t small_r, Item* items, uint32_t item_cap, Item* large,
+                         uint32_t large_cap, Counters* cnt, hipStream_t st);
+hipError_t launch_expand(const DevScene* scenes, const DevSensor* sens, const Item* large,
+                         Item* items, uint32_t item_cap, uint32_t large_cap, uint32_t row_chunk,
+                         Counters* cnt, uint32_t nblocks, hipStream_t st);
+hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, const Item* items,
+                        uint32_t item_cap, Counters* cnt, unsigned long long* keys,
+                        uint32_t nblocks, hipStream_t st);
+hipError_t launch_allpairs(const DevScene* scenes, const DevSensor* sens, uint32_t sensor,
+                           uint32_t ntri, uint32_t nrays, Statics* scratch,
+                           unsigned long long* keys, hipStream_t st);
+hipError_t launch_resolve(const unsigned long long* keys, uint32_t n, float* dist, uint32_t* tri,
+                          hipStream_t st);
+hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* rx, const float* ry,
+                       const float* rz, const float* nx, const float* ny, const float* nz,
+                       const float* phase, const DeformParam* groups, const double* pose_in,
+                       float* x, float* y, float* z, hipStream_t st);
+hipError_t launch_sensor_tables(const float* elev, uint32_t gamma, uint32_t chi, double dtheta,
+                                float2* chan, double2* chan_d, float* sin_tab, float2* az,
+                                uint32_t lut_size, uint16_t* lut, hipStream_t st);
+hipError_t launch_validate(const float* xyz, uint32_t nv, const uint32_t* idx, uint64_t nidx,
+                           uint32_t* bad, hipStream_t st);
+hipError_t launch_soa(const float* xyz, uint32_t nv, float* x, float* y, float* z,
+                      hipStream_t st);
+hipError_t launch_copy(const float* src, float* dst, uint32_t n, hipStream_t st);
+
+}  // namespace grca

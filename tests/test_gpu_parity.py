@@ -1,0 +1,191 @@
+"""GPU parity of the HIP caster against the FP64 oracle (through the C ABI).
+
+Every test prints the case it runs before touching the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2605_10457_amd import grca, synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = grca.Context(0)
+    yield c
+    c.close()
+
+
+def _cast(ctx, ids, n, flags=0):
+    return ctx.cast_host(ids, n, flags)
+
+
+def _parity(ctx, sensor, v, f, scene_id=0, sensor_id=0, rays=None, all_pairs_check=True,
+            label=""):
+    ctx.scene_update(scene_id, v, f)
+    ctx.sensor_config(sensor_id, sensor, scene_id)
+    n = len(sensor["elevation"]) * sensor["rays_per_channel"]
+    d, t = _cast(ctx, [sensor_id], n)
+    if all_pairs_check:
+        d2, t2 = _cast(ctx, [sensor_id], n, grca.GRCA_CAST_ALL_PAIRS)
+        assert np.array_equal(t, t2) and np.array_equal(d.view(np.uint32), d2.view(np.uint32)), \
+            f"{label}: culled != all-pairs at {np.nonzero(t != t2)[0][:10]}"
+    orc = O.cast(sensor, v, f, rays=rays)
+    sel = orc["rays"]
+    rep = parity.check(sensor, v, f, orc, d[sel], t[sel])
+    parity.assert_parity(rep, label)
+    return rep, d, t
+
+
+def test_config1_full_parity(ctx):
+    _say("config1 full: 19.6k tris, 32x512 rays, oracle on every ray")
+    wl = synth.config1()
+    rep, d, t = _parity(ctx, wl.sensors[0], wl.scene.vertices, wl.scene.indices, label="config1")
+    c = rep["counts"]
+    assert c["hits"] > 5000
+    st = ctx.last_stats()
+    print("config1", c, st, flush=True)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_small_adversarial_scenes(ctx, seed):
+    _say(f"small adversarial scene seed={seed}")
+    v, f = synth.small_random_scene(seed, n_tris=80)
+    fovs = [360.0, 180.0, 90.0, 300.0]
+    s = synth.sensor((0.1 * seed, -0.2, 0.05), 0.3 * seed, synth.elevations_full_sphere(24), 96,
+                     fovs[seed % 4], 0.05, 40.0)
+    _parity(ctx, s, v, f, label=f"adv{seed}")
+
+
+def test_ground_plane_closed_form_gpu(ctx):
+    _say("ground plane, full-sphere grid incl. the nadir channel")
+    rng = np.random.default_rng(3)
+    b = synth._Builder()
+    g = synth._ground(b, 40.0, 20, rng)
+    v, f = b.build()
+    s = synth.sensor((0.3, -0.2, 1.8), 0.7, synth.elevations_full_sphere(32), 64, 360.0, 0.05, 60.0)
+    _parity(ctx, s, v, f, label="ground")
+
+
+def test_sphere_around_emitter_gpu(ctx):
+    _say("icosphere level 4 centred on the emitter: every ray hits")
+    o = np.array([1.5, -2.0, 3.0])
+    sv, sf = synth.icosphere(4)
+    v = (sv * 7.0 + o).astype(np.float32)
+    s = synth.sensor(o, 0.2, synth.elevations_full_sphere(32), 128, 360.0, 0.05, 100.0)
+    rep, d, t = _parity(ctx, s, v, sf, label="sphere")
+    assert np.all(t != grca.GRCA_MISS_TRI)
+
+
+def test_box_interior_gpu(ctx):
+    _say("sensor inside an axis-aligned box")
+    lo = np.array([-3.0, -2.0, -1.0])
+    hi = np.array([4.0, 5.0, 2.5])
+    bv, bf = synth.unit_box()
+    v = ((bv + 0.5) * (hi - lo) + lo).astype(np.float32)
+    s = synth.sensor((0.4, 1.1, 0.3), 0.3, synth.elevations_full_sphere(40), 200, 360.0, 0.05, 50.0)
+    rep, d, t = _parity(ctx, s, v, bf, label="box")
+    assert np.all(t != grca.GRCA_MISS_TRI)
+
+
+def test_batch_equals_alone_bitwise(ctx):
+    _say("8 sensors of uneven shape in one cast vs each alone")
+    wl = synth.config1()
+    ctx.scene_update(0, wl.scene.vertices, wl.scene.indices)
+    shapes = [(32, 512, 360.0), (16, 256, 180.0), (8, 100, 90.0), (24, 300, 360.0)] * 2
+    sens = synth.ring_rig(shapes, radius=8.0, seed=4, full_sphere=True)
+    ids = list(range(10, 18))
+    for i, s in zip(ids, sens):
+        ctx.sensor_config(i, s, 0)
+    sizes = [len(s["elevation"]) * s["rays_per_channel"] for s in sens]
+    d_all, t_all = _cast(ctx, ids, sum(sizes))
+    off = 0
+    for i, n in zip(ids, sizes):
+        d1, t1 = _cast(ctx, [i], n)
+        assert np.array_equal(t1, t_all[off:off + n])
+        assert np.array_equal(d1.view(np.uint32), d_all[off:off + n].view(np.uint32))
+        off += n
+    # reversed order: outputs follow the caller's order
+    d_rev, t_rev = _cast(ctx, ids[::-1], sum(sizes))
+    off_r = 0
+    offs = np.cumsum([0] + sizes)
+    for j, i in enumerate(ids[::-1]):
+        n = sizes[len(ids) - 1 - j]
+        k = len(ids) - 1 - j
+        assert np.array_equal(t_rev[off_r:off_r + n], t_all[offs[k]:offs[k] + n])
+        off_r += n
+
+
+@pytest.mark.parametrize("opts", [dict(small_channels=1, small_rays=1),
+                                  dict(small_channels=64, small_rays=64),
+                                  dict(small_channels=255, small_rays=4096, row_chunk=7),
+                                  dict(bounds_block=64, persist_waves_cu=1),
+                                  dict(bounds_block=1024, row_chunk=4096)])
+def test_options_do_not_change_results(ctx, opts):
+    _say(f"tuning options {opts}")
+    wl = synth.config1()
+    ctx.scene_update(0, wl.scene.vertices, wl.scene.indices)
+    ctx.sensor_config(0, wl.sensors[0], 0)
+    n = 32 * 512
+    base = _cast(ctx, [0], n)
+    old = ctx.get_options()
+    try:
+        ctx.set_options(**opts)
+        other = _cast(ctx, [0], n)
+    finally:
+        ctx.set_options(**old)
+    assert np.array_equal(base[1], other[1])
+    assert np.array_equal(base[0].view(np.uint32), other[0].view(np.uint32))
+
+
+def test_queue_overflow_recasts(ctx):
+    _say("tiny queue capacities force overflow and recast")
+    wl = synth.config1()
+    c2 = grca.Context(0)
+    try:
+        c2.set_options(item_capacity=64, large_capacity=64)
+        c2.scene_update(0, wl.scene.vertices, wl.scene.indices)
+        c2.sensor_config(0, wl.sensors[0], 0)
+        d, t = c2.cast_host([0], 32 * 512)
+        st = c2.last_stats()
+        assert st["recasts"] >= 1
+    finally:
+        c2.close()
+    ctx.scene_update(0, wl.scene.vertices, wl.scene.indices)
+    ctx.sensor_config(0, wl.sensors[0], 0)
+    d0, t0 = _cast(ctx, [0], 32 * 512)
+    assert np.array_equal(t, t0) and np.array_equal(d.view(np.uint32), d0.view(np.uint32))
+
+
+def test_invalid_inputs_rejected(ctx):
+    _say("invalid inputs return error codes")
+    v = np.zeros((3, 3), np.float32)
+    with pytest.raises(grca.GrcaError) as e:
+        ctx.scene_update(99, v, np.array([[0, 1, 3]], np.uint32))
+    assert e.value.status == grca.GRCA_ERR_INVALID_ARG
+    vb = v.copy()
+    vb[1, 1] = np.nan
+    with pytest.raises(grca.GrcaError):
+        ctx.scene_update(99, vb, np.array([[0, 1, 2]], np.uint32))
+    s = synth.sensor((0, 0, 0), 0.0, np.array([0.1, 0.0], np.float32), 8)
+    with pytest.raises(grca.GrcaError):
+        ctx.sensor_config(99, s, 0)  # not ascending
+    s = synth.sensor((0, 0, 0), 0.0, np.array([0.0], np.float32), 8)
+    s["forward"] = np.array([1.0, 0.01, 0.0], np.float32)
+    with pytest.raises(grca.GrcaError):
+        ctx.sensor_config(99, s, 0)  # basis not orthonormal
+    with pytest.raises(grca.GrcaError) as e:
+        ctx.cast([12345], np.empty(1, np.float32), np.empty(1, np.uint32))
+    assert e.value.status == grca.GRCA_ERR_NOT_FOUND
