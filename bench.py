@@ -1,0 +1,267 @@
+#!/usr/bin/env python
+"""Frame benchmark of the emitter-centric caster on one MI355X.
+
+Workload (default): 8 LiDARs of 128x4096 rays (4 x 360 deg, 4 x 180 deg facing
+outward) on a 20 m ring over ~22M triangles of which ~9M are dynamic (20 rigid
+vehicle proxies re-posed with a fresh random pose, per-axis scale and yaw
+every frame, plus 10 sinusoidally deforming grids), range 0.05-1000 m.
+
+A step is one frame: pose the dynamic geometry, then cast every ray of the 8
+sensors (bounds + binning, large-class expansion, intersection, resolve).
+  * batched: one hipGraph replay per frame (one 8-origin bounds pass, one
+    persistent work queue for all sensors) -- this is `value`;
+  * plain:   pose + one grca_cast per sensor, issued back to back, no graph.
+Inputs are resident in HBM before the timed region; per-frame pose matrices
+are generated beforehand and copied inside the frame (48 B per instance).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rays/s + frame ms, 8×(128×4096) LiDARs on 22M tris; batched vs plain; p99"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3          # published MI355X vector FP32
+FLOPS_PER_RTIC = 22               # ray test: 2 mul (direction) + 4 dot products x 5 flops
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a, np.float64), q)) if len(a) else float("nan")
+
+
+def oracle_pose(scene, frame):
+    """The oracle's own pose of the dynamic geometry (FP64, rounded to FP32)."""
+    from oracle import oracle as O
+    from paper_2605_10457_amd import synth
+    v = scene.vertices.copy()
+    if scene.rigid is not None:
+        mats = scene.instance_matrices(frame)
+        for i, (s, c) in enumerate(zip(scene.rigid.vertex_start, scene.rigid.vertex_count)):
+            v[s:s + c] = O.pose_rigid(scene.vertices[s:s + c], mats[i])
+    off = 0
+    for g in scene.deform:
+        s, c = g.vertex_start, g.vertex_count
+        v[s:s + c] = O.pose_deform(scene.vertices[s:s + c], scene.deform_normals[off:off + c],
+                                   scene.deform_phase[off:off + c], g.amplitude, g.omega,
+                                   synth.deform_time(frame))
+        off += c
+    return v
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--range-max", type=float, default=1000.0)
+    ap.add_argument("--scale", type=float, default=1.0, help="scene size factor (1 = 22M tris)")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rays", type=int, default=16, help="oracle rays per sensor")
+    ap.add_argument("--tuning", default=None, help="JSON file of grca options")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}); this "
+              "build has no multi-GPU path: sensors or triangles would shard across GPUs as "
+              "described in DESIGN.md.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_10457_amd import grca, synth
+
+    t0 = time.time()
+    wl = synth.config4(range_max=args.range_max, scale=args.scale)
+    sc = wl.scene
+    n_sens = len(wl.sensors)
+    sizes = [len(s["elevation"]) * s["rays_per_channel"] for s in wl.sensors]
+    n_rays = int(sum(sizes))
+    log(f"workload: {sc.num_triangles} tris ({sc.n_dynamic_tris} dynamic), {n_rays} rays, "
+        f"generated in {time.time() - t0:.1f}s")
+    mats = [sc.instance_matrices(i) for i in range(args.warmup + args.steps + 1)]
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ctx = grca.Context(0)
+    opts = {"item_capacity": 96 << 20, "large_capacity": 8 << 20}
+    if args.tuning and os.path.exists(args.tuning):
+        opts.update(json.load(open(args.tuning)).get("options", {}))
+    ctx.set_options(**opts)
+    ids = grca.load_workload(ctx, wl, scene_id=0, frame=0, stream=stream)
+    torch.cuda.synchronize()
+    dist = torch.empty(n_rays, dtype=torch.float32, device=dev)
+    tri = torch.empty(n_rays, dtype=torch.int32, device=dev)
+    log(f"scene resident; options {ctx.get_options()}")
+
+    # ---------------- batched: hipGraph frame
+    frame = grca.grca_frame_create(ctx.h, 0, ids, dist, tri)
+    for i in range(args.warmup):
+        grca.grca_frame_launch(ctx.h, frame, mats[i], synth.deform_time(i), stream)
+        grca.grca_frame_synchronize(ctx.h, frame, stream)
+    torch.cuda.synchronize()
+    log("batched warmup done")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    stage_rows = []
+    launches_before = args.warmup
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        f = args.warmup + k
+        ev[k][0].record(stream)
+        grca.grca_frame_launch(ctx.h, frame, mats[f], synth.deform_time(f), stream)
+        ev[k][1].record(stream)
+        done = launches_before + k - (grca.FRAME_RING - 1)
+        if done >= launches_before:
+            stage_rows.append(grca.grca_frame_stage_times(ctx.h, frame, done))
+    torch.cuda.synchronize()
+    wall_batched = time.perf_counter() - t_start
+    for done in range(max(launches_before, launches_before + args.steps - (grca.FRAME_RING - 1)),
+                      launches_before + args.steps):
+        stage_rows.append(grca.grca_frame_stage_times(ctx.h, frame, done))
+    grca.grca_frame_synchronize(ctx.h, frame, stream)
+    stats = ctx.last_stats()
+    if stats["recasts"]:
+        log(f"WARNING: queue overflow during the timed frames ({stats['recasts']} recasts)")
+    b_ms = [a.elapsed_time(b) for a, b in ev]
+    stage_ms = {k: float(np.mean([r[k] for r in stage_rows])) for k in grca.STAGES}
+    log(f"batched: mean {np.mean(b_ms):.3f} ms p50 {pct(b_ms, 50):.3f} p99 {pct(b_ms, 99):.3f}; "
+        f"stages {stage_ms}; stats {stats}")
+    d_batched = dist.clone()
+    t_batched = tri.clone()
+    grca.grca_frame_destroy(frame)
+
+    # ---------------- plain: pose + one cast per sensor, no graph
+    p_ms = []
+    if not args.no_plain:
+        offs = np.cumsum([0] + sizes)
+        for i in range(args.warmup):
+            ctx.scene_pose(0, mats[i], synth.deform_time(i), stream)
+            for s in range(n_sens):
+                ctx.cast([ids[s]], dist[offs[s]:offs[s + 1]], tri[offs[s]:offs[s + 1]],
+                         stream=stream)
+            ctx.synchronize(stream)
+        pev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        for k in range(args.steps):
+            f = args.warmup + k
+            pev[k][0].record(stream)
+            ctx.scene_pose(0, mats[f], synth.deform_time(f), stream)
+            for s in range(n_sens):
+                ctx.cast([ids[s]], dist[offs[s]:offs[s + 1]], tri[offs[s]:offs[s + 1]],
+                         stream=stream)
+            pev[k][1].record(stream)
+        torch.cuda.synchronize()
+        ctx.synchronize(stream)
+        p_ms = [a.elapsed_time(b) for a, b in pev]
+        log(f"plain: mean {np.mean(p_ms):.3f} ms p50 {pct(p_ms, 50):.3f} p99 {pct(p_ms, 99):.3f}")
+        same = bool(torch.equal(dist, d_batched) and torch.equal(tri, t_batched))
+        log(f"plain == batched (last frame, bitwise): {same}")
+    else:
+        same = None
+
+    mean_b = float(np.mean(b_ms))
+    value = n_rays / (mean_b * 1e-3)
+
+    # ---------------- roofline of the dominant kernel
+    dom = max(("bounds", "expand", "isect"), key=lambda k: stage_ms[k])
+    if dom == "isect":
+        achieved = FLOPS_PER_RTIC * stats["rtic"] / (stage_ms["isect"] * 1e-3) / 1e12
+        roof = {"kernel": "isect_kernel", "bound": "alu", "achieved": achieved,
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                "traffic": None,
+                "work": f"{FLOPS_PER_RTIC} FP32 flops x {stats['rtic']} RTIC per launch"}
+    else:
+        # bounds/binning: per triangle 12 B of indices + its share of the unique
+        # vertices (12 B each) read once for all 8 origins, + 16 B per record
+        recs = stats["rect_items"] + stats["large_records"]
+        nbytes = 12 * sc.num_triangles + 12 * sc.num_vertices + 16 * recs
+        if dom == "expand":
+            nbytes = 16 * stats["large_records"] + 16 * stats["row_items"]
+        achieved = nbytes / (stage_ms[dom] * 1e-3) / 1e9
+        roof = {"kernel": f"{dom}_kernel", "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None, "work": f"{nbytes} algorithmic bytes per launch"}
+    rtic_s = stats["rtic"] / (stage_ms["isect"] * 1e-3)
+
+    # ---------------- CPU baseline: the oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        from tests import parity
+        v_or = oracle_pose(sc, args.warmup + args.steps - 1)
+        rng = np.random.default_rng(7)
+        tot_rays = 0
+        t_cpu = 0.0
+        threads = 0
+        bad = 0
+        counts = {}
+        offs = np.cumsum([0] + sizes)
+        d_np = d_batched.cpu().numpy()
+        t_np = t_batched.cpu().numpy().view(np.uint32)
+        for s_i, s in enumerate(wl.sensors):
+            rays = np.sort(rng.choice(sizes[s_i], args.cpu_rays, replace=False)).astype(np.uint32)
+            tc = time.perf_counter()
+            orc = O.cast(s, v_or, sc.indices, rays=rays)
+            t_cpu += time.perf_counter() - tc
+            threads = orc["threads"]
+            tot_rays += len(rays)
+            sel = offs[s_i] + rays.astype(np.int64)
+            rep = parity.check(s, v_or, sc.indices, orc, d_np[sel], t_np[sel])
+            bad += rep["counts"]["clean_mismatch"] + rep["counts"]["flagged_unacceptable"]
+            for k2, v2 in rep["counts"].items():
+                counts[k2] = counts.get(k2, 0) + v2
+        cpu = {"value": tot_rays / t_cpu, "unit": "rays/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"{args.cpu_rays} seeded rays per sensor x {n_sens} sensors of the last "
+                         f"timed frame, FP64 brute force over all {sc.num_triangles} triangles",
+               "seconds": t_cpu, "extrapolated_frame_s": t_cpu * n_rays / tot_rays,
+               "parity_on_sample": {"violations": int(bad), **counts}}
+        log(f"cpu oracle: {tot_rays} rays in {t_cpu:.1f}s on {threads} threads; parity {counts} bad={bad}")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": mean_b, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded generator; the paper's meshes are not available)",
+        "config": {"workload": "8 LiDARs 128x4096 (4x360, 4x180 deg) on a 20 m ring, "
+                               f"{sc.num_triangles} tris ({sc.n_dynamic_tris} dynamic: 20 rigid "
+                               "vehicle proxies with full-instant pose + 10 deforming grids), "
+                               f"range 0.05-{args.range_max:g} m; batched hipGraph frame",
+                   "rays_per_frame": n_rays, "triangles": sc.num_triangles,
+                   "dynamic_triangles": sc.n_dynamic_tris, "sensors": n_sens},
+        "frame_ms": {"batched": {"mean": mean_b, "p50": pct(b_ms, 50), "p99": pct(b_ms, 99)},
+                     "plain": ({"mean": float(np.mean(p_ms)), "p50": pct(p_ms, 50),
+                                "p99": pct(p_ms, 99)} if p_ms else None)},
+        "speedup_batched_vs_plain": (float(np.mean(p_ms)) / mean_b) if p_ms else None,
+        "plain_equals_batched": same,
+        "host_wall_ms_per_frame": wall_batched * 1e3 / args.steps,
+        "stage_ms": stage_ms,
+        "rtic_per_frame": stats["rtic"], "rtic_per_s": rtic_s,
+        "work": {k: stats[k] for k in ("pairs_tested", "rect_items", "large_records", "row_items")},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -92,6 +92,11 @@ const char* grca_last_error(const grca_context* ctx);
 grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id, const float* vertices_xyz,
                               uint32_t num_vertices, const uint32_t* indices,
                               uint32_t num_triangles, uint32_t flags, void* hip_stream);
+/* Copy the scene's current vertex positions (after any pose) into
+ * vertices_xyz_host (num_vertices * 3 FP32, xyz-interleaved).  Waits for
+ * `hip_stream`. */
+grca_status grca_scene_download(grca_context* ctx, uint32_t scene_id, float* vertices_xyz_host,
+                                void* hip_stream);
 /* Free scene `scene_id` and its dynamic-geometry tables. */
 grca_status grca_scene_release(grca_context* ctx, uint32_t scene_id);
 
@@ -230,6 +235,13 @@ grca_status grca_frame_launch(grca_frame* frame, const float* instance_matrices,
  * frame is re-run. */
 grca_status grca_frame_synchronize(grca_frame* frame, void* hip_stream);
 void grca_frame_destroy(grca_frame* frame);
+/* Device time of each stage of launch number `launch` of this frame (0 = the
+ * first grca_frame_launch), measured with HIP events recorded between the
+ * stages inside the graph: ms[0] pose, [1] key init, [2] bounds + binning,
+ * [3] large-class expansion, [4] intersection, [5] resolve.  Only the last
+ * GRCA_FRAME_RING launches are kept; waits for that launch. */
+#define GRCA_FRAME_RING 4
+grca_status grca_frame_stage_times(grca_frame* frame, uint64_t launch, float* ms6);
 
 /* ---- workspaces: concurrent casts (serving) ------------------------------------ */
 

@@ -93,6 +93,7 @@ def load() -> ctypes.CDLL:
         "grca_last_error": ([P], ctypes.c_char_p),
         "grca_scene_update": ([P, U32, P, U32, P, U32, U32, P], ctypes.c_int),
         "grca_scene_release": ([P, U32], ctypes.c_int),
+        "grca_scene_download": ([P, U32, P, P], ctypes.c_int),
         "grca_scene_set_rigid": ([P, U32, U32, P, P, P], ctypes.c_int),
         "grca_scene_set_deform": ([P, U32, U32, P, P, P, P], ctypes.c_int),
         "grca_scene_pose": ([P, U32, P, ctypes.c_double, U32, P], ctypes.c_int),
@@ -107,6 +108,7 @@ def load() -> ctypes.CDLL:
         "grca_frame_launch": ([P, P, ctypes.c_double, P], ctypes.c_int),
         "grca_frame_synchronize": ([P, P], ctypes.c_int),
         "grca_frame_destroy": ([P], None),
+        "grca_frame_stage_times": ([P, U64, P], ctypes.c_int),
         "grca_workspace_create": ([P, U64, U64, ctypes.POINTER(P), ctypes.POINTER(U64)],
                                   ctypes.c_int),
         "grca_workspace_destroy": ([P], None),
@@ -124,10 +126,11 @@ def load() -> ctypes.CDLL:
 def exported_symbols() -> list[str]:
     return [
         "grca_create", "grca_destroy", "grca_last_error", "grca_scene_update",
-        "grca_scene_release", "grca_scene_set_rigid", "grca_scene_set_deform", "grca_scene_pose",
+        "grca_scene_release", "grca_scene_download", "grca_scene_set_rigid", "grca_scene_set_deform", "grca_scene_pose",
         "grca_sensor_config", "grca_sensor_release", "grca_cast", "grca_synchronize",
         "grca_last_stats", "grca_get_options", "grca_set_options", "grca_frame_create",
         "grca_frame_launch", "grca_frame_synchronize", "grca_frame_destroy",
+        "grca_frame_stage_times",
         "grca_workspace_create", "grca_workspace_destroy", "grca_cast_ws",
         "grca_workspace_synchronize",
     ]
@@ -184,6 +187,12 @@ def grca_scene_update(ctx, scene_id, vertices, indices, flags=0, stream=None):
     nt = 0 if indices is None else (int(indices.shape[0]) if not dev else int(indices.numel() // 3))
     _check(ctx, load().grca_scene_update(ctx, scene_id, _ptr(vertices), nv, _ptr(indices), nt,
                                          flags, _stream(stream)))
+
+
+def grca_scene_download(ctx, scene_id, num_vertices: int, stream=None) -> np.ndarray:
+    out = np.empty((int(num_vertices), 3), np.float32)
+    _check(ctx, load().grca_scene_download(ctx, scene_id, _ptr(out), _stream(stream)))
+    return out
 
 
 def grca_scene_release(ctx, scene_id):
@@ -299,6 +308,16 @@ def grca_frame_destroy(frame):
     load().grca_frame_destroy(frame)
 
 
+STAGES = ("pose", "init", "bounds", "expand", "isect", "resolve")
+FRAME_RING = 4
+
+
+def grca_frame_stage_times(ctx, frame, launch: int) -> dict:
+    ms = np.zeros(6, np.float32)
+    _check(ctx, load().grca_frame_stage_times(frame, int(launch), _ptr(ms)))
+    return dict(zip(STAGES, (float(x) for x in ms)))
+
+
 def grca_workspace_create(ctx, max_rays, item_capacity):
     h = ctypes.c_void_p()
     nbytes = ctypes.c_uint64()
@@ -341,6 +360,9 @@ class Context:
 
     def scene_update(self, scene_id, vertices, indices, flags=0, stream=None):
         grca_scene_update(self.h, scene_id, vertices, indices, flags, stream)
+
+    def scene_download(self, scene_id, num_vertices, stream=None):
+        return grca_scene_download(self.h, scene_id, num_vertices, stream)
 
     def scene_release(self, scene_id):
         grca_scene_release(self.h, scene_id)

@@ -1,0 +1,252 @@
+"""Continuous-batching serving loop for LiDAR frame requests on one GPU.
+
+Each client keeps its scene (static + dynamic geometry) and its sensor rig
+resident in HBM for the whole run.  A frame request asks for one frame of one
+client: pose the client's dynamic geometry at the request's simulation time,
+then cast all of the client's sensors.
+
+The scheduler owns K slots; a slot is a library workspace (ray keys, work
+queues, counters) with its own HIP stream and output buffers.  Whenever a slot
+is free it takes every admissible queued request -- requests of different
+clients in one batch -- poses their scenes on the slot's stream and issues ONE
+multi-scene cast over all their sensors.  Requests that arrive while other
+batches are on the GPU join the next batch as soon as a slot and HBM budget
+free up; batches on different slots overlap on the device.
+
+Admission: a request's transient HBM is its rays x 16 B (key + outputs); a
+batch must fit its slot (max rays) and the global transient budget.  A client
+has at most one request in flight (its scene is re-posed per request).
+
+Latency is measured on the host clock from arrival to outputs ready.
+"""
+from __future__ import annotations
+
+import dataclasses
+import heapq
+import math
+import time
+
+import numpy as np
+
+from . import grca, synth
+
+BYTES_PER_RAY = 16  # 8 B key + 4 B distance + 4 B triangle id
+
+
+@dataclasses.dataclass
+class Client:
+    cid: int
+    workload: synth.Workload
+    scene_id: int
+    sensor_ids: list
+    rays: int
+    rate_hz: float
+
+
+@dataclasses.dataclass(order=True)
+class Request:
+    arrival: float
+    rid: int = dataclasses.field(compare=False)
+    cid: int = dataclasses.field(compare=False)
+    frame: int = dataclasses.field(compare=False)
+    done: float = dataclasses.field(default=math.nan, compare=False)
+    slot: int = dataclasses.field(default=-1, compare=False)
+    batch: int = dataclasses.field(default=-1, compare=False)
+    offset: int = dataclasses.field(default=0, compare=False)
+
+
+class Slot:
+    def __init__(self, torch, ctx, idx, max_rays, item_cap):
+        self.idx = idx
+        self.ws, self.bytes = grca.grca_workspace_create(ctx.h, max_rays, item_cap)
+        self.stream = torch.cuda.Stream()
+        self.dist = torch.empty(max_rays, dtype=torch.float32, device="cuda")
+        self.tri = torch.empty(max_rays, dtype=torch.int32, device="cuda")
+        self.max_rays = max_rays
+        self.event = None
+        self.reqs: list[Request] = []
+        self.rays = 0
+
+
+class Server:
+    def __init__(self, ctx: grca.Context, clients: list[Client], slots: int = 3,
+                 max_rays_per_slot: int = 16 << 20, item_cap: int = 64 << 20,
+                 transient_budget_bytes: int = 32 << 30, keep_outputs: set | None = None):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+        self.clients = {c.cid: c for c in clients}
+        self.slots = [Slot(torch, ctx, i, max_rays_per_slot, item_cap) for i in range(slots)]
+        self.budget = transient_budget_bytes
+        self.in_use = 0
+        self.busy_clients: set = set()
+        self.keep = keep_outputs or set()
+        self.outputs: dict = {}
+        self.batches = 0
+        self.admitted = 0
+        self.rejected = 0
+        self.max_batch = 0
+
+    # -------------------------------------------------------------- batching
+    def _launch(self, slot: Slot, reqs: list[Request], now: float):
+        ids, off = [], 0
+        for r in reqs:
+            c = self.clients[r.cid]
+            sc = c.workload.scene
+            mats = sc.instance_matrices(r.frame) if sc.rigid is not None else None
+            if sc.rigid is not None or sc.deform:
+                self.ctx.scene_pose(c.scene_id, mats, synth.deform_time(r.frame), slot.stream)
+            r.offset = off
+            r.slot = slot.idx
+            r.batch = self.batches
+            ids.extend(c.sensor_ids)
+            off += c.rays
+            self.busy_clients.add(r.cid)
+        grca.grca_cast_ws(self.ctx.h, slot.ws, ids, slot.dist, slot.tri, slot.stream)
+        ev = self.torch.cuda.Event()
+        ev.record(slot.stream)
+        slot.event = ev
+        slot.reqs = reqs
+        slot.rays = off
+        self.in_use += off * BYTES_PER_RAY
+        self.batches += 1
+        self.max_batch = max(self.max_batch, len(reqs))
+
+    def _complete(self, slot: Slot, now: float):
+        grca.grca_workspace_synchronize(self.ctx.h, slot.ws, slot.stream)
+        for r in slot.reqs:
+            r.done = now
+            self.busy_clients.discard(r.cid)
+            if r.rid in self.keep:
+                c = self.clients[r.cid]
+                d = slot.dist[r.offset:r.offset + c.rays].cpu().numpy().copy()
+                t = slot.tri[r.offset:r.offset + c.rays].cpu().numpy().view(np.uint32).copy()
+                self.outputs[r.rid] = (d, t)
+        self.in_use -= slot.rays * BYTES_PER_RAY
+        slot.event = None
+        slot.reqs = []
+        slot.rays = 0
+
+    def _admit(self, queue: list, slot: Slot) -> list:
+        """Take queued requests (oldest first) that fit the slot and budget."""
+        batch, rays, keep = [], 0, []
+        taken = set()
+        for r in sorted(queue):
+            c = self.clients[r.cid]
+            if r.cid in self.busy_clients or r.cid in taken:
+                keep.append(r)
+                continue
+            need = c.rays
+            if c.rays > slot.max_rays or c.rays * BYTES_PER_RAY > self.budget:
+                self.rejected += 1           # can never fit: reject
+                continue
+            if rays + need > slot.max_rays or \
+                    self.in_use + (rays + need) * BYTES_PER_RAY > self.budget:
+                keep.append(r)
+                continue
+            batch.append(r)
+            taken.add(r.cid)
+            rays += need
+        queue[:] = keep
+        self.admitted += len(batch)
+        return batch
+
+    # -------------------------------------------------------------- run loop
+    def run(self, requests: list[Request], time_scale: float = 1.0, log=None) -> dict:
+        """Serve `requests` (arrival times in seconds from start, real clock)."""
+        pending = list(sorted(requests))
+        queue: list[Request] = []
+        t0 = time.perf_counter()
+        nxt = 0
+        total = len(pending)
+        finished = 0
+        last_log = t0
+        while finished < total:
+            now = time.perf_counter() - t0
+            while nxt < total and pending[nxt].arrival * time_scale <= now:
+                queue.append(pending[nxt])
+                nxt += 1
+            for s in self.slots:
+                if s.event is not None and s.event.query():
+                    now = time.perf_counter() - t0
+                    finished += len(s.reqs)
+                    self._complete(s, now)
+            for s in self.slots:
+                if s.event is None and queue:
+                    b = self._admit(queue, s)
+                    if b:
+                        self._launch(s, b, now)
+            finished = sum(1 for r in pending if not math.isnan(r.done)) + self.rejected
+            if log and time.perf_counter() - last_log > 5.0:
+                last_log = time.perf_counter()
+                log(f"served {finished}/{total} queued {len(queue)} batches {self.batches}")
+            if all(s.event is None for s in self.slots) and not queue and nxt < total:
+                wait = pending[nxt].arrival * time_scale - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.002))
+            else:
+                time.sleep(0.0002)
+        wall = time.perf_counter() - t0
+        lat = np.array([(r.done - r.arrival * time_scale) * 1e3 for r in pending
+                        if not math.isnan(r.done)])
+        rays = sum(self.clients[r.cid].rays for r in pending if not math.isnan(r.done))
+        return {
+            "requests": total, "served": int(lat.size), "rejected": self.rejected,
+            "batches": self.batches, "max_batch": self.max_batch,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)) if lat.size else None,
+                           "p99": float(np.percentile(lat, 99)) if lat.size else None,
+                           "mean": float(lat.mean()) if lat.size else None},
+            "rays_per_s": rays / wall, "wall_s": wall,
+            "slot_bytes": [s.bytes for s in self.slots],
+        }
+
+    def close(self):
+        for s in self.slots:
+            if s.event is not None:
+                s.event.synchronize()
+            grca.grca_workspace_destroy(s.ws)
+        self.slots = []
+
+
+def make_clients(ctx: grca.Context, n_clients: int = 16, tri_scale: float = 1.0,
+                 seed_extra: int = 0, log=None) -> list[Client]:
+    """Build and upload the clients' resident scenes and rigs (config 5 recipe)."""
+    clients = []
+    next_sensor = 0
+    for c in range(n_clients):
+        wl = synth.client_workload(c, seed_extra=seed_extra, tri_scale=tri_scale)
+        ids = grca.load_workload(ctx, wl, scene_id=1000 + c, first_sensor_id=next_sensor, frame=0)
+        next_sensor += len(ids)
+        rays = sum(len(s["elevation"]) * s["rays_per_channel"] for s in wl.sensors)
+        rng = np.random.default_rng([synth.BASE_SEED + 5 + seed_extra, c, 99])
+        clients.append(Client(c, wl, 1000 + c, ids, rays, float(rng.uniform(10, 20))))
+        if log:
+            log(f"client {c}: {wl.scene.num_triangles} tris ({wl.scene.n_dynamic_tris} dyn), "
+                f"{len(ids)} sensors, {rays} rays, {clients[-1].rate_hz:.1f} Hz")
+    return clients
+
+
+def poisson_requests(clients: list[Client], duration_s: float, seed: int = 0) -> list[Request]:
+    rng = np.random.default_rng(seed)
+    reqs = []
+    rid = 0
+    for c in clients:
+        t = 0.0
+        frame = 0
+        while True:
+            t += rng.exponential(1.0 / c.rate_hz)
+            if t >= duration_s:
+                break
+            reqs.append(Request(t, rid, c.cid, frame))
+            rid += 1
+            frame += 1
+    return reqs
+
+
+def solo(ctx: grca.Context, client: Client, frame: int):
+    """The request's result when cast alone (for the batched == alone check)."""
+    sc = client.workload.scene
+    mats = sc.instance_matrices(frame) if sc.rigid is not None else None
+    if sc.rigid is not None or sc.deform:
+        ctx.scene_pose(client.scene_id, mats, synth.deform_time(frame))
+    return ctx.cast_host(client.sensor_ids, client.rays)

@@ -1,0 +1,244 @@
+"""GPU tests of the frame systems: device pose vs the oracle's pose, hipGraph
+frame replays vs eager casts, multi-scene casts, concurrent workspaces, device
+inputs, and sampled oracle parity at the larger workload sizes."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2605_10457_amd import grca, synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def small_dyn():
+    # config 4's recipe at 1% scale: ~220k tris, 20 rigid instances + 10 grids
+    return synth.config4(scale=0.01)
+
+
+def oracle_pose(scene, frame):
+    v = scene.vertices.copy()
+    if scene.rigid is not None:
+        mats = scene.instance_matrices(frame)
+        for i, (s, c) in enumerate(zip(scene.rigid.vertex_start, scene.rigid.vertex_count)):
+            v[s:s + c] = O.pose_rigid(scene.vertices[s:s + c], mats[i])
+    off = 0
+    for g in scene.deform:
+        s, c = g.vertex_start, g.vertex_count
+        v[s:s + c] = O.pose_deform(scene.vertices[s:s + c], scene.deform_normals[off:off + c],
+                                   scene.deform_phase[off:off + c], g.amplitude, g.omega,
+                                   synth.deform_time(frame))
+        off += c
+    return v
+
+
+def _sample_parity(sensors, v, f, d, t, per_sensor, seed, label):
+    rng = np.random.default_rng(seed)
+    off = 0
+    tot = {}
+    for s in sensors:
+        n = len(s["elevation"]) * s["rays_per_channel"]
+        rays = np.sort(rng.choice(n, min(per_sensor, n), replace=False)).astype(np.uint32)
+        orc = O.cast(s, v, f, rays=rays)
+        sel = off + rays.astype(np.int64)
+        rep = parity.check(s, v, f, orc, d[sel], t[sel])
+        parity.assert_parity(rep, label)
+        for k, x in rep["counts"].items():
+            tot[k] = tot.get(k, 0) + x
+        off += n
+    print(label, tot, flush=True)
+    return tot
+
+
+def test_pose_matches_oracle(torch, small_dyn):
+    sc = small_dyn.scene
+    ctx = grca.Context(0)
+    try:
+        for frame in (0, 7):
+            _say(f"pose frame {frame}: {sc.num_vertices} vertices")
+            grca.load_workload(ctx, small_dyn, frame=frame)
+            got = ctx.scene_download(0, sc.num_vertices)
+            ref = oracle_pose(sc, frame)
+            diff = got.view(np.uint32).astype(np.int64) - ref.view(np.uint32).astype(np.int64)
+            n_bad = int(np.count_nonzero(diff))
+            assert np.max(np.abs(diff)) <= 1, "pose differs by more than one FP32 ulp"
+            assert n_bad <= 1e-5 * diff.size, n_bad
+            assert not np.array_equal(got, sc.vertices)   # something moved
+    finally:
+        ctx.close()
+
+
+def test_frame_replays_match_eager_and_oracle(torch, small_dyn):
+    sc = small_dyn.scene
+    ctx = grca.Context(0)
+    try:
+        ctx.set_options(item_capacity=16 << 20, large_capacity=1 << 20)
+        ids = grca.load_workload(ctx, small_dyn, frame=0)
+        n = sum(len(s["elevation"]) * s["rays_per_channel"] for s in small_dyn.sensors)
+        dist = torch.empty(n, dtype=torch.float32, device="cuda")
+        tri = torch.empty(n, dtype=torch.int32, device="cuda")
+        st = torch.cuda.current_stream()
+        fr = grca.grca_frame_create(ctx.h, 0, ids, dist, tri)
+        try:
+            for frame in range(5):
+                _say(f"frame replay {frame}")
+                grca.grca_frame_launch(ctx.h, fr, sc.instance_matrices(frame),
+                                       synth.deform_time(frame), st)
+                grca.grca_frame_synchronize(ctx.h, fr, st)
+                d_f = dist.cpu().numpy().copy()
+                t_f = tri.cpu().numpy().view(np.uint32).copy()
+                # eager work between replays: pose + cast through the plain path
+                ctx.scene_pose(0, sc.instance_matrices(frame), synth.deform_time(frame), st)
+                d_e, t_e = ctx.cast_host(ids, n)
+                assert np.array_equal(t_f, t_e), f"frame {frame}: graph != eager"
+                assert np.array_equal(d_f.view(np.uint32), d_e.view(np.uint32))
+                times = grca.grca_frame_stage_times(ctx.h, fr, frame)
+                assert all(v >= 0 for v in times.values())
+                if frame in (0, 4):
+                    v_or = oracle_pose(sc, frame)
+                    _sample_parity(small_dyn.sensors, v_or, sc.indices, d_f, t_f, 24, frame,
+                                   f"frame{frame}")
+        finally:
+            grca.grca_frame_destroy(fr)
+    finally:
+        ctx.close()
+
+
+def test_multi_scene_cast_equals_separate(torch):
+    _say("one cast over sensors of two scenes")
+    a = synth.config1()
+    vb, fb = synth.small_random_scene(3, n_tris=200, spread=10.0)
+    ctx = grca.Context(0)
+    try:
+        ctx.scene_update(1, a.scene.vertices, a.scene.indices)
+        ctx.scene_update(2, vb, fb)
+        sa = a.sensors[0]
+        sb = synth.sensor((0.5, 0.5, 0.5), 1.0, synth.elevations_full_sphere(16), 64, 180.0, 0.05, 50.0)
+        ctx.sensor_config(5, sa, 1)
+        ctx.sensor_config(6, sb, 2)
+        ctx.sensor_config(7, dict(sa, origin=np.array([3.0, 1.0, 2.0], np.float32)), 1)
+        na, nb = 32 * 512, 16 * 64
+        d, t = ctx.cast_host([6, 5, 7], nb + 2 * na)
+        d6, t6 = ctx.cast_host([6], nb)
+        d5, t5 = ctx.cast_host([5], na)
+        d7, t7 = ctx.cast_host([7], na)
+        assert np.array_equal(t[:nb], t6) and np.array_equal(t[nb:nb + na], t5)
+        assert np.array_equal(t[nb + na:], t7)
+        assert np.array_equal(d.view(np.uint32), np.concatenate([d6, d5, d7]).view(np.uint32))
+    finally:
+        ctx.close()
+
+
+def test_workspaces_on_two_streams(torch):
+    _say("two workspaces, two streams, overlapping casts")
+    a = synth.config1()
+    ctx = grca.Context(0)
+    try:
+        ctx.scene_update(0, a.scene.vertices, a.scene.indices)
+        s0 = a.sensors[0]
+        s1 = dict(s0, origin=np.array([5.0, -3.0, 2.5], np.float32))
+        ctx.sensor_config(0, s0, 0)
+        ctx.sensor_config(1, s1, 0)
+        n = 32 * 512
+        ref0 = ctx.cast_host([0], n)
+        ref1 = ctx.cast_host([1], n)
+        w0, b0 = grca.grca_workspace_create(ctx.h, n, 1 << 18)
+        w1, b1 = grca.grca_workspace_create(ctx.h, n, 1 << 18)
+        assert b0 > 0
+        st0, st1 = torch.cuda.Stream(), torch.cuda.Stream()
+        outs = [(torch.empty(n, dtype=torch.float32, device="cuda"),
+                 torch.empty(n, dtype=torch.int32, device="cuda")) for _ in range(2)]
+        for rep in range(3):
+            grca.grca_cast_ws(ctx.h, w0, [0], outs[0][0], outs[0][1], st0)
+            grca.grca_cast_ws(ctx.h, w1, [1], outs[1][0], outs[1][1], st1)
+            grca.grca_workspace_synchronize(ctx.h, w0, st0)
+            grca.grca_workspace_synchronize(ctx.h, w1, st1)
+            torch.cuda.synchronize()
+            for (dd, tt), (rd, rt) in zip(outs, (ref0, ref1)):
+                assert np.array_equal(tt.cpu().numpy().view(np.uint32), rt)
+                assert np.array_equal(dd.cpu().numpy().view(np.uint32), rd.view(np.uint32))
+        with pytest.raises(grca.GrcaError) as e:
+            grca.grca_cast_ws(ctx.h, w0, [0, 1], outs[0][0], outs[0][1], st0)
+        assert e.value.status == grca.GRCA_ERR_CAPACITY
+        grca.grca_workspace_destroy(w0)
+        grca.grca_workspace_destroy(w1)
+    finally:
+        ctx.close()
+
+
+def test_device_inputs(torch):
+    _say("scene from device tensors, and device-side index validation")
+    a = synth.config1()
+    ctx = grca.Context(0)
+    try:
+        ctx.scene_update(0, a.scene.vertices, a.scene.indices)
+        ctx.sensor_config(0, a.sensors[0], 0)
+        ref = ctx.cast_host([0], 32 * 512)
+        v = torch.from_numpy(a.scene.vertices.copy()).cuda()
+        f = torch.from_numpy(a.scene.indices.astype(np.int32)).cuda()
+        ctx.scene_update(3, v, f)
+        ctx.sensor_config(1, a.sensors[0], 3)
+        got = ctx.cast_host([1], 32 * 512)
+        assert np.array_equal(got[1], ref[1])
+        bad = f.clone()
+        bad[5, 1] = a.scene.num_vertices + 7
+        with pytest.raises(grca.GrcaError) as e:
+            ctx.scene_update(4, v, bad)
+        assert e.value.status == grca.GRCA_ERR_INVALID_ARG
+    finally:
+        ctx.close()
+
+
+def test_config2_subset_parity(torch):
+    wl = synth.config2()
+    sc = wl.scene
+    ctx = grca.Context(0)
+    try:
+        for frame in (0, 50):
+            _say(f"config2 frame {frame}: {sc.num_triangles} tris, 128x4096 rays")
+            ids = grca.load_workload(ctx, wl, frame=frame)
+            n = 128 * 4096
+            d, t = ctx.cast_host(ids, n)
+            v_or = oracle_pose(sc, frame)
+            _sample_parity(wl.sensors, v_or, sc.indices, d, t, 400, frame, f"config2-f{frame}")
+            print("stats", ctx.last_stats(), flush=True)
+    finally:
+        ctx.close()
+
+
+def test_config4_sample_parity_and_all_pairs(torch):
+    wl = synth.config4()
+    sc = wl.scene
+    ctx = grca.Context(0)
+    try:
+        _say(f"config4 full: {sc.num_triangles} tris, 8 x 128x4096 rays")
+        ctx.set_options(item_capacity=96 << 20, large_capacity=8 << 20)
+        ids = grca.load_workload(ctx, wl, frame=3)
+        n = sum(len(s["elevation"]) * s["rays_per_channel"] for s in wl.sensors)
+        d, t = ctx.cast_host(ids, n)
+        st = ctx.last_stats()
+        print("config4 stats", st, flush=True)
+        assert st["recasts"] == 0
+        v_or = oracle_pose(sc, 3)
+        _sample_parity(wl.sensors, v_or, sc.indices, d, t, 12, 3, "config4")
+        _say("config4: culled vs all-pairs, bitwise, on sensor 4 (180 deg)")
+        n4 = 128 * 4096
+        d4, t4 = ctx.cast_host([ids[4]], n4, grca.GRCA_CAST_ALL_PAIRS)
+        off = 4 * n4
+        assert np.array_equal(t4, t[off:off + n4])
+        assert np.array_equal(d4.view(np.uint32), d[off:off + n4].view(np.uint32))
+    finally:
+        ctx.close()
