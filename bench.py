@@ -63,6 +63,48 @@ def oracle_pose(scene, frame):
     return v
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("grca_kernels.hip", "grca_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2605_10457_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_summary(paths) -> str:
+    """Per-kernel mean of each counter over the dispatches of rocprofv3 CSVs."""
+    import csv
+    acc = {}
+    for p in paths:
+        with open(p) as fh:
+            for row in csv.DictReader(fh):
+                name = row.get("Kernel_Name", "?").split("(")[0].split("<")[0]
+                key = (name, row.get("Counter_Name", "?"))
+                acc.setdefault(key, []).append(float(row.get("Counter_Value", "nan")))
+    lines = ["| kernel | counter | dispatches | mean per dispatch |", "|---|---|---|---|"]
+    for (k, c), v in sorted(acc.items()):
+        lines.append(f"| {k} | {c} | {len(v)} | {np.mean(v):.6g} |")
+    return "\n".join(lines)
+
+
+def load_traffic(kernel: str):
+    """Measured HBM bytes per launch of `kernel` from profiles/, if the kernel
+    sources are unchanged since the counters were taken; else None."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_config4.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for ln in open(path):
+        if ":" in ln and not ln.startswith("#"):
+            k, v = ln.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    v = kv.get(f"{kernel}_bytes_per_launch")
+    return float(v) if v else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,7 +116,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=16, help="oracle rays per sensor")
     ap.add_argument("--tuning", default=None, help="JSON file of grca options")
+    ap.add_argument("--opt", action="append", default=[], help="option override k=v")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 1 GiB device copy first (scale reference for PMC byte counters)")
+    ap.add_argument("--pmc-summary", nargs="+", default=None,
+                    help="summarise rocprofv3 counter_collection.csv files and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(pmc_summary(args.pmc_summary))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -103,12 +153,22 @@ def main():
     opts = {"item_capacity": 96 << 20, "large_capacity": 8 << 20}
     if args.tuning and os.path.exists(args.tuning):
         opts.update(json.load(open(args.tuning)).get("options", {}))
+    for kv in args.opt:
+        k, v = kv.split("=")
+        opts[k] = int(v)
     ctx.set_options(**opts)
     ids = grca.load_workload(ctx, wl, scene_id=0, frame=0, stream=stream)
     torch.cuda.synchronize()
     dist = torch.empty(n_rays, dtype=torch.float32, device=dev)
     tri = torch.empty(n_rays, dtype=torch.int32, device=dev)
     log(f"scene resident; options {ctx.get_options()}")
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del a, b
 
     # ---------------- batched: hipGraph frame
     frame = grca.grca_frame_create(ctx.h, 0, ids, dist, tri)
@@ -187,7 +247,7 @@ def main():
         achieved = FLOPS_PER_RTIC * stats["rtic"] / (stage_ms["isect"] * 1e-3) / 1e12
         roof = {"kernel": "isect_kernel", "bound": "alu", "achieved": achieved,
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                "traffic": None,
+                "traffic": load_traffic("isect_kernel"),
                 "work": f"{FLOPS_PER_RTIC} FP32 flops x {stats['rtic']} RTIC per launch"}
     else:
         # bounds/binning: per triangle 12 B of indices + its share of the unique
@@ -199,7 +259,8 @@ def main():
         achieved = nbytes / (stage_ms[dom] * 1e-3) / 1e9
         roof = {"kernel": f"{dom}_kernel", "bound": "hbm", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": None, "work": f"{nbytes} algorithmic bytes per launch"}
+                "traffic": load_traffic(f"{dom}_kernel"),
+                "work": f"{nbytes} algorithmic bytes per launch"}
     rtic_s = stats["rtic"] / (stage_ms["isect"] * 1e-3)
 
     # ---------------- CPU baseline: the oracle on a bounded sample

@@ -211,6 +211,9 @@ typedef struct {
   uint32_t row_chunk;        /* max rays per per-channel work item (W), 1..65535       */
   uint32_t bounds_block;     /* threads per block of the bounds pass: 64..1024, x64    */
   uint32_t persist_waves_cu; /* resident waves per CU of the persistent kernels, 1..32 */
+  uint32_t group_cull;       /* 1: cull each wave's 64 triangles per sensor with one
+                                bounding-sphere test first (the group-level cone test
+                                of section 8, "Future Work"); never changes results */
   uint64_t item_capacity;    /* initial work-queue capacity (items)                    */
   uint64_t large_capacity;   /* initial large-record queue capacity                    */
 } grca_options;

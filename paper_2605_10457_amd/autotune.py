@@ -26,8 +26,10 @@ SPACE = {
     "row_chunk": [64, 128, 256, 512, 1024, 2048],
     "bounds_block": [128, 256, 512],
     "persist_waves_cu": [4, 8, 16, 24, 32],
+    "group_cull": [0, 1],
 }
-ORDER = ["small_channels", "small_rays", "row_chunk", "bounds_block", "persist_waves_cu"]
+ORDER = ["group_cull", "small_channels", "small_rays", "row_chunk", "bounds_block",
+         "persist_waves_cu"]
 TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
 
 

@@ -392,7 +392,7 @@ grca_status enqueue_kernels(grca_context* ctx, grca_workspace* ws, uint32_t slot
   } else {
     HIPCHK(launch_bounds(dscenes, (uint32_t)P.scenes.size(), P.total_blocks, o.bounds_block,
                          dsens, o.small_channels, o.small_rays, ws->items, icap, ws->large, lcap,
-                         ws->cnt, st));
+                         ws->cnt, o.group_cull, st));
     const uint32_t pb = persist_blocks(ctx);
     HIPCHK(launch_expand(dscenes, dsens, ws->large, ws->items, icap, lcap, o.row_chunk, ws->cnt,
                          pb, st));
@@ -490,6 +490,7 @@ extern "C" grca_status grca_create(int hip_device, grca_context** out) {
   ctx->opt.row_chunk = 256;
   ctx->opt.bounds_block = 256;
   ctx->opt.persist_waves_cu = 16;
+  ctx->opt.group_cull = 1;
   ctx->opt.item_capacity = 1u << 20;
   ctx->opt.large_capacity = 1u << 16;
   ctx->def_ws = new grca_workspace();
@@ -1082,6 +1083,7 @@ extern "C" grca_status grca_set_options(grca_context* ctx, const grca_options* o
   const uint32_t b = o->bounds_block;
   if (b != 64 && b != 128 && b != 256 && b != 512 && b != 1024)
     return fail(ctx, GRCA_ERR_INVALID_ARG, "bounds_block must be 64, 128, 256, 512 or 1024");
+  if (o->group_cull > 1) return fail(ctx, GRCA_ERR_INVALID_ARG, "group_cull must be 0 or 1");
   if (o->persist_waves_cu < 1 || o->persist_waves_cu > 32)
     return fail(ctx, GRCA_ERR_INVALID_ARG, "persist_waves_cu outside [1, 32]");
   if (o->item_capacity < 64 || o->item_capacity > 0xFFFFFFF0ull ||
@@ -1176,7 +1178,7 @@ grca_status capture_one(grca_context* ctx, grca_frame* fr, int inst, const Plan&
   if (e == hipSuccess && erc == GRCA_OK)
     e = launch_bounds(ws->dscenes, (uint32_t)P.scenes.size(), P.total_blocks, o.bounds_block,
                       ws->dsens, o.small_channels, o.small_rays, ws->items, icap, ws->large,
-                      lcap, ws->cnt, st);
+                      lcap, ws->cnt, o.group_cull, st);
   mark(3);
   if (e == hipSuccess && erc == GRCA_OK)
     e = launch_expand(ws->dscenes, ws->dsens, ws->large, ws->items, icap, lcap, o.row_chunk,

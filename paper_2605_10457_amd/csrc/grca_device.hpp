@@ -127,17 +127,17 @@ __device__ inline bool make_statics(float ax, float ay, float az_, float bx, flo
     const double c2 = P[k][0] * E[1] - P[k][1] * E[0];
     const double l2 = c0 * c0 + c1 * c1 + c2 * c2;
     if (!(l2 > 0.0)) return false;
-    const double il = sg / sqrt(l2);
+    const double il = sg * rsqrt(l2);
     n[k][0] = c0 * il;
     n[k][1] = c1 * il;
     n[k][2] = c2 * il;
   }
-  const double iN = sg / sqrt(nN2);
+  const double iN = sg * rsqrt(nN2);
   st.n0x = (float)n[0][0]; st.n0y = (float)n[0][1]; st.n0z = (float)n[0][2];
   st.n1x = (float)n[1][0]; st.n1y = (float)n[1][1]; st.n1z = (float)n[1][2];
   st.n2x = (float)n[2][0]; st.n2y = (float)n[2][1]; st.n2z = (float)n[2][2];
   st.Nx = (float)(N[0] * iN); st.Ny = (float)(N[1] * iN); st.Nz = (float)(N[2] * iN);
-  st.h = (float)(g * sg / sqrt(nN2));
+  st.h = (float)(g * iN);
   st.pad0 = st.pad1 = st.pad2 = 0.0f;
   if (nrm_out) {
 #pragma unroll

@@ -141,8 +141,9 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
       const float ex = x[k] - cx, ey = y[k] - cy, ez = z[k] - cz;
       rc2 = fmaxf(rc2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
     }
-    const float dc = sqrtf(fmaf(cx, cx, fmaf(cy, cy, cz * cz)));
-    if (dc - sqrtf(rc2) * 1.0001f > dmax * (1.0f + 1e-5f) + 1e-6f) return false;
+    // |c| - r_c > D_max  <=>  |c|^2 > (D_max + r_c)^2 (both sides non-negative)
+    const float reach = dmax * (1.0f + 1e-5f) + 1e-6f + sqrtf(rc2) * 1.0001f;
+    if (fmaf(cx, cx, fmaf(cy, cy, cz * cz)) > reach * reach * (1.0f + 1e-5f)) return false;
   }
   const float r2min = fminf(r2[0], fminf(r2[1], r2[2]));
   float s_lo, s_hi;
@@ -267,6 +268,58 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
   return true;
 }
 
+// Group-level culling (the "group" extension of the cone-triangle test to a
+// whole group of triangles): the wave's 64 consecutive triangles are bounded
+// by a sphere (centre c, radius rad, wave-uniform).  Returns true when no
+// ray of sensor `s` can reach anything inside the sphere: it lies beyond
+// range_max, or the band of elevations it subtends holds no channel, or (on
+// a partial-FOV sensor) the azimuths it subtends miss the field of view.
+// Conservative: any doubt (sphere near the origin, wide angles) keeps the group.
+__device__ inline bool group_culled(float cx, float cy, float cz, float rad, const DevSensor& s) {
+  const float dx = cx - s.o[0], dy = cy - s.o[1], dz = cz - s.o[2];
+  const float lf = fmaf(dx, s.f[0], fmaf(dy, s.f[1], dz * s.f[2]));
+  const float lr = fmaf(dx, s.r[0], fmaf(dy, s.r[1], dz * s.r[2]));
+  const float lu = fmaf(dx, s.u[0], fmaf(dy, s.u[1], dz * s.u[2]));
+  const float h2 = fmaf(lf, lf, lr * lr);
+  const float D2 = fmaf(lu, lu, h2);
+  const float r = rad * 1.0001f + 1e-6f;
+  if (D2 <= 4.0f * r * r) return false;  // sphere within 30 deg of the origin: keep
+  const float D = sqrtf(D2);
+  if (D - r > s.dmax * (1.0f + 1e-5f) + 1e-6f) return true;
+  const float invD = 1.0f / D;
+  const float sa = r * invD;                    // sin(alpha), alpha <= 30 deg
+  const float ca = sqrtf(fmaxf(1.0f - sa * sa, 0.0f));
+  const float hc = sqrtf(h2);
+  const float sc = lu * invD, cc = hc * invD;   // sin, cos of the centre's elevation
+  float s_hi = sc >= ca ? 1.0f : fmaf(sc, ca, cc * sa);
+  float s_lo = -sc >= ca ? -1.0f : fmaf(sc, ca, -cc * sa);
+  s_lo -= 1e-5f + ETA_SIN;
+  s_hi += 1e-5f + ETA_SIN;
+  const uint32_t j = chan_search(s, s_lo, false);
+  if (j >= s.gamma || s.sin_tab[j] > s_hi) return true;
+  if (!s.wrap && hc > 2.0f * r) {
+    const float beta = asinf(fminf(r / hc, 1.0f)) + 1e-4f;
+    const float az = atan2f(lr, lf);
+    const float half = 0.5f * (float)(s.chi - 1) / s.inv_dtheta;
+    const float mid = s.theta_start + half;
+    float d = az - mid;
+    d -= TWO_PI_F * floorf((d + PI_F) * (1.0f / TWO_PI_F));
+    if (fabsf(d) > half + beta + 1e-4f) return true;
+  }
+  return false;
+}
+
+__device__ inline float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
   // Blocks are handed to the 8 XCDs round robin; give each XCD a contiguous
   // run of triangles so that shared vertices stay in one XCD's L2.
@@ -279,7 +332,8 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void bounds_kernel(
     const DevScene* __restrict__ scenes, uint32_t nscenes, const DevSensor* __restrict__ sens,
     uint32_t small_c, uint32_t small_r, Item* __restrict__ items, uint32_t item_cap,
-    Item* __restrict__ large, uint32_t large_cap, Counters* __restrict__ cnt) {
+    Item* __restrict__ large, uint32_t large_cap, Counters* __restrict__ cnt,
+    uint32_t group_cull) {
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
   uint32_t sc = 0;
   while (sc + 1 < nscenes && b >= scenes[sc + 1].block_start) ++sc;
@@ -293,8 +347,33 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
     vx[1] = S.x[i1]; vy[1] = S.y[i1]; vz[1] = S.z[i1];
     vx[2] = S.x[i2]; vy[2] = S.y[i2]; vz[2] = S.z[i2];
   }
+  // bounding sphere of the wave's triangles (AABB centre, max vertex distance)
+  float gcx = 0.0f, gcy = 0.0f, gcz = 0.0f, grad = 0.0f;
+  bool any_active = __ballot(active) != 0ull;
+  if (group_cull && any_active) {
+    const float big = 3.0e38f;
+    const float mnx = wave_min(active ? fminf(vx[0], fminf(vx[1], vx[2])) : big);
+    const float mny = wave_min(active ? fminf(vy[0], fminf(vy[1], vy[2])) : big);
+    const float mnz = wave_min(active ? fminf(vz[0], fminf(vz[1], vz[2])) : big);
+    const float mxx = wave_max(active ? fmaxf(vx[0], fmaxf(vx[1], vx[2])) : -big);
+    const float mxy = wave_max(active ? fmaxf(vy[0], fmaxf(vy[1], vy[2])) : -big);
+    const float mxz = wave_max(active ? fmaxf(vz[0], fmaxf(vz[1], vz[2])) : -big);
+    gcx = 0.5f * (mnx + mxx);
+    gcy = 0.5f * (mny + mxy);
+    gcz = 0.5f * (mnz + mxz);
+    float r2 = 0.0f;
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float ex = vx[k] - gcx, ey = vy[k] - gcy, ez = vz[k] - gcz;
+        r2 = fmaxf(r2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+      }
+    }
+    grad = sqrtf(wave_max(r2));
+  }
   for (uint32_t n = S.sensor_begin; n < S.sensor_end; ++n) {
     const DevSensor& s = sens[n];
+    if (!any_active || (group_cull && group_culled(gcx, gcy, gcz, grad, s))) continue;
     Span sp;
     const bool ok = active && span_of(vx, vy, vz, s, small_c, small_r, sp);
     const uint32_t chan = ok ? (sp.c_from | (sp.c_count << 16)) : 0u;
@@ -734,12 +813,13 @@ hipError_t launch_init(unsigned long long* keys, uint32_t n, Counters* cnt, hipS
 hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t total_blocks,
                          uint32_t block, const DevSensor* sens, uint32_t small_c,
                          uint32_t small_r, Item* items, uint32_t item_cap, Item* large,
-                         uint32_t large_cap, Counters* cnt, hipStream_t st) {
+                         uint32_t large_cap, Counters* cnt, uint32_t group_cull, hipStream_t st) {
   if (total_blocks == 0) return hipSuccess;
 #define GRCA_BOUNDS_CASE(B)                                                                   \
   case B:                                                                                     \
     hipLaunchKernelGGL(bounds_kernel<B>, dim3(total_blocks), dim3(B), 0, st, scenes, nscenes, \
-                       sens, small_c, small_r, items, item_cap, large, large_cap, cnt);       \
+                       sens, small_c, small_r, items, item_cap, large, large_cap, cnt,        \
+                       group_cull);                                                           \
     break;
   switch (block) {
     GRCA_BOUNDS_CASE(64)

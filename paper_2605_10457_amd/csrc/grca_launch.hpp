@@ -28,7 +28,8 @@ hipError_t launch_init(unsigned long long* keys, uint32_t n, Counters* cnt, hipS
 hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t total_blocks,
                          uint32_t block, const DevSensor* sens, uint32_t small_c,
                          uint32_t small_r, Item* items, uint32_t item_cap, Item* large,
-                         uint32_t large_cap, Counters* cnt, hipStream_t st);
+                         uint32_t large_cap, Counters* cnt, uint32_t group_cull,
+                         hipStream_t st);
 hipError_t launch_expand(const DevScene* scenes, const DevSensor* sens, const Item* large,
                          Item* items, uint32_t item_cap, uint32_t large_cap, uint32_t row_chunk,
                          Counters* cnt, uint32_t nblocks, hipStream_t st);

@@ -22,7 +22,6 @@ Latency is measured on the host clock from arrival to outputs ready.
 from __future__ import annotations
 
 import dataclasses
-import heapq
 import math
 import time
 
@@ -53,6 +52,33 @@ class Request:
     slot: int = dataclasses.field(default=-1, compare=False)
     batch: int = dataclasses.field(default=-1, compare=False)
     offset: int = dataclasses.field(default=0, compare=False)
+
+
+def plan_batch(queue, client_rays: dict, busy: set, slot_max_rays: int, budget_bytes: int,
+               in_use_bytes: int):
+    """Admission for one free slot: oldest requests first, at most one per
+    client, skipping clients with a request in flight; a request joins the
+    batch while the batch fits the slot's ray capacity and the transient HBM
+    budget.  Requests that can never fit (larger than a slot or the whole
+    budget) are rejected.  Returns (batch, still_queued, rejected)."""
+    batch, keep, rejected = [], [], []
+    taken = set()
+    rays = 0
+    for r in sorted(queue):
+        need = client_rays[r.cid]
+        if need > slot_max_rays or need * BYTES_PER_RAY > budget_bytes:
+            rejected.append(r)
+            continue
+        if r.cid in busy or r.cid in taken:
+            keep.append(r)
+            continue
+        if rays + need > slot_max_rays or in_use_bytes + (rays + need) * BYTES_PER_RAY > budget_bytes:
+            keep.append(r)
+            continue
+        batch.append(r)
+        taken.add(r.cid)
+        rays += need
+    return batch, keep, rejected
 
 
 class Slot:
@@ -128,26 +154,11 @@ class Server:
         slot.rays = 0
 
     def _admit(self, queue: list, slot: Slot) -> list:
-        """Take queued requests (oldest first) that fit the slot and budget."""
-        batch, rays, keep = [], 0, []
-        taken = set()
-        for r in sorted(queue):
-            c = self.clients[r.cid]
-            if r.cid in self.busy_clients or r.cid in taken:
-                keep.append(r)
-                continue
-            need = c.rays
-            if c.rays > slot.max_rays or c.rays * BYTES_PER_RAY > self.budget:
-                self.rejected += 1           # can never fit: reject
-                continue
-            if rays + need > slot.max_rays or \
-                    self.in_use + (rays + need) * BYTES_PER_RAY > self.budget:
-                keep.append(r)
-                continue
-            batch.append(r)
-            taken.add(r.cid)
-            rays += need
+        batch, keep, rejected = plan_batch(queue, {c: x.rays for c, x in self.clients.items()},
+                                           self.busy_clients, slot.max_rays, self.budget,
+                                           self.in_use)
         queue[:] = keep
+        self.rejected += len(rejected)
         self.admitted += len(batch)
         return batch
 
@@ -159,27 +170,25 @@ class Server:
         t0 = time.perf_counter()
         nxt = 0
         total = len(pending)
-        finished = 0
+        completed = 0
         last_log = t0
-        while finished < total:
+        while completed + self.rejected < total:
             now = time.perf_counter() - t0
             while nxt < total and pending[nxt].arrival * time_scale <= now:
                 queue.append(pending[nxt])
                 nxt += 1
             for s in self.slots:
                 if s.event is not None and s.event.query():
-                    now = time.perf_counter() - t0
-                    finished += len(s.reqs)
-                    self._complete(s, now)
+                    completed += len(s.reqs)
+                    self._complete(s, time.perf_counter() - t0)
             for s in self.slots:
                 if s.event is None and queue:
                     b = self._admit(queue, s)
                     if b:
                         self._launch(s, b, now)
-            finished = sum(1 for r in pending if not math.isnan(r.done)) + self.rejected
             if log and time.perf_counter() - last_log > 5.0:
                 last_log = time.perf_counter()
-                log(f"served {finished}/{total} queued {len(queue)} batches {self.batches}")
+                log(f"served {completed}/{total} queued {len(queue)} batches {self.batches}")
             if all(s.event is None for s in self.slots) and not queue and nxt < total:
                 wait = pending[nxt].arrival * time_scale - (time.perf_counter() - t0)
                 if wait > 0:
