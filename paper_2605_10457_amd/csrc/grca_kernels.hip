@@ -116,7 +116,7 @@ __device__ inline uint32_t chan_search(const DevSensor& s, float x, bool strict)
 // Returns false when no ray of the sensor can reach the triangle.
 __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const float (&vz)[3],
                                const DevSensor& s, uint32_t small_c, uint32_t small_r,
-                               Span& sp) {
+                               bool need_range, bool need_pole, Span& sp) {
   float x[3], y[3], z[3], r2[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -128,10 +128,10 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
   }
   // range prefilter: the triangle lies inside the blind ball (convex), or its
   // bounding sphere lies beyond range_max.
-  const float r2max = fmaxf(r2[0], fmaxf(r2[1], r2[2]));
   const float dmin = s.dmin, dmax = s.dmax;
-  if (r2max < dmin * dmin * (1.0f - 1e-5f)) return false;
-  {
+  if (need_range) {
+    const float r2max = fmaxf(r2[0], fmaxf(r2[1], r2[2]));
+    if (r2max < dmin * dmin * (1.0f - 1e-5f)) return false;
     const float cx = (x[0] + x[1] + x[2]) * (1.0f / 3.0f);
     const float cy = (y[0] + y[1] + y[2]) * (1.0f / 3.0f);
     const float cz = (z[0] + z[1] + z[2]) * (1.0f / 3.0f);
@@ -174,6 +174,7 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
     if (s_hi > 0.0f) s_hi = fminf(s_hi * kb, 1.0f);
     if (s_lo < 0.0f) s_lo = fmaxf(s_lo * kb, -1.0f);
     // Vertical axis through the origin vs the triangle's horizontal projection.
+    if (need_pole) {
     float e[3], tol[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -189,6 +190,7 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
       const bool dn = z[0] < 0.0f && z[1] < 0.0f && z[2] < 0.0f;
       if (!dn) s_hi = 1.0f;
       if (!up) s_lo = -1.0f;
+    }
     }
   }
   const float smax_abs = fmaxf(fabsf(s_lo), fabsf(s_hi));
@@ -275,7 +277,15 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
 // range_max, or the band of elevations it subtends holds no channel, or (on
 // a partial-FOV sensor) the azimuths it subtends miss the field of view.
 // Conservative: any doubt (sphere near the origin, wide angles) keeps the group.
-__device__ inline bool group_culled(float cx, float cy, float cz, float rad, const DevSensor& s) {
+struct GroupVerdict {
+  bool culled;      // no ray of the sensor can reach the group
+  bool need_range;  // the group straddles range_min or range_max: test triangles
+  bool need_pole;   // the group touches the vertical axis through the origin
+};
+
+__device__ inline GroupVerdict group_test(float cx, float cy, float cz, float rad,
+                                          const DevSensor& s) {
+  GroupVerdict v{false, true, true};
   const float dx = cx - s.o[0], dy = cy - s.o[1], dz = cz - s.o[2];
   const float lf = fmaf(dx, s.f[0], fmaf(dy, s.f[1], dz * s.f[2]));
   const float lr = fmaf(dx, s.r[0], fmaf(dy, s.r[1], dz * s.r[2]));
@@ -283,9 +293,13 @@ __device__ inline bool group_culled(float cx, float cy, float cz, float rad, con
   const float h2 = fmaf(lf, lf, lr * lr);
   const float D2 = fmaf(lu, lu, h2);
   const float r = rad * 1.0001f + 1e-6f;
-  if (D2 <= 4.0f * r * r) return false;  // sphere within 30 deg of the origin: keep
+  // the vertical line through the origin misses the sphere: no triangle of
+  // the group can surround it
+  v.need_pole = !(h2 > r * r * 1.0001f);
+  if (D2 <= 4.0f * r * r) return v;  // sphere within 30 deg of the origin: keep
   const float D = sqrtf(D2);
-  if (D - r > s.dmax * (1.0f + 1e-5f) + 1e-6f) return true;
+  if (D - r > s.dmax * (1.0f + 1e-5f) + 1e-6f) { v.culled = true; return v; }
+  v.need_range = !(D + r < s.dmax * (1.0f - 1e-5f) && D - r > s.dmin * (1.0f + 1e-5f));
   const float invD = 1.0f / D;
   const float sa = r * invD;                    // sin(alpha), alpha <= 30 deg
   const float ca = sqrtf(fmaxf(1.0f - sa * sa, 0.0f));
@@ -296,7 +310,7 @@ __device__ inline bool group_culled(float cx, float cy, float cz, float rad, con
   s_lo -= 1e-5f + ETA_SIN;
   s_hi += 1e-5f + ETA_SIN;
   const uint32_t j = chan_search(s, s_lo, false);
-  if (j >= s.gamma || s.sin_tab[j] > s_hi) return true;
+  if (j >= s.gamma || s.sin_tab[j] > s_hi) { v.culled = true; return v; }
   if (!s.wrap && hc > 2.0f * r) {
     const float beta = asinf(fminf(r / hc, 1.0f)) + 1e-4f;
     const float az = atan2f(lr, lf);
@@ -304,9 +318,9 @@ __device__ inline bool group_culled(float cx, float cy, float cz, float rad, con
     const float mid = s.theta_start + half;
     float d = az - mid;
     d -= TWO_PI_F * floorf((d + PI_F) * (1.0f / TWO_PI_F));
-    if (fabsf(d) > half + beta + 1e-4f) return true;
+    if (fabsf(d) > half + beta + 1e-4f) v.culled = true;
   }
-  return false;
+  return v;
 }
 
 __device__ inline float wave_min(float v) {
@@ -373,9 +387,15 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
   }
   for (uint32_t n = S.sensor_begin; n < S.sensor_end; ++n) {
     const DevSensor& s = sens[n];
-    if (!any_active || (group_cull && group_culled(gcx, gcy, gcz, grad, s))) continue;
+    if (!any_active) continue;
+    GroupVerdict gv{false, true, true};
+    if (group_cull) {
+      gv = group_test(gcx, gcy, gcz, grad, s);
+      if (gv.culled) continue;
+    }
     Span sp;
-    const bool ok = active && span_of(vx, vy, vz, s, small_c, small_r, sp);
+    const bool ok = active && span_of(vx, vy, vz, s, small_c, small_r, gv.need_range,
+                                      gv.need_pole, sp);
     const uint32_t chan = ok ? (sp.c_from | (sp.c_count << 16)) : 0u;
     const bool is_large = ok && sp.large;
     const bool rect0 = ok && !sp.large;
@@ -623,22 +643,30 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     Statics st;
     ItemInfo inf;
     for (uint32_t f = lane; f < total; f += 64) {
-      // owner = last item whose prefix start <= f
-      uint32_t lo = 0, hi = 64;
-#pragma unroll
-      for (int it = 0; it < 6; ++it) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (pre_s[w][mid] <= f) lo = mid; else hi = mid;
-      }
-      if ((int)lo != cur) {
+      // owner = last item whose prefix start <= f (pre_s[w][64] == total > f).
+      // f grows with each step, so the owner never moves backwards: keep it
+      // while its range still covers f, else bisect the items after it.
+      uint32_t lo;
+      if (cur >= 0 && pre_s[w][cur + 1] > f) {
+        lo = (uint32_t)cur;
+      } else {
+        lo = cur >= 0 ? (uint32_t)cur + 1u : 0u;
+        uint32_t hi = 64;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (pre_s[w][mid] <= f) lo = mid; else hi = mid;
+        }
         cur = (int)lo;
         st = st_s[w][lo];
         inf = in_s[w][lo];
       }
       const uint32_t local = f - pre_s[w][lo];
-      uint32_t c = (uint32_t)((float)local * inf.inv_rc);
-      if (c * inf.r_count > local) --c;
-      else if ((c + 1) * inf.r_count <= local) ++c;
+      uint32_t c = 0;
+      if (local >= inf.r_count) {
+        c = (uint32_t)((float)local * inf.inv_rc);
+        if (c * inf.r_count > local) --c;
+        else if ((c + 1) * inf.r_count <= local) ++c;
+      }
       const uint32_t r = local - c * inf.r_count;
       const uint32_t ch = inf.c_from + c;
       uint32_t ray = inf.r_start + r;
