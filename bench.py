@@ -115,6 +115,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=16, help="oracle rays per sensor")
+    ap.add_argument("--ranges", default="10,50,100",
+                    help="range_max values (m) of the range-culling sweep ('' to skip)")
+    ap.add_argument("--range-steps", type=int, default=10)
     ap.add_argument("--tuning", default=None, help="JSON file of grca options")
     ap.add_argument("--opt", action="append", default=[], help="option override k=v")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -241,6 +244,35 @@ def main():
     mean_b = float(np.mean(b_ms))
     value = n_rays / (mean_b * 1e-3)
 
+    # ---------------- range-culling sweep (batched frames at shorter range_max)
+    sweep = {}
+    for rng_s in [x for x in args.ranges.split(",") if x.strip()]:
+        dmax = float(rng_s)
+        for k, s in enumerate(wl.sensors):
+            ctx.sensor_config(ids[k], dict(s, range_max=np.float32(dmax)), 0)
+        fr2 = grca.grca_frame_create(ctx.h, 0, ids, dist, tri)
+        for i in range(2):
+            grca.grca_frame_launch(ctx.h, fr2, mats[i], synth.deform_time(i), stream)
+            grca.grca_frame_synchronize(ctx.h, fr2, stream)
+        sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.range_steps)]
+        for k in range(args.range_steps):
+            f = args.warmup + k
+            sev[k][0].record(stream)
+            grca.grca_frame_launch(ctx.h, fr2, mats[f], synth.deform_time(f), stream)
+            sev[k][1].record(stream)
+        torch.cuda.synchronize()
+        grca.grca_frame_synchronize(ctx.h, fr2, stream)
+        s_ms = [a.elapsed_time(b) for a, b in sev]
+        st2 = ctx.last_stats()
+        sweep[f"{dmax:g}"] = {"mean_ms": float(np.mean(s_ms)), "p99_ms": pct(s_ms, 99),
+                             "rays_per_s": n_rays / (float(np.mean(s_ms)) * 1e-3),
+                             "rtic": st2["rtic"]}
+        log(f"range_max {dmax:g} m: {sweep[f'{dmax:g}']}")
+        grca.grca_frame_destroy(fr2)
+    for k, s in enumerate(wl.sensors):
+        ctx.sensor_config(ids[k], s, 0)
+
     # ---------------- roofline of the dominant kernel
     dom = max(("bounds", "expand", "isect"), key=lambda k: stage_ms[k])
     if dom == "isect":
@@ -317,6 +349,7 @@ def main():
         "stage_ms": stage_ms,
         "rtic_per_frame": stats["rtic"], "rtic_per_s": rtic_s,
         "work": {k: stats[k] for k in ("pairs_tested", "rect_items", "large_records", "row_items")},
+        "range_sweep": sweep,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

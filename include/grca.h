@@ -60,6 +60,11 @@ typedef enum {
 #define GRCA_MEM_HOST 0u             /* caller pointers are host memory                  */
 #define GRCA_MEM_DEVICE 1u           /* caller pointers are device memory                */
 #define GRCA_UPDATE_VERTICES_ONLY 2u /* scene_update: keep topology, indices may be NULL */
+#define GRCA_CULL_BACKFACE 4u        /* cast: single-sided, only front faces count:
+                                        d . ((v1 - v0) x (v2 - v0)) < 0 (counter-clockwise
+                                        as seen by the ray, the Moller-Trumbore culling
+                                        branch); the back-face filter of the appendix's
+                                        early pass, applied per hit                      */
 #define GRCA_CAST_ALL_PAIRS 8u       /* cast: test every ray against every triangle (no
                                         culling; the reference for "culling never drops
                                         a hit").  Same per-pair arithmetic, so culled and

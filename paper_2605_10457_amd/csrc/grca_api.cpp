@@ -287,7 +287,7 @@ struct Plan {
 };
 
 grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32_t block,
-                      Plan& P) {
+                      Plan& P, uint32_t flags = 0) {
   if (n == 0) return fail(ctx, GRCA_ERR_INVALID_ARG, "num_sensors must be >= 1");
   if (n > 4096) return fail(ctx, GRCA_ERR_INVALID_ARG, "at most 4096 sensors per cast");
   std::vector<const SensorData*> sd(n);
@@ -353,6 +353,16 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
     d.inv_dtheta_d = 1.0 / S.dtheta;
     d.period_idx_d = kTwoPi / S.dtheta;
     d.chan = S.chan; d.chan_d = S.chan_d; d.sin_tab = S.sin_tab; d.lut = S.lut; d.az = S.az;
+    d.cull_back = 0;
+    if (flags & GRCA_CULL_BACKFACE) {
+      const float* f = S.desc.forward;
+      const float* r = S.desc.right;
+      const float* u = S.desc.up;
+      const double det = (double)f[0] * ((double)r[1] * u[2] - (double)r[2] * u[1]) -
+                         (double)f[1] * ((double)r[0] * u[2] - (double)r[2] * u[0]) +
+                         (double)f[2] * ((double)r[0] * u[1] - (double)r[1] * u[0]);
+      d.cull_back = det > 0.0 ? 1 : -1;
+    }
     P.sens[k] = d;
   }
   P.total_blocks = blocks;
@@ -445,7 +455,8 @@ grca_status ws_drain(grca_context* ctx, grca_workspace* ws) {
       rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
       if (rc != GRCA_OK) { R.live = false; return rc; }
       Plan P;
-      rc = make_plan(ctx, R.ids.data(), (uint32_t)R.ids.size(), ctx->opt.bounds_block, P);
+      rc = make_plan(ctx, R.ids.data(), (uint32_t)R.ids.size(), ctx->opt.bounds_block, P,
+                     R.flags);
       if (rc != GRCA_OK) { R.live = false; return rc; }
       rc = enqueue_kernels(ctx, ws, slot, P, R.dist, R.tri, R.flags, R.st);
       if (rc != GRCA_OK) { R.live = false; return rc; }
@@ -962,7 +973,7 @@ grca_status cast_on(grca_context* ctx, grca_workspace* ws, const uint32_t* ids, 
                     float* out_dist, uint32_t* out_tri, uint32_t flags, hipStream_t st) {
   if (n && !ids) return fail(ctx, GRCA_ERR_INVALID_ARG, "NULL sensor id list");
   Plan P;
-  grca_status rc = make_plan(ctx, ids, n, ctx->opt.bounds_block, P);
+  grca_status rc = make_plan(ctx, ids, n, ctx->opt.bounds_block, P, flags);
   if (rc != GRCA_OK) return rc;
   if (ws->fixed && P.rays > ws->key_cap)
     return fail(ctx, GRCA_ERR_CAPACITY, "cast has more rays than the workspace holds");

@@ -43,7 +43,7 @@ struct DevSensor {
   float theta_start;   // theta_0 = -floor(chi/2) * dtheta (FP32 copy for the bounds pass)
   float inv_dtheta;    // chi / fov
   float period_idx;    // 2 pi / dtheta: one full turn in ray-index units
-  float pad0;
+  int32_t cull_back;   // 0: two-sided; +1/-1: single-sided, sign = handedness of (f, r, u)
   double theta_start_d, inv_dtheta_d, period_idx_d;
   const float2* chan;   // (cos phi_j, sin phi_j), FP32
   const double2* chan_d; // (cos phi_j, sin phi_j), FP64
@@ -117,6 +117,10 @@ __device__ inline bool make_statics(float ax, float ay, float az_, float bx, flo
   const double nN2 = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
   if (!(nN2 > 0.0) || g == 0.0 || !(g == g)) return false;
   const double sg = g > 0.0 ? 1.0 : -1.0;
+  // Single-sided casting keeps only front faces, d . (e1 x e2) < 0 in world
+  // coordinates; a hit has sign(d . N) = sign(p0 . N), and the local frame
+  // flips that sign when (f, r, u) is left-handed.
+  if (s.cull_back != 0 && (double)s.cull_back * sg > 0.0) return false;
   double n[3][3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {

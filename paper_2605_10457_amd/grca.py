@@ -28,6 +28,7 @@ GRCA_MISS_TRI = 0xFFFFFFFF
 GRCA_MEM_HOST = 0
 GRCA_MEM_DEVICE = 1
 GRCA_UPDATE_VERTICES_ONLY = 2
+GRCA_CULL_BACKFACE = 4
 GRCA_CAST_ALL_PAIRS = 8
 
 _STATUS = {1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "CAPACITY", 5: "NOT_FOUND"}

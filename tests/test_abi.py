@@ -37,3 +37,17 @@ def test_binding_signatures_load():
         pytest.skip("libgrca.so not built")
     lib = grca.load()
     assert lib.grca_cast.restype is ctypes.c_int
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/grca.h must compile as C99 (no C++ in the public ABI)."""
+    import subprocess
+    src = tmp_path / "use_abi.c"
+    src.write_text('#include "grca.h"\n'
+                   'int probe(grca_context* c) {\n'
+                   '  grca_sensor_desc d; grca_options o; grca_stats s; (void)d; (void)s;\n'
+                   '  return (int)grca_get_options(c, &o) + (int)GRCA_MISS_TRI;\n}\n')
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-pedantic", "-c",
+                        "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                        str(tmp_path / "use_abi.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr

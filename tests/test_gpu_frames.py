@@ -242,3 +242,39 @@ def test_config4_sample_parity_and_all_pairs(torch):
         assert np.array_equal(d4.view(np.uint32), d[off:off + n4].view(np.uint32))
     finally:
         ctx.close()
+
+
+def test_config3_scaled_parity(torch):
+    wl = synth.config3(scale=0.1)
+    sc = wl.scene
+    _say(f"config3 at 10%: {sc.num_triangles} tris ({sc.n_dynamic_tris} deformable), 8 uneven sensors")
+    ctx = grca.Context(0)
+    try:
+        ctx.set_options(item_capacity=32 << 20, large_capacity=4 << 20)
+        ids = grca.load_workload(ctx, wl, frame=25)
+        n = sum(len(s["elevation"]) * s["rays_per_channel"] for s in wl.sensors)
+        d, t = ctx.cast_host(ids, n)
+        v_or = oracle_pose(sc, 25)
+        _sample_parity(wl.sensors, v_or, sc.indices, d, t, 48, 25, "config3")
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("dmax", [10.0, 50.0])
+def test_range_limited_parity(torch, dmax):
+    wl = synth.config4(scale=0.02, range_max=dmax)
+    sc = wl.scene
+    _say(f"config4 recipe at 2% with range_max {dmax} m")
+    ctx = grca.Context(0)
+    try:
+        ctx.set_options(item_capacity=16 << 20, large_capacity=2 << 20)
+        ids = grca.load_workload(ctx, wl, frame=1)
+        n = sum(len(s["elevation"]) * s["rays_per_channel"] for s in wl.sensors)
+        d, t = ctx.cast_host(ids, n)
+        assert np.all(np.isinf(d) | (d <= dmax * (1 + 1e-6)))
+        v_or = oracle_pose(sc, 1)
+        _sample_parity(wl.sensors, v_or, sc.indices, d, t, 48, 1, f"range{dmax:g}")
+        d4, t4 = ctx.cast_host([ids[4]], 128 * 4096, grca.GRCA_CAST_ALL_PAIRS)
+        assert np.array_equal(t4, t[4 * 128 * 4096:5 * 128 * 4096])
+    finally:
+        ctx.close()

@@ -190,3 +190,36 @@ def test_invalid_inputs_rejected(ctx):
     with pytest.raises(grca.GrcaError) as e:
         ctx.cast([12345], np.empty(1, np.float32), np.empty(1, np.uint32))
     assert e.value.status == grca.GRCA_ERR_NOT_FOUND
+
+
+def test_single_sided_cast(ctx):
+    _say("GRCA_CULL_BACKFACE: config1 parity and the inside of a closed sphere")
+    wl = synth.config1()
+    s = wl.sensors[0]
+    v, f = wl.scene.vertices, wl.scene.indices
+    ctx.scene_update(0, v, f)
+    ctx.sensor_config(0, s, 0)
+    n = 32 * 512
+    d, t = _cast(ctx, [0], n, grca.GRCA_CULL_BACKFACE)
+    d2, t2 = _cast(ctx, [0], n, grca.GRCA_CULL_BACKFACE | grca.GRCA_CAST_ALL_PAIRS)
+    assert np.array_equal(t, t2)
+    s1 = dict(s, oracle_flags=1)
+    orc = O.cast(s1, v, f)
+    rep = parity.check(s1, v, f, orc, d, t)
+    parity.assert_parity(rep, "single-sided config1")
+    # from inside an outward-wound sphere every face is a back face
+    o = np.array([1.0, 2.0, 3.0])
+    sv, sf = synth.icosphere(3)
+    vs = (sv * 5.0 + o).astype(np.float32)
+    ss = synth.sensor(o, 0.0, synth.elevations_full_sphere(16), 64, 360.0, 0.05, 100.0)
+    ctx.scene_update(1, vs, sf)
+    ctx.sensor_config(1, ss, 1)
+    d, t = _cast(ctx, [1], 16 * 64, grca.GRCA_CULL_BACKFACE)
+    assert np.all(t == grca.GRCA_MISS_TRI)
+    # a left-handed sensor basis sees the same faces
+    sl = dict(ss, right=-ss["right"])
+    ctx.sensor_config(2, sl, 1)
+    d, t = _cast(ctx, [2], 16 * 64, grca.GRCA_CULL_BACKFACE)
+    assert np.all(t == grca.GRCA_MISS_TRI)
+    d, t = _cast(ctx, [2], 16 * 64)
+    assert np.all(t != grca.GRCA_MISS_TRI)
