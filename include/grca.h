@@ -158,6 +158,12 @@ typedef struct {
                                          whose azimuth index wraps                          */
   float range_min, range_max;         /* a hit counts iff t in [range_min, range_max];
                                          0 < range_min <= range_max < +inf                  */
+  const float* azimuth_offset_rad;    /* optional (NULL = none), chi host values: ray R has
+                                         azimuth theta_R + offset_R (angular noise, appendix
+                                         "Ray Noise Simulation"); |offset_R| <= fov / chi   */
+  const uint8_t* ray_mask;            /* optional (NULL = all on), gamma * chi host values
+                                         at C * chi + R: 0 switches ray (C, R) off; it then
+                                         reports a miss (non-spinning / animated patterns)  */
 } grca_sensor_desc;
 
 /* Create or replace sensor `sensor_id`.  Builds the per-sensor channel and

@@ -65,6 +65,8 @@ typedef struct {
   float range_min;
   float range_max;
   uint32_t flags; /* bit 0: single-sided (cull back faces) */
+  const float* azimuth_offset_rad; /* optional, chi values: theta*_R = theta_R + offset_R */
+  const uint8_t* ray_mask;         /* optional, gamma*chi values: 0 = ray switched off  */
 } oracle_sensor;
 
 /* ---- small vector helpers (FP64) ---------------------------------------- */
@@ -91,7 +93,9 @@ static void load_vertex(const float* xyz, uint32_t i, double* o) {
 void oracle_ray_direction(const oracle_sensor* s, uint32_t C, uint32_t R, double* d) {
   const double chi = (double)s->rays_per_channel;
   const double dtheta = (double)s->fov_rad / chi;
-  const double theta = ((double)R - floor(chi / 2.0)) * dtheta;
+  double theta = ((double)R - floor(chi / 2.0)) * dtheta;
+  /* angular noise (appendix "Ray Noise Simulation"): a pre-stored perturbed azimuth */
+  if (s->azimuth_offset_rad) theta += (double)s->azimuth_offset_rad[R];
   const double phi = (double)s->channel_elevation_rad[C];
   const double ct = cos(theta), st = sin(theta), cp = cos(phi), sp = sin(phi);
   for (int k = 0; k < 3; ++k)
@@ -176,6 +180,14 @@ static void cast_one(const cast_job* J, uint64_t i) {
   const uint32_t g = J->rays[i];
   const uint32_t chi = s->rays_per_channel;
   const uint32_t C = g / chi, R = g % chi;
+  if (s->ray_mask && !s->ray_mask[g]) { /* switched-off ray (non-spinning patterns) */
+    J->out_t[i] = INFINITY;
+    J->out_tri[i] = 0xFFFFFFFFu;
+    J->out_flags[i] = 0;
+    if (J->out_t2) J->out_t2[i] = INFINITY;
+    if (J->out_tri2) J->out_tri2[i] = 0xFFFFFFFFu;
+    return;
+  }
   double o[3] = {s->origin[0], s->origin[1], s->origin[2]};
   double d[3];
   oracle_ray_direction(s, C, R, d);

@@ -52,6 +52,8 @@ class OracleSensor(ctypes.Structure):
         ("range_min", ctypes.c_float),
         ("range_max", ctypes.c_float),
         ("flags", ctypes.c_uint32),
+        ("azimuth_offset_rad", ctypes.POINTER(ctypes.c_float)),
+        ("ray_mask", ctypes.POINTER(ctypes.c_uint8)),
     ]
 
 
@@ -105,6 +107,14 @@ class _Sensor:
         s.range_min = float(np.float32(sensor.get("range_min", 0.05)))
         s.range_max = float(np.float32(sensor.get("range_max", 1000.0)))
         s.flags = int(sensor.get("oracle_flags", 0))
+        self.az_off = None
+        self.mask = None
+        if sensor.get("azimuth_offset") is not None:
+            self.az_off = _f32(sensor["azimuth_offset"])
+            s.azimuth_offset_rad = self.az_off.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        if sensor.get("ray_mask") is not None:
+            self.mask = np.ascontiguousarray(sensor["ray_mask"], np.uint8).reshape(-1)
+            s.ray_mask = self.mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         self.s = s
 
     @property

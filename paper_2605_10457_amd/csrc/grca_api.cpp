@@ -59,8 +59,10 @@ struct SensorData {
   float* sin_tab = nullptr;
   uint16_t* lut = nullptr;
   float2* az = nullptr;
+  uint8_t* mask = nullptr;
   uint32_t lut_size = 0;
   double dtheta = 0.0;
+  float az_noise = 0.0f;
   bool wrap = false;
 };
 
@@ -89,7 +91,7 @@ void free_scene(SceneData& s) {
 }
 
 void free_sensor(SensorData& s) {
-  dfree(s.chan); dfree(s.chan_d); dfree(s.sin_tab); dfree(s.lut); dfree(s.az);
+  dfree(s.chan); dfree(s.chan_d); dfree(s.sin_tab); dfree(s.lut); dfree(s.az); dfree(s.mask);
 }
 
 }  // namespace
@@ -353,6 +355,8 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
     d.inv_dtheta_d = 1.0 / S.dtheta;
     d.period_idx_d = kTwoPi / S.dtheta;
     d.chan = S.chan; d.chan_d = S.chan_d; d.sin_tab = S.sin_tab; d.lut = S.lut; d.az = S.az;
+    d.mask = S.mask;
+    d.az_noise = S.az_noise;
     d.cull_back = 0;
     if (flags & GRCA_CULL_BACKFACE) {
       const float* f = S.desc.forward;
@@ -912,6 +916,17 @@ extern "C" grca_status grca_sensor_config(grca_context* ctx, uint32_t sensor_id,
       return fail(ctx, GRCA_ERR_INVALID_ARG, "fov outside (0, 2 pi]");
     if (!(s->range_min > 0.0f) || !(s->range_max >= s->range_min) || !std::isfinite(s->range_max))
       return fail(ctx, GRCA_ERR_INVALID_ARG, "need 0 < range_min <= range_max < inf");
+    float az_noise = 0.0f;
+    if (s->azimuth_offset_rad) {
+      const double step = (double)s->fov_rad / (double)s->rays_per_channel;
+      for (uint32_t r = 0; r < s->rays_per_channel; ++r) {
+        const float a = s->azimuth_offset_rad[r];
+        if (!std::isfinite(a) || std::fabs((double)a) > step)
+          return fail(ctx, GRCA_ERR_INVALID_ARG, "azimuth offset not finite or beyond one ray step");
+        az_noise = std::max(az_noise, std::fabs(a));
+      }
+      az_noise = az_noise * 1.0001f + 1e-7f;
+    }
     HIPCHK(hipSetDevice(ctx->device));
     SensorData sd;
     sd.desc = *s;
@@ -919,25 +934,37 @@ extern "C" grca_status grca_sensor_config(grca_context* ctx, uint32_t sensor_id,
     sd.desc.channel_elevation_rad = nullptr;
     sd.dtheta = (double)s->fov_rad / (double)s->rays_per_channel;
     sd.wrap = std::fabs((double)s->fov_rad - kTwoPi) <= 1e-6;
+    sd.az_noise = az_noise;
+    sd.desc.azimuth_offset_rad = nullptr;
+    sd.desc.ray_mask = nullptr;
     uint32_t lut = std::max<uint32_t>(512, 4 * s->num_channels);
     sd.lut_size = std::min<uint32_t>(lut, 1u << 16);
     const uint32_t g = s->num_channels, c = s->rays_per_channel;
     auto cleanup = [&]() { free_sensor(sd); };
     hipError_t e = hipSuccess;
     float* elev_d = nullptr;
+    float* off_d = nullptr;
     if ((e = dmalloc(&sd.chan, g)) != hipSuccess || (e = dmalloc(&sd.chan_d, g)) != hipSuccess ||
         (e = dmalloc(&sd.sin_tab, g)) != hipSuccess || (e = dmalloc(&sd.az, c)) != hipSuccess ||
-        (e = dmalloc(&sd.lut, sd.lut_size)) != hipSuccess || (e = dmalloc(&elev_d, g)) != hipSuccess) {
+        (e = dmalloc(&sd.lut, sd.lut_size)) != hipSuccess || (e = dmalloc(&elev_d, g)) != hipSuccess ||
+        (s->azimuth_offset_rad && (e = dmalloc(&off_d, c)) != hipSuccess) ||
+        (s->ray_mask && (e = dmalloc(&sd.mask, (size_t)g * c)) != hipSuccess)) {
       cleanup();
       dfree(elev_d);
+      dfree(off_d);
       return fail(ctx, GRCA_ERR_OUT_OF_MEMORY, std::string("sensor tables: ") + hipGetErrorString(e));
     }
     e = hipMemcpy(elev_d, sd.elev.data(), 4ull * g, hipMemcpyHostToDevice);
+    if (e == hipSuccess && off_d)
+      e = hipMemcpy(off_d, s->azimuth_offset_rad, 4ull * c, hipMemcpyHostToDevice);
+    if (e == hipSuccess && sd.mask)
+      e = hipMemcpy(sd.mask, s->ray_mask, (size_t)g * c, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-      e = launch_sensor_tables(elev_d, g, c, sd.dtheta, sd.chan, sd.chan_d, sd.sin_tab, sd.az,
-                               sd.lut_size, sd.lut, nullptr);
+      e = launch_sensor_tables(elev_d, g, c, sd.dtheta, off_d, sd.chan, sd.chan_d, sd.sin_tab,
+                               sd.az, sd.lut_size, sd.lut, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     dfree(elev_d);
+    dfree(off_d);
     if (e != hipSuccess) {
       cleanup();
       return fail(ctx, GRCA_ERR_DEVICE, std::string("sensor tables: ") + hipGetErrorString(e));

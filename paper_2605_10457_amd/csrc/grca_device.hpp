@@ -49,7 +49,10 @@ struct DevSensor {
   const double2* chan_d; // (cos phi_j, sin phi_j), FP64
   const float* sin_tab; // sin phi_j (FP32, equal to chan[j].y), ascending
   const uint16_t* lut;  // lut[b] = first j with sin_tab[j] >= -1 + 2b/lut_size
-  const float2* az;     // (cos theta_R, sin theta_R), FP32
+  const float2* az;     // (cos theta_R, sin theta_R), FP32 (offsets included)
+  const uint8_t* mask;  // optional active-ray mask at C * chi + R (nullptr: all on)
+  float az_noise;       // max |azimuth offset| (radians), widens every azimuth span
+  uint32_t pad1;
 };
 
 struct DevScene {

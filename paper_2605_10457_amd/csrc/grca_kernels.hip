@@ -219,7 +219,7 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
       full = true;
     } else {
       const float cmin_el = sqrtf(fmaxf(1.0f - smax_abs * smax_abs, 0.0f));
-      const float m = MARGIN_AZ + MARGIN_AZ_POLE / fmaxf(cmin_el, 1e-3f);
+      const float m = MARGIN_AZ + MARGIN_AZ_POLE / fmaxf(cmin_el, 1e-3f) + s.az_noise;
       float a = t0 + lo - m - s.theta_start;
       a -= TWO_PI_F * floorf(a * (1.0f / TWO_PI_F));
       if (a < 0.0f) a = 0.0f;
@@ -312,7 +312,7 @@ __device__ inline GroupVerdict group_test(float cx, float cy, float cz, float ra
   const uint32_t j = chan_search(s, s_lo, false);
   if (j >= s.gamma || s.sin_tab[j] > s_hi) { v.culled = true; return v; }
   if (!s.wrap && hc > 2.0f * r) {
-    const float beta = asinf(fminf(r / hc, 1.0f)) + 1e-4f;
+    const float beta = asinf(fminf(r / hc, 1.0f)) + 1e-4f + s.az_noise;
     const float az = atan2f(lr, lf);
     const float half = 0.5f * (float)(s.chi - 1) / s.inv_dtheta;
     const float mid = s.theta_start + half;
@@ -448,6 +448,14 @@ __device__ inline void arc_intersect(ArcSet& A, double xl, double xh) {
 // Ray-index ranges [start, start + count) of one angular piece.
 __device__ inline int piece_ranges(const DevSensor& s, double lo, double hi, uint32_t* st,
                                    uint32_t* ct) {
+  // rays with azimuth offsets: nominal angle within max |offset| of the piece
+  lo -= (double)s.az_noise;
+  hi += (double)s.az_noise;
+  if (hi - lo >= TWO_PI) {
+    st[0] = 0;
+    ct[0] = s.chi;
+    return 1;
+  }
   double a = lo - s.theta_start_d;
   a -= TWO_PI * floor(a / TWO_PI);
   if (a < 0.0) a = 0.0;
@@ -583,6 +591,7 @@ struct ItemInfo {
   float dmin, dmax;
   const float2* chan;
   const float2* az;
+  const uint8_t* mask;
   float inv_rc;
   uint32_t pad;
 };
@@ -628,6 +637,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
         inf.dmax = s.dmax;
         inf.chan = s.chan;
         inf.az = s.az;
+        inf.mask = s.mask;
         inf.inv_rc = 1.0f / (float)rc;
         inf.pad = 0;
         in_s[w][lane] = inf;
@@ -671,11 +681,13 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
       const uint32_t ch = inf.c_from + c;
       uint32_t ray = inf.r_start + r;
       if (ray >= inf.chi) ray -= inf.chi;
+      const uint32_t gl = ch * inf.chi + ray;
+      if (inf.mask && !inf.mask[gl]) continue;
       const float2 cp = inf.chan[ch];
       const float2 ca = inf.az[ray];
       const unsigned long long key = ray_test(st, cp.x, cp.y, ca.x, ca.y, inf.dmin, inf.dmax,
                                               inf.tri);
-      if (key != KEY_INIT) key_min(keys, inf.key_offset + ch * inf.chi + ray, key);
+      if (key != KEY_INIT) key_min(keys, inf.key_offset + gl, key);
     }
     wave_sync();
   }
@@ -707,7 +719,7 @@ __global__ __launch_bounds__(256) void allpairs_kernel(const DevSensor* __restri
   const DevSensor& s = sens[sensor];
   const uint32_t nrays = s.gamma * s.chi;
   const uint32_t g = blockIdx.x * 256 + threadIdx.x;
-  const bool act = g < nrays;
+  const bool act = g < nrays && !(s.mask && !s.mask[g]);
   const uint32_t ch = act ? g / s.chi : 0, ray = act ? g % s.chi : 0;
   const float2 cp = s.chan[ch];
   const float2 ca = s.az[ray];
@@ -774,9 +786,9 @@ __global__ __launch_bounds__(256) void pose_kernel(
 
 // ------------------------------------------------------------------ sensor tables
 __global__ void sensor_tables_kernel(const float* __restrict__ elev, uint32_t gamma, uint32_t chi,
-                                     double dtheta, float2* __restrict__ chan,
-                                     double2* __restrict__ chan_d, float* __restrict__ sin_tab,
-                                     float2* __restrict__ az) {
+                                     double dtheta, const float* __restrict__ az_off,
+                                     float2* __restrict__ chan, double2* __restrict__ chan_d,
+                                     float* __restrict__ sin_tab, float2* __restrict__ az) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < gamma) {
     const double p = (double)elev[i];
@@ -787,7 +799,8 @@ __global__ void sensor_tables_kernel(const float* __restrict__ elev, uint32_t ga
   }
   if (i < chi) {
     // theta_R = (R - floor(chi / 2)) * dtheta (section 3.1, centred start)
-    const double th = ((double)i - (double)(chi / 2)) * dtheta;
+    double th = ((double)i - (double)(chi / 2)) * dtheta;
+    if (az_off) th += (double)az_off[i];
     az[i] = make_float2((float)cos(th), (float)sin(th));
   }
 }
@@ -908,11 +921,12 @@ hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* r
 }
 
 hipError_t launch_sensor_tables(const float* elev, uint32_t gamma, uint32_t chi, double dtheta,
-                                float2* chan, double2* chan_d, float* sin_tab, float2* az,
-                                uint32_t lut_size, uint16_t* lut, hipStream_t st) {
+                                const float* az_off, float2* chan, double2* chan_d,
+                                float* sin_tab, float2* az, uint32_t lut_size, uint16_t* lut,
+                                hipStream_t st) {
   const uint32_t n = gamma > chi ? gamma : chi;
   hipLaunchKernelGGL(sensor_tables_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, elev, gamma,
-                     chi, dtheta, chan, chan_d, sin_tab, az);
+                     chi, dtheta, az_off, chan, chan_d, sin_tab, az);
   hipLaunchKernelGGL(sensor_lut_kernel, dim3(cdiv(lut_size, 256)), dim3(256), 0, st, sin_tab,
                      gamma, lut_size, lut);
   return hipGetLastError();

@@ -46,8 +46,9 @@ hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* r
                        const float* phase, const DeformParam* groups, const double* pose_in,
                        float* x, float* y, float* z, hipStream_t st);
 hipError_t launch_sensor_tables(const float* elev, uint32_t gamma, uint32_t chi, double dtheta,
-                                float2* chan, double2* chan_d, float* sin_tab, float2* az,
-                                uint32_t lut_size, uint16_t* lut, hipStream_t st);
+                                const float* az_off, float2* chan, double2* chan_d,
+                                float* sin_tab, float2* az, uint32_t lut_size, uint16_t* lut,
+                                hipStream_t st);
 hipError_t launch_validate(const float* xyz, uint32_t nv, const uint32_t* idx, uint64_t nidx,
                            uint32_t* bad, hipStream_t st);
 hipError_t launch_soa(const float* xyz, uint32_t nv, float* x, float* y, float* z,

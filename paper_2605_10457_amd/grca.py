@@ -53,6 +53,8 @@ class SensorDesc(ctypes.Structure):
         ("fov_rad", ctypes.c_float),
         ("range_min", ctypes.c_float),
         ("range_max", ctypes.c_float),
+        ("azimuth_offset_rad", ctypes.POINTER(ctypes.c_float)),
+        ("ray_mask", ctypes.POINTER(ctypes.c_uint8)),
     ]
 
 
@@ -242,7 +244,16 @@ def make_sensor_desc(sensor: dict, scene_id: int):
     d.fov_rad = float(np.float32(sensor["fov"]))
     d.range_min = float(np.float32(sensor.get("range_min", 0.05)))
     d.range_max = float(np.float32(sensor.get("range_max", 1000.0)))
-    return d, elev
+    keep = [elev]
+    if sensor.get("azimuth_offset") is not None:
+        off = np.ascontiguousarray(sensor["azimuth_offset"], np.float32)
+        d.azimuth_offset_rad = off.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        keep.append(off)
+    if sensor.get("ray_mask") is not None:
+        m = np.ascontiguousarray(sensor["ray_mask"], np.uint8).reshape(-1)
+        d.ray_mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        keep.append(m)
+    return d, keep
 
 
 def grca_sensor_config(ctx, sensor_id, sensor: dict, scene_id: int):

@@ -223,3 +223,28 @@ def test_single_sided_cast(ctx):
     assert np.all(t == grca.GRCA_MISS_TRI)
     d, t = _cast(ctx, [2], 16 * 64)
     assert np.all(t != grca.GRCA_MISS_TRI)
+
+
+def test_azimuth_noise_and_ray_mask(ctx):
+    _say("per-ray azimuth offsets (angular noise) and an active-ray mask")
+    wl = synth.config1()
+    v, f = wl.scene.vertices, wl.scene.indices
+    s = wl.sensors[0]
+    rng = np.random.default_rng(12)
+    step = float(s["fov"]) / s["rays_per_channel"]
+    noisy = dict(s, azimuth_offset=rng.uniform(-0.45, 0.45, 512).astype(np.float32) * step)
+    ctx.scene_update(0, v, f)
+    rep, d, t = _parity(ctx, noisy, v, f, sensor_id=3, label="azimuth noise")
+    mask = (rng.uniform(size=32 * 512) < 0.7).astype(np.uint8)
+    masked = dict(s, ray_mask=mask)
+    ctx.sensor_config(4, masked, 0)
+    ctx.sensor_config(5, s, 0)
+    dm, tm = _cast(ctx, [4], 32 * 512)
+    d0, t0 = _cast(ctx, [5], 32 * 512)
+    on = mask.astype(bool)
+    assert np.array_equal(tm[on], t0[on])
+    assert np.all(tm[~on] == grca.GRCA_MISS_TRI) and np.all(np.isinf(dm[~on]))
+    d2, t2 = _cast(ctx, [4], 32 * 512, grca.GRCA_CAST_ALL_PAIRS)
+    assert np.array_equal(t2, tm)
+    with pytest.raises(grca.GrcaError):
+        ctx.sensor_config(6, dict(s, azimuth_offset=np.full(512, 2 * step, np.float32)), 0)

@@ -332,3 +332,38 @@ def test_pose_deform_phases():
     out = O.pose_deform(rest, nrm, half, 0.5, 1.0, 0.0)
     ref = rest.astype(np.float64) + 0.5 * math.sin(float(np.float32(math.pi / 2))) * nrm.astype(np.float64)
     assert np.array_equal(out, ref.astype(np.float32))
+
+
+# ---------------------------------------------------------------- noise / masks
+def test_constant_azimuth_offset_equals_yawed_sensor():
+    """A constant per-ray azimuth offset delta is the sensor turned by -delta
+    about up (theta grows toward right = clockwise from above)."""
+    v, f = synth.small_random_scene(2, n_tris=60)
+    delta = 0.0123
+    base = _sensor(origin=(0.1, 0.2, 0.05), yaw=0.4, elev=synth.elevations_full_sphere(8),
+                   rays=32, rmax=40.0)
+    noisy = dict(base, azimuth_offset=np.full(32, delta, np.float32))
+    turned = _sensor(origin=(0.1, 0.2, 0.05), yaw=0.4 - delta, elev=synth.elevations_full_sphere(8),
+                     rays=32, rmax=40.0)
+    a = O.cast(noisy, v, f)
+    b = O.cast(turned, v, f)
+    ok = (a["flags"] | b["flags"]) & (O.GRAZING | O.NEAR_TIE | O.RANGE_EDGE) == 0
+    assert ok.sum() > 100
+    assert np.array_equal(a["tri"][ok], b["tri"][ok])
+    hit = ok & (a["tri"] != O.MISS)
+    assert np.allclose(a["t"][hit], b["t"][hit], rtol=1e-6)
+    for C, R in [(3, 0), (5, 17)]:
+        da = O.ray_direction(noisy, C, R)
+        db = O.ray_direction(turned, C, R)
+        assert np.allclose(da, db, atol=1e-7)
+
+
+def test_ray_mask_switches_rays_off():
+    v, f = synth.small_random_scene(4, n_tris=60)
+    s = _sensor(origin=(0.1, 0.2, 0.05), elev=synth.elevations_full_sphere(8), rays=32, rmax=40.0)
+    mask = np.random.default_rng(1).integers(0, 2, 8 * 32).astype(np.uint8)
+    a = O.cast(s, v, f)
+    b = O.cast(dict(s, ray_mask=mask), v, f)
+    on = mask.astype(bool)
+    assert np.array_equal(a["tri"][on], b["tri"][on])
+    assert np.all(b["tri"][~on] == O.MISS) and np.all(np.isinf(b["t"][~on]))
