@@ -182,8 +182,6 @@ def main():
     log("batched warmup done")
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
-    stage_rows = []
-    launches_before = args.warmup
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
@@ -191,18 +189,19 @@ def main():
         ev[k][0].record(stream)
         grca.grca_frame_launch(ctx.h, frame, mats[f], synth.deform_time(f), stream)
         ev[k][1].record(stream)
-        done = launches_before + k - (grca.FRAME_RING - 1)
-        if done >= launches_before:
-            stage_rows.append(grca.grca_frame_stage_times(ctx.h, frame, done))
     torch.cuda.synchronize()
     wall_batched = time.perf_counter() - t_start
-    for done in range(max(launches_before, launches_before + args.steps - (grca.FRAME_RING - 1)),
-                      launches_before + args.steps):
-        stage_rows.append(grca.grca_frame_stage_times(ctx.h, frame, done))
     grca.grca_frame_synchronize(ctx.h, frame, stream)
     stats = ctx.last_stats()
     if stats["recasts"]:
         log(f"WARNING: queue overflow during the timed frames ({stats['recasts']} recasts)")
+    # per-kernel device times: the same frames launched stage by stage with
+    # HIP events between the stages, on the same stream
+    stage_rows = []
+    for k in range(args.steps):
+        f = args.warmup + k
+        stage_rows.append(grca.grca_frame_profile(ctx.h, frame, mats[f], synth.deform_time(f),
+                                                  stream))
     b_ms = [a.elapsed_time(b) for a, b in ev]
     stage_ms = {k: float(np.mean([r[k] for r in stage_rows])) for k in grca.STAGES}
     log(f"batched: mean {np.mean(b_ms):.3f} ms p50 {pct(b_ms, 50):.3f} p99 {pct(b_ms, 99):.3f}; "

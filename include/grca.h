@@ -249,13 +249,13 @@ grca_status grca_frame_launch(grca_frame* frame, const float* instance_matrices,
  * frame is re-run. */
 grca_status grca_frame_synchronize(grca_frame* frame, void* hip_stream);
 void grca_frame_destroy(grca_frame* frame);
-/* Device time of each stage of launch number `launch` of this frame (0 = the
- * first grca_frame_launch), measured with HIP events recorded between the
- * stages inside the graph: ms[0] pose, [1] key init, [2] bounds + binning,
- * [3] large-class expansion, [4] intersection, [5] resolve.  Only the last
- * GRCA_FRAME_RING launches are kept; waits for that launch. */
-#define GRCA_FRAME_RING 4
-grca_status grca_frame_stage_times(grca_frame* frame, uint64_t launch, float* ms6);
+/* One frame exactly as grca_frame_launch runs it (same kernels, buffers and
+ * arguments), but launched stage by stage on hip_stream with HIP events
+ * recorded between the stages; waits and returns the device time of each
+ * stage in ms6: [0] pose, [1] key init, [2] bounds + binning, [3] large-class
+ * expansion, [4] intersection, [5] resolve. */
+grca_status grca_frame_profile(grca_frame* frame, const float* instance_matrices, double time_s,
+                               void* hip_stream, float* ms6);
 
 /* ---- workspaces: concurrent casts (serving) ------------------------------------ */
 

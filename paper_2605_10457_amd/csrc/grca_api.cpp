@@ -148,12 +148,9 @@ struct grca_frame {
   uint32_t* out_tri = nullptr;
   grca_workspace* ws = nullptr;
   hipStream_t cap_stream = nullptr;
-  // GRCA_FRAME_RING instances of the same graph, each with its own stage events
-  hipGraph_t graph[GRCA_FRAME_RING] = {};
-  hipGraphExec_t exec[GRCA_FRAME_RING] = {};
-  hipEvent_t tev[GRCA_FRAME_RING][7] = {};
-  bool timed = true;
-  uint64_t launches = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t tev[7] = {};  // stage events of grca_frame_profile
 };
 
 struct grca_context {
@@ -1192,69 +1189,74 @@ extern "C" grca_status grca_workspace_synchronize(grca_context* ctx, grca_worksp
 
 // =============================================================== frames
 namespace {
-grca_status capture_one(grca_context* ctx, grca_frame* fr, int inst, const Plan& P) {
+// The frame's stage sequence on stream `st`; with `ev` non-null an event is
+// recorded before the first stage and after each stage.
+grca_status enqueue_frame(grca_context* ctx, grca_frame* fr, const Plan& P, hipStream_t st,
+                          hipEvent_t* ev) {
   SceneData& sc = ctx->scenes.at(fr->scene_id);
   grca_workspace* ws = fr->ws;
-  hipStream_t st = fr->cap_stream;
-  hipEvent_t* ev = fr->tev[inst];
-  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  grca_status erc = GRCA_OK;
   const grca_options& o = ctx->opt;
   const uint32_t n = (uint32_t)P.rays;
   const uint32_t icap = (uint32_t)std::min<uint64_t>(ws->item_cap, 0xFFFFFFFFull);
   const uint32_t lcap = (uint32_t)std::min<uint64_t>(ws->large_cap, 0xFFFFFFFFull);
   const uint32_t pb = persist_blocks(ctx);
-  hipError_t e = hipSuccess;
-  auto mark = [&](int k) {
-    if (fr->timed && e == hipSuccess) e = hipEventRecord(ev[k], st);
-  };
-  mark(0);
-  if (sc.pose_in) erc = enqueue_pose_kernels(ctx, sc, st);
-  mark(1);
-  if (erc == GRCA_OK && e == hipSuccess) e = launch_init(ws->keys, n, ws->cnt, st);
-  mark(2);
-  if (e == hipSuccess && erc == GRCA_OK)
-    e = launch_bounds(ws->dscenes, (uint32_t)P.scenes.size(), P.total_blocks, o.bounds_block,
-                      ws->dsens, o.small_channels, o.small_rays, ws->items, icap, ws->large,
-                      lcap, ws->cnt, o.group_cull, st);
-  mark(3);
-  if (e == hipSuccess && erc == GRCA_OK)
-    e = launch_expand(ws->dscenes, ws->dsens, ws->large, ws->items, icap, lcap, o.row_chunk,
-                      ws->cnt, pb, st);
-  mark(4);
-  if (e == hipSuccess && erc == GRCA_OK)
-    e = launch_isect(ws->dscenes, ws->dsens, ws->items, icap, ws->cnt, ws->keys, pb, st);
-  mark(5);
-  if (e == hipSuccess && erc == GRCA_OK) e = launch_resolve(ws->keys, n, fr->out_dist, fr->out_tri, st);
-  mark(6);
-  if (e == hipSuccess && erc == GRCA_OK)
-    e = hipMemcpyAsync(ws->cnt_host, ws->cnt, sizeof(Counters), hipMemcpyDeviceToHost, st);
+  if (ev) HIPCHK(hipEventRecord(ev[0], st));
+  if (sc.pose_in) {
+    grca_status rc = enqueue_pose_kernels(ctx, sc, st);
+    if (rc != GRCA_OK) return rc;
+  }
+  if (ev) HIPCHK(hipEventRecord(ev[1], st));
+  HIPCHK(launch_init(ws->keys, n, ws->cnt, st));
+  if (ev) HIPCHK(hipEventRecord(ev[2], st));
+  HIPCHK(launch_bounds(ws->dscenes, (uint32_t)P.scenes.size(), P.total_blocks, o.bounds_block,
+                       ws->dsens, o.small_channels, o.small_rays, ws->items, icap, ws->large,
+                       lcap, ws->cnt, o.group_cull, st));
+  if (ev) HIPCHK(hipEventRecord(ev[3], st));
+  HIPCHK(launch_expand(ws->dscenes, ws->dsens, ws->large, ws->items, icap, lcap, o.row_chunk,
+                       ws->cnt, pb, st));
+  if (ev) HIPCHK(hipEventRecord(ev[4], st));
+  HIPCHK(launch_isect(ws->dscenes, ws->dsens, ws->items, icap, ws->cnt, ws->keys, pb, st));
+  if (ev) HIPCHK(hipEventRecord(ev[5], st));
+  HIPCHK(launch_resolve(ws->keys, n, fr->out_dist, fr->out_tri, st));
+  if (ev) HIPCHK(hipEventRecord(ev[6], st));
+  HIPCHK(hipMemcpyAsync(ws->cnt_host, ws->cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  return GRCA_OK;
+}
+
+grca_status capture_one(grca_context* ctx, grca_frame* fr, const Plan& P) {
+  hipStream_t st = fr->cap_stream;
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  const grca_status erc = enqueue_frame(ctx, fr, P, st, nullptr);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(st, &g);
-  if (erc != GRCA_OK) { if (g) (void)hipGraphDestroy(g); return erc; }
-  if (e != hipSuccess || e2 != hipSuccess) {
+  if (erc != GRCA_OK) {
     if (g) (void)hipGraphDestroy(g);
-    return fail(ctx, GRCA_ERR_DEVICE, std::string("frame capture: ") +
-                                          hipGetErrorString(e != hipSuccess ? e : e2));
+    return erc;
   }
-  fr->graph[inst] = g;
-  HIPCHK(hipGraphInstantiate(&fr->exec[inst], g, nullptr, nullptr, 0));
+  if (e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(ctx, GRCA_ERR_DEVICE, std::string("frame capture: ") + hipGetErrorString(e2));
+  }
+  fr->graph = g;
+  HIPCHK(hipGraphInstantiate(&fr->exec, g, nullptr, nullptr, 0));
   return GRCA_OK;
 }
 
 void destroy_graphs(grca_frame* fr) {
-  for (int i = 0; i < GRCA_FRAME_RING; ++i) {
-    if (fr->exec[i]) (void)hipGraphExecDestroy(fr->exec[i]);
-    if (fr->graph[i]) (void)hipGraphDestroy(fr->graph[i]);
-    fr->exec[i] = nullptr;
-    fr->graph[i] = nullptr;
-  }
+  if (fr->exec) (void)hipGraphExecDestroy(fr->exec);
+  if (fr->graph) (void)hipGraphDestroy(fr->graph);
+  fr->exec = nullptr;
+  fr->graph = nullptr;
+}
+
+grca_status frame_plan(grca_context* ctx, grca_frame* fr, Plan& P) {
+  return make_plan(ctx, fr->ids.data(), (uint32_t)fr->ids.size(), ctx->opt.bounds_block, P);
 }
 
 grca_status capture_frame(grca_context* ctx, grca_frame* fr) {
   destroy_graphs(fr);
   Plan P;
-  grca_status rc = make_plan(ctx, fr->ids.data(), (uint32_t)fr->ids.size(), ctx->opt.bounds_block, P);
+  grca_status rc = frame_plan(ctx, fr, P);
   if (rc != GRCA_OK) return rc;
   grca_workspace* ws = fr->ws;
   rc = ws_quiesce(ctx, ws);
@@ -1269,15 +1271,8 @@ grca_status capture_frame(grca_context* ctx, grca_frame* fr) {
   std::memcpy(ws->dscenes_host, P.scenes.data(), P.scenes.size() * sizeof(DevScene));
   HIPCHK(hipMemcpy(ws->dsens, ws->dsens_host, P.sens.size() * sizeof(DevSensor), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(ws->dscenes, ws->dscenes_host, P.scenes.size() * sizeof(DevScene), hipMemcpyHostToDevice));
-  for (int i = 0; i < GRCA_FRAME_RING; ++i) {
-    rc = capture_one(ctx, fr, i, P);
-    if (rc != GRCA_OK && i == 0 && fr->timed) {
-      // event nodes unsupported: capture without stage timing
-      fr->timed = false;
-      rc = capture_one(ctx, fr, i, P);
-    }
-    if (rc != GRCA_OK) return rc;
-  }
+  rc = capture_one(ctx, fr, P);
+  if (rc != GRCA_OK) return rc;
   CastRecord& R = ws->rec[0];
   R.ids = fr->ids;
   R.rays = P.rays;
@@ -1315,10 +1310,9 @@ extern "C" grca_status grca_frame_create(grca_context* ctx, uint32_t scene_id,
     grca_status rc = ws_init(ctx, fr->ws);
     if (rc == GRCA_OK && hipStreamCreateWithFlags(&fr->cap_stream, hipStreamNonBlocking) != hipSuccess)
       rc = fail(ctx, GRCA_ERR_DEVICE, "stream creation failed");
-    for (int i = 0; i < GRCA_FRAME_RING && rc == GRCA_OK; ++i)
-      for (int k = 0; k < 7 && rc == GRCA_OK; ++k)
-        if (hipEventCreate(&fr->tev[i][k]) != hipSuccess)
-          rc = fail(ctx, GRCA_ERR_DEVICE, "event creation failed");
+    for (int k = 0; k < 7 && rc == GRCA_OK; ++k)
+      if (hipEventCreate(&fr->tev[k]) != hipSuccess)
+        rc = fail(ctx, GRCA_ERR_DEVICE, "event creation failed");
     if (rc == GRCA_OK) rc = capture_frame(ctx, fr);
     if (rc != GRCA_OK) {
       grca_frame_destroy(fr);
@@ -1343,8 +1337,7 @@ extern "C" grca_status grca_frame_launch(grca_frame* fr, const float* instance_m
     if (ws->rec[0].live && ws->rec[0].st != st) HIPCHK(hipStreamWaitEvent(st, ws->ev[0], 0));
     grca_status rc = stage_pose(ctx, it->second, instance_matrices, time_s, false, st);
     if (rc != GRCA_OK) return rc;
-    HIPCHK(hipGraphLaunch(fr->exec[fr->launches % GRCA_FRAME_RING], st));
-    fr->launches++;
+    HIPCHK(hipGraphLaunch(fr->exec, st));
     HIPCHK(hipEventRecord(ws->ev[0], st));
     ws->rec[0].live = true;
     ws->rec[0].st = st;
@@ -1378,8 +1371,7 @@ extern "C" grca_status grca_frame_synchronize(grca_frame* fr, void* hip_stream) 
       rc = capture_frame(ctx, fr);
       if (rc != GRCA_OK) return rc;
       ws->rec[0].recasts++;
-      HIPCHK(hipGraphLaunch(fr->exec[fr->launches % GRCA_FRAME_RING], st));
-      fr->launches++;
+      HIPCHK(hipGraphLaunch(fr->exec, st));
       HIPCHK(hipEventRecord(ws->ev[0], st));
     }
     return fail(ctx, GRCA_ERR_CAPACITY, "frame queue kept overflowing after regrowth");
@@ -1391,26 +1383,40 @@ extern "C" void grca_frame_destroy(grca_frame* fr) {
   if (fr->ctx) (void)hipSetDevice(fr->ctx->device);
   if (fr->ws) (void)ws_quiesce(fr->ctx, fr->ws);
   destroy_graphs(fr);
-  for (int i = 0; i < GRCA_FRAME_RING; ++i)
-    for (int k = 0; k < 7; ++k)
-      if (fr->tev[i][k]) (void)hipEventDestroy(fr->tev[i][k]);
+  for (int k = 0; k < 7; ++k)
+    if (fr->tev[k]) (void)hipEventDestroy(fr->tev[k]);
   if (fr->cap_stream) (void)hipStreamDestroy(fr->cap_stream);
   if (fr->ctx && fr->ctx->last_ws == fr->ws) fr->ctx->last_ws = nullptr;
   ws_free(fr->ws);
   delete fr;
 }
 
-extern "C" grca_status grca_frame_stage_times(grca_frame* fr, uint64_t launch, float* ms6) {
+extern "C" grca_status grca_frame_profile(grca_frame* fr, const float* instance_matrices,
+                                          double time_s, void* hip_stream, float* ms6) {
   if (!fr || !fr->ctx || !ms6) return GRCA_ERR_INVALID_ARG;
   grca_context* ctx = fr->ctx;
   GUARD({
-    if (!fr->timed) return fail(ctx, GRCA_ERR_DEVICE, "stage timing unavailable on this device");
-    if (launch >= fr->launches || launch + GRCA_FRAME_RING < fr->launches)
-      return fail(ctx, GRCA_ERR_INVALID_ARG, "launch not among the last GRCA_FRAME_RING");
     HIPCHK(hipSetDevice(ctx->device));
-    hipEvent_t* ev = fr->tev[launch % GRCA_FRAME_RING];
-    HIPCHK(hipEventSynchronize(ev[6]));
-    for (int k = 0; k < 6; ++k) HIPCHK(hipEventElapsedTime(&ms6[k], ev[k], ev[k + 1]));
+    auto it = ctx->scenes.find(fr->scene_id);
+    if (it == ctx->scenes.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "frame scene was released");
+    if (!std::isfinite(time_s)) return fail(ctx, GRCA_ERR_INVALID_ARG, "time not finite");
+    hipStream_t st = as_stream(hip_stream);
+    grca_workspace* ws = fr->ws;
+    if (ws->rec[0].live && ws->rec[0].st != st) HIPCHK(hipStreamWaitEvent(st, ws->ev[0], 0));
+    grca_status rc = stage_pose(ctx, it->second, instance_matrices, time_s, false, st);
+    if (rc != GRCA_OK) return rc;
+    Plan P;
+    rc = frame_plan(ctx, fr, P);
+    if (rc != GRCA_OK) return rc;
+    rc = enqueue_frame(ctx, fr, P, st, fr->tev);
+    if (rc != GRCA_OK) return rc;
+    HIPCHK(hipEventRecord(ws->ev[0], st));
+    ws->rec[0].live = true;
+    ws->rec[0].st = st;
+    ws->last_slot = 0;
+    ctx->last_ws = ws;
+    HIPCHK(hipEventSynchronize(fr->tev[6]));
+    for (int k = 0; k < 6; ++k) HIPCHK(hipEventElapsedTime(&ms6[k], fr->tev[k], fr->tev[k + 1]));
     return GRCA_OK;
   })
 }

@@ -112,7 +112,7 @@ def load() -> ctypes.CDLL:
         "grca_frame_launch": ([P, P, ctypes.c_double, P], ctypes.c_int),
         "grca_frame_synchronize": ([P, P], ctypes.c_int),
         "grca_frame_destroy": ([P], None),
-        "grca_frame_stage_times": ([P, U64, P], ctypes.c_int),
+        "grca_frame_profile": ([P, P, ctypes.c_double, P, P], ctypes.c_int),
         "grca_workspace_create": ([P, U64, U64, ctypes.POINTER(P), ctypes.POINTER(U64)],
                                   ctypes.c_int),
         "grca_workspace_destroy": ([P], None),
@@ -134,7 +134,7 @@ def exported_symbols() -> list[str]:
         "grca_sensor_config", "grca_sensor_release", "grca_cast", "grca_synchronize",
         "grca_last_stats", "grca_get_options", "grca_set_options", "grca_frame_create",
         "grca_frame_launch", "grca_frame_synchronize", "grca_frame_destroy",
-        "grca_frame_stage_times",
+        "grca_frame_profile",
         "grca_workspace_create", "grca_workspace_destroy", "grca_cast_ws",
         "grca_workspace_synchronize",
     ]
@@ -322,12 +322,15 @@ def grca_frame_destroy(frame):
 
 
 STAGES = ("pose", "init", "bounds", "expand", "isect", "resolve")
-FRAME_RING = 4
 
 
-def grca_frame_stage_times(ctx, frame, launch: int) -> dict:
+def grca_frame_profile(ctx, frame, matrices, time_s, stream=None) -> dict:
+    """Run one frame stage by stage with events between stages; per-stage ms."""
+    if matrices is not None:
+        matrices = np.ascontiguousarray(matrices, np.float32).reshape(-1, 12)
     ms = np.zeros(6, np.float32)
-    _check(ctx, load().grca_frame_stage_times(frame, int(launch), _ptr(ms)))
+    _check(ctx, load().grca_frame_profile(frame, _ptr(matrices), float(time_s), _stream(stream),
+                                          _ptr(ms)))
     return dict(zip(STAGES, (float(x) for x in ms)))
 
 

@@ -105,8 +105,11 @@ def test_frame_replays_match_eager_and_oracle(torch, small_dyn):
                 d_e, t_e = ctx.cast_host(ids, n)
                 assert np.array_equal(t_f, t_e), f"frame {frame}: graph != eager"
                 assert np.array_equal(d_f.view(np.uint32), d_e.view(np.uint32))
-                times = grca.grca_frame_stage_times(ctx.h, fr, frame)
+                times = grca.grca_frame_profile(ctx.h, fr, sc.instance_matrices(frame),
+                                                synth.deform_time(frame), st)
                 assert all(v >= 0 for v in times.values())
+                assert np.array_equal(tri.cpu().numpy().view(np.uint32), t_f), \
+                    "profiled frame != graph frame"
                 if frame in (0, 4):
                     v_or = oracle_pose(sc, frame)
                     _sample_parity(small_dyn.sensors, v_or, sc.indices, d_f, t_f, 24, frame,
