@@ -1091,7 +1091,7 @@ extern "C" grca_status grca_last_stats(grca_context* ctx, grca_stats* out) {
     const CastRecord& R = ws->rec[slot];
     out->rays = R.rays;
     out->pairs_tested = R.pairs;
-    out->rect_items = c.n_rect;
+    out->rect_items = c.n_items >= c.n_rows ? c.n_items - c.n_rows : 0;
     out->large_records = c.n_large;
     out->row_items = c.n_rows;
     out->rtic = c.rtic;

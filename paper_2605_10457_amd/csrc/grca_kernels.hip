@@ -36,6 +36,8 @@ constexpr float MARGIN_AZ_POLE = 1e-6f;
 constexpr float S_POLE = 0.9999f;
 // Angular margin (sine) of the per-channel arcs of the large class.
 constexpr double SIN_M = 4e-6;
+// Work items claimed per atomic ticket by one wave of the intersection kernel.
+constexpr uint32_t ITEMS_PER_TICKET = 256;
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
 
@@ -175,22 +177,36 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
     if (s_lo < 0.0f) s_lo = fmaxf(s_lo * kb, -1.0f);
     // Vertical axis through the origin vs the triangle's horizontal projection.
     if (need_pole) {
-    float e[3], tol[3];
+      // The projection can only surround the axis if its bounding box holds
+      // the origin (margin well above the FP32 error of the local coordinates).
+      const float mg = 1e-6f * sqrtf(fmaxf(r2[0], fmaxf(r2[1], r2[2])));
+      const bool box_out = (x[0] > mg && x[1] > mg && x[2] > mg) ||
+                           (x[0] < -mg && x[1] < -mg && x[2] < -mg) ||
+                           (y[0] > mg && y[1] > mg && y[2] > mg) ||
+                           (y[0] < -mg && y[1] < -mg && y[2] < -mg);
+      if (!box_out) {
+        // 2D edge functions q_k x (q_{k+1} - q_k), the edge taken from the
+        // world-space vertex difference so that no cancellation sets the error
+        float e[3], tol[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int k1 = (k + 1) % 3;
-      e[k] = x[k] * y[k1] - x[k1] * y[k];
-      tol[k] = 1e-5f * (fabsf(x[k]) + fabsf(y[k])) * (fabsf(x[k1]) + fabsf(y[k1]));
-    }
-    const bool in_pos = e[0] >= -tol[0] && e[1] >= -tol[1] && e[2] >= -tol[2];
-    const bool in_neg = e[0] <= tol[0] && e[1] <= tol[1] && e[2] <= tol[2];
-    if (in_pos || in_neg) {
-      full = true;
-      const bool up = z[0] > 0.0f && z[1] > 0.0f && z[2] > 0.0f;
-      const bool dn = z[0] < 0.0f && z[1] < 0.0f && z[2] < 0.0f;
-      if (!dn) s_hi = 1.0f;
-      if (!up) s_lo = -1.0f;
-    }
+        for (int k = 0; k < 3; ++k) {
+          const int k1 = (k + 1) % 3;
+          const float ex = vx[k1] - vx[k], ey = vy[k1] - vy[k], ez = vz[k1] - vz[k];
+          const float dxl = fmaf(ex, s.f[0], fmaf(ey, s.f[1], ez * s.f[2]));
+          const float dyl = fmaf(ex, s.r[0], fmaf(ey, s.r[1], ez * s.r[2]));
+          e[k] = x[k] * dyl - y[k] * dxl;
+          tol[k] = 4e-6f * sqrtf(r2[k]) * (fabsf(dxl) + fabsf(dyl));
+        }
+        const bool in_pos = e[0] >= -tol[0] && e[1] >= -tol[1] && e[2] >= -tol[2];
+        const bool in_neg = e[0] <= tol[0] && e[1] <= tol[1] && e[2] <= tol[2];
+        if (in_pos || in_neg) {
+          full = true;
+          const bool up = z[0] > 0.0f && z[1] > 0.0f && z[2] > 0.0f;
+          const bool dn = z[0] < 0.0f && z[1] < 0.0f && z[2] < 0.0f;
+          if (!dn) s_hi = 1.0f;
+          if (!up) s_lo = -1.0f;
+        }
+      }
     }
   }
   const float smax_abs = fmaxf(fabsf(s_lo), fabsf(s_hi));
@@ -342,12 +358,24 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
   return x * q + (x < rem ? x : rem) + local;
 }
 
+// One thread per triangle; the loop over the observing sensors reads the
+// sensor descriptors with wave-uniform loads.  Small-class records of the
+// whole block are compacted into an LDS stage and flushed to the global
+// queue with ONE atomic reservation and coalesced stores per flush; the rare
+// large-class records are appended with one atomic per wave.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void bounds_kernel(
     const DevScene* __restrict__ scenes, uint32_t nscenes, const DevSensor* __restrict__ sens,
     uint32_t small_c, uint32_t small_r, Item* __restrict__ items, uint32_t item_cap,
     Item* __restrict__ large, uint32_t large_cap, Counters* __restrict__ cnt,
     uint32_t group_cull) {
+  constexpr int WAVES = BLOCK / 64;
+  constexpr uint32_t STAGE = 4u * BLOCK;  // <= 2 records per lane per sensor
+  __shared__ Item s_items[STAGE];
+  __shared__ uint32_t s_wcnt[WAVES];
+  __shared__ uint32_t s_staged, s_base;
+  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
   uint32_t sc = 0;
   while (sc + 1 < nscenes && b >= scenes[sc + 1].block_start) ++sc;
@@ -361,9 +389,10 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
     vx[1] = S.x[i1]; vy[1] = S.y[i1]; vz[1] = S.z[i1];
     vx[2] = S.x[i2]; vy[2] = S.y[i2]; vz[2] = S.z[i2];
   }
+  if (threadIdx.x == 0) s_staged = 0;
   // bounding sphere of the wave's triangles (AABB centre, max vertex distance)
   float gcx = 0.0f, gcy = 0.0f, gcz = 0.0f, grad = 0.0f;
-  bool any_active = __ballot(active) != 0ull;
+  const bool any_active = __ballot(active) != 0ull;
   if (group_cull && any_active) {
     const float big = 3.0e38f;
     const float mnx = wave_min(active ? fminf(vx[0], fminf(vx[1], vx[2])) : big);
@@ -385,27 +414,62 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
     }
     grad = sqrtf(wave_max(r2));
   }
+  __syncthreads();
   for (uint32_t n = S.sensor_begin; n < S.sensor_end; ++n) {
     const DevSensor& s = sens[n];
-    if (!any_active) continue;
-    GroupVerdict gv{false, true, true};
-    if (group_cull) {
-      gv = group_test(gcx, gcy, gcz, grad, s);
-      if (gv.culled) continue;
-    }
+    // wave-uniform group verdict; every wave still takes part in the barriers
+    GroupVerdict gv{!any_active, true, true};
+    if (group_cull && any_active) gv = group_test(gcx, gcy, gcz, grad, s);
     Span sp;
-    const bool ok = active && span_of(vx, vy, vz, s, small_c, small_r, gv.need_range,
-                                      gv.need_pole, sp);
+    bool ok = false;
+    if (!gv.culled) {
+      ok = active && span_of(vx, vy, vz, s, small_c, small_r, gv.need_range, gv.need_pole, sp);
+    }
     const uint32_t chan = ok ? (sp.c_from | (sp.c_count << 16)) : 0u;
     const bool is_large = ok && sp.large;
     const bool rect0 = ok && !sp.large;
     const bool rect1 = rect0 && sp.r1_count > 0;
-    Item r0{tri, chan, rect0 ? (sp.r0_start | (sp.r0_count << 16)) : 0u, n};
-    wave_push(rect0, r0, items, item_cap, &cnt->n_items, &cnt->overflow, 1u, &cnt->n_rect);
-    Item r1{tri, chan, rect1 ? (sp.r1_start | (sp.r1_count << 16)) : 0u, n};
-    wave_push(rect1, r1, items, item_cap, &cnt->n_items, &cnt->overflow, 1u, &cnt->n_rect);
     Item lg{tri, chan, 0u, n};
     wave_push(is_large, lg, large, large_cap, &cnt->n_large, &cnt->overflow, 2u, nullptr);
+    // block compaction of the small-class records into the LDS stage
+    const unsigned long long m0 = __ballot(rect0), m1 = __ballot(rect1);
+    const uint32_t c0 = (uint32_t)__popcll(m0);
+    if (lane == 0) s_wcnt[w] = c0 + (uint32_t)__popcll(m1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t acc = s_staged;
+#pragma unroll
+      for (int i = 0; i < WAVES; ++i) {
+        const uint32_t t = s_wcnt[i];
+        s_wcnt[i] = acc;
+        acc += t;
+      }
+      s_staged = acc;
+    }
+    __syncthreads();
+    const uint32_t wb = s_wcnt[w];
+    const unsigned long long lt = __lanemask_lt();
+    if (rect0) s_items[wb + (uint32_t)__popcll(m0 & lt)] =
+        Item{tri, chan, sp.r0_start | (sp.r0_count << 16), n};
+    if (rect1) s_items[wb + c0 + (uint32_t)__popcll(m1 & lt)] =
+        Item{tri, chan, sp.r1_start | (sp.r1_count << 16), n};
+    __syncthreads();
+    const uint32_t staged = s_staged;
+    if (staged > STAGE - 2u * BLOCK || (n + 1 == S.sensor_end && staged > 0)) {
+      if (threadIdx.x == 0) s_base = atomicAdd(&cnt->n_items, staged);
+      __syncthreads();
+      const uint32_t base = s_base;
+      bool ovf = false;
+      for (uint32_t i = threadIdx.x; i < staged; i += BLOCK) {
+        const uint32_t slot = base + i;
+        if (slot < item_cap) items[slot] = s_items[i];
+        else ovf = true;
+      }
+      if (ovf) atomicOr(&cnt->overflow, 1u);
+      __syncthreads();
+      if (threadIdx.x == 0) s_staged = 0;
+      __syncthreads();
+    }
   }
 }
 
@@ -417,44 +481,35 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
 // A_k = cos(phi) |n_k,xy|.  Each edge gives an arc (or everything / nothing);
 // their intersection is the channel's exact span, with no seam or CW/CCW
 // ambiguity.  Computed in FP64.
-struct ArcSet {
-  int n;
-  double lo[6], hi[6];
-};
-
-__device__ inline void arc_intersect(ArcSet& A, double xl, double xh) {
-  ArcSet out;
-  out.n = 0;
-  for (int i = 0; i < A.n; ++i) {
-    const double p0 = A.lo[i], p1 = A.hi[i];
-    // shift the arc so that its start lies in (p0 - 2 pi, p0]
-    const double k = ceil((xl - p0) / TWO_PI);
-    const double s0 = xl - k * TWO_PI, s1 = xh - k * TWO_PI;
-    for (int c = 0; c < 2; ++c) {
-      const double q0 = s0 + c * TWO_PI, q1 = s1 + c * TWO_PI;
-      const double l = fmax(p0, q0), h = fmin(p1, q1);
-      if (l <= h) {
-        if (out.n < 6) {
-          out.lo[out.n] = l; out.hi[out.n] = h; ++out.n;
-        } else {  // cannot happen geometrically (at most 3 pieces); stay conservative
-          out.lo[5] = fmin(out.lo[5], l); out.hi[5] = fmax(out.hi[5], h);
-        }
-      }
-    }
-  }
-  A = out;
+// Intersection of the angular piece [p0, p1] (width <= 2 pi) with the arc
+// [xl, xh] (width <= 2 pi): up to two pieces, written to (o0) and (o1).
+__device__ inline void piece_cap_arc(bool pv, double p0, double p1, double xl, double xh,
+                                     bool& v0, double& l0, double& h0, bool& v1, double& l1,
+                                     double& h1) {
+  v0 = v1 = false;
+  l0 = h0 = l1 = h1 = 0.0;
+  if (!pv) return;
+  // shift the arc so that its start lies in (p0 - 2 pi, p0]; two copies cover P
+  const double k = ceil((xl - p0) / TWO_PI);
+  const double s0 = xl - k * TWO_PI, s1 = xh - k * TWO_PI;
+  l0 = fmax(p0, s0); h0 = fmin(p1, s1); v0 = l0 <= h0;
+  l1 = fmax(p0, s0 + TWO_PI); h1 = fmin(p1, s1 + TWO_PI); v1 = l1 <= h1;
 }
 
-// Ray-index ranges [start, start + count) of one angular piece.
-__device__ inline int piece_ranges(const DevSensor& s, double lo, double hi, uint32_t* st,
-                                   uint32_t* ct) {
+// Ray-index ranges of one angular piece: (st0, ct0) and (st1, ct1), a count of
+// 0 meaning no range.  Full-spin sensors wrap the index modulo chi; partial
+// fields of view split a piece that runs past theta_0 + 2 pi.
+__device__ inline void piece_ranges(const DevSensor& s, bool valid, double lo, double hi,
+                                    uint32_t& st0, uint32_t& ct0, uint32_t& st1, uint32_t& ct1) {
+  st0 = ct0 = st1 = ct1 = 0;
+  if (!valid) return;
   // rays with azimuth offsets: nominal angle within max |offset| of the piece
   lo -= (double)s.az_noise;
   hi += (double)s.az_noise;
+  const long chi = (long)s.chi;
   if (hi - lo >= TWO_PI) {
-    st[0] = 0;
-    ct[0] = s.chi;
-    return 1;
+    ct0 = (uint32_t)chi;
+    return;
   }
   double a = lo - s.theta_start_d;
   a -= TWO_PI * floor(a / TWO_PI);
@@ -462,29 +517,90 @@ __device__ inline int piece_ranges(const DevSensor& s, double lo, double hi, uin
   const double w = hi - lo;
   const double fa = a * s.inv_dtheta_d, fb = (a + w) * s.inv_dtheta_d;
   const long ra = (long)ceil(fa), rb = (long)floor(fb);
-  const long chi = (long)s.chi;
-  int n = 0;
   if (s.wrap) {
     long c = rb - ra + 1;
     if (c > 0) {
       if (c > chi) c = chi;
-      st[0] = (uint32_t)(ra % chi);
-      ct[0] = (uint32_t)c;
-      n = 1;
+      st0 = (uint32_t)(ra % chi);
+      ct0 = (uint32_t)c;
     }
-  } else {
-    if (ra <= chi - 1 && rb >= ra) {
-      const long e0 = rb < chi - 1 ? rb : chi - 1;
-      st[n] = (uint32_t)ra; ct[n] = (uint32_t)(e0 - ra + 1); ++n;
+    return;
+  }
+  if (ra <= chi - 1 && rb >= ra) {
+    const long e0 = rb < chi - 1 ? rb : chi - 1;
+    st0 = (uint32_t)ra;
+    ct0 = (uint32_t)(e0 - ra + 1);
+  }
+  const double fb2 = (a + w - TWO_PI) * s.inv_dtheta_d;
+  if (fb2 >= 0.0) {
+    long e1 = (long)floor(fb2);
+    if (e1 > chi - 1) e1 = chi - 1;
+    st1 = 0;
+    ct1 = (uint32_t)(e1 + 1);
+  }
+}
+
+// The candidate rays of channel (cj, sj): directions on the positive side
+// of all three edge planes moved outward by SIN_M.  Each edge restricts the
+// azimuth to an arc (or not at all, or completely); the pieces of their
+// intersection are built with static slots (1 after the first arc, 2 after
+// the second, 4 after the third) so that everything stays in registers.
+struct ChannelPieces {
+  bool whole;          // every azimuth is a candidate
+  bool v[4];
+  double lo[4], hi[4];
+};
+
+__device__ inline ChannelPieces channel_pieces(const double (&nrm)[3][3], const double (&beta)[3],
+                                               const double (&hxy)[3], double cj, double sj) {
+  ChannelPieces P;
+  P.whole = true;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    P.v[i] = false;
+    P.lo[i] = P.hi[i] = 0.0;
+  }
+  bool empty = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double Ak = fabs(cj) * hxy[k];
+    const double rhs = -SIN_M - sj * nrm[k][2];
+    if (empty || rhs <= -Ak) continue;  // this edge keeps every azimuth
+    if (rhs > Ak) {                     // this edge keeps none
+      empty = true;
+      continue;
     }
-    const double fb2 = (a + w - TWO_PI) * s.inv_dtheta_d;
-    if (fb2 >= 0.0) {
-      long e1 = (long)floor(fb2);
-      if (e1 > chi - 1) e1 = chi - 1;
-      st[n] = 0; ct[n] = (uint32_t)(e1 + 1); ++n;
+    const double rho = fmin(1.0, fmax(-1.0, rhs / Ak));
+    const double wd = acos(rho);
+    // cos(phi) < 0 (a channel rounded past the pole) mirrors the azimuth
+    const double bc = cj >= 0.0 ? beta[k] : beta[k] + 3.14159265358979323846;
+    const double xl = bc - wd, xh = bc + wd;
+    if (P.whole) {
+      P.whole = false;
+      P.v[0] = true; P.lo[0] = xl; P.hi[0] = xh;
+    } else if (k == 1) {
+      bool v0, v1;
+      double l0, h0, l1, h1;
+      piece_cap_arc(P.v[0], P.lo[0], P.hi[0], xl, xh, v0, l0, h0, v1, l1, h1);
+      P.v[0] = v0; P.lo[0] = l0; P.hi[0] = h0;
+      P.v[1] = v1; P.lo[1] = l1; P.hi[1] = h1;
+    } else if (k == 2) {
+      bool v0, v1, v2, v3;
+      double l0, h0, l1, h1, l2, h2, l3, h3;
+      piece_cap_arc(P.v[0], P.lo[0], P.hi[0], xl, xh, v0, l0, h0, v1, l1, h1);
+      piece_cap_arc(P.v[1], P.lo[1], P.hi[1], xl, xh, v2, l2, h2, v3, l3, h3);
+      P.v[0] = v0; P.lo[0] = l0; P.hi[0] = h0;
+      P.v[1] = v1; P.lo[1] = l1; P.hi[1] = h1;
+      P.v[2] = v2; P.lo[2] = l2; P.hi[2] = h2;
+      P.v[3] = v3; P.lo[3] = l3; P.hi[3] = h3;
     }
   }
-  return n;
+  if (empty) {
+    P.whole = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) P.v[i] = false;
+  }
+  return P;
 }
 
 template <int WPB>
@@ -519,42 +635,26 @@ __global__ __launch_bounds__(WPB * 64) void expand_kernel(
     for (uint32_t base = 0; base < c_count; base += 64) {
       const uint32_t j = c_from + base + lane;
       const bool act = base + lane < c_count;
-      uint32_t rs[12], rc[12];
-      int nr = 0;
+      // up to 4 pieces x 2 index ranges per channel, in fixed slots
+      uint32_t rs[8], rc[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) rs[i] = rc[i] = 0;
       if (act) {
         const double2 cs = s.chan_d[j];
-        const double cj = cs.x, sj = cs.y;
-        ArcSet A;
-        A.n = 0;
-        bool empty = false, restricted = false;
+        const ChannelPieces P = channel_pieces(nrm, beta, hxy, cs.x, cs.y);
+        if (P.whole) {
+          rc[0] = s.chi;
+        } else {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const double Ak = fabs(cj) * hxy[k];
-          const double rhs = -SIN_M - sj * nrm[k][2];
-          if (rhs <= -Ak) continue;  // the whole circle satisfies this edge
-          if (rhs > Ak) { empty = true; continue; }
-          double rho = rhs / Ak;
-          rho = fmin(1.0, fmax(-1.0, rho));
-          const double w = acos(rho);
-          // cos phi < 0 (a channel rounded past the pole) mirrors the azimuth
-          const double b = cj >= 0.0 ? beta[k] : beta[k] + 3.14159265358979323846;
-          if (!restricted) {
-            A.n = 1; A.lo[0] = b - w; A.hi[0] = b + w; restricted = true;
-          } else {
-            arc_intersect(A, b - w, b + w);
-          }
-        }
-        if (!empty) {
-          if (!restricted) {
-            rs[0] = 0; rc[0] = s.chi; nr = 1;
-          } else {
-            for (int i = 0; i < A.n && nr < 11; ++i) nr += piece_ranges(s, A.lo[i], A.hi[i], rs + nr, rc + nr);
-          }
+          for (int i = 0; i < 4; ++i)
+            piece_ranges(s, P.v[i], P.lo[i], P.hi[i], rs[2 * i], rc[2 * i], rs[2 * i + 1],
+                         rc[2 * i + 1]);
         }
       }
       // count row items (ranges chopped into row_chunk rays)
       uint32_t nitems = 0;
-      for (int i = 0; i < nr; ++i) nitems += (rc[i] + row_chunk - 1) / row_chunk;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) nitems += (rc[i] + row_chunk - 1) / row_chunk;
       const uint32_t incl = wave_incl_scan(nitems);
       const uint32_t total = __shfl(incl, 63, 64);
       if (total == 0) continue;
@@ -566,7 +666,8 @@ __global__ __launch_bounds__(WPB * 64) void expand_kernel(
       wbase = __shfl(wbase, 63, 64);
       uint32_t slot = wbase + incl - nitems;
       bool ovf = false;
-      for (int i = 0; i < nr; ++i) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
         for (uint32_t o = 0; o < rc[i]; o += row_chunk) {
           const uint32_t c = min(row_chunk, rc[i] - o);
           uint32_t r0 = rs[i] + o;
@@ -607,10 +708,16 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
   const uint32_t w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   const uint32_t n_items = min(cnt->n_items, item_cap);
+  uint32_t ticket = 0, sub = ITEMS_PER_TICKET;
   for (;;) {
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(&cnt->tk_items, 64u);
-    base = __shfl(base, 0, 64);
+    // one ticket covers ITEMS_PER_TICKET items, processed 64 at a time
+    if (sub == ITEMS_PER_TICKET) {
+      if (lane == 0) ticket = atomicAdd(&cnt->tk_items, ITEMS_PER_TICKET);
+      ticket = __shfl(ticket, 0, 64);
+      sub = 0;
+    }
+    const uint32_t base = ticket + sub;
+    sub += 64;
     if (base >= n_items) break;
     const uint32_t i = base + lane;
     uint32_t count = 0;

@@ -21,7 +21,8 @@ def test_serving_mix_equals_alone():
         keep = {r.rid for r in reqs[::7]}
         srv = serving.Server(ctx, clients, slots=3, max_rays_per_slot=6 << 20,
                              item_cap=16 << 20, transient_budget_bytes=2 << 30, keep_outputs=keep)
-        rep = srv.run(reqs)
+        # arrivals compressed 20x so that requests queue up behind batches in flight
+        rep = srv.run(reqs, time_scale=0.05)
         print("serving", rep, flush=True)
         assert rep["served"] == len(reqs) and rep["rejected"] == 0
         assert rep["max_batch"] >= 2, "requests from different clients never shared a batch"
