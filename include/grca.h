@@ -225,6 +225,10 @@ typedef struct {
   uint32_t group_cull;       /* 1: cull each wave's 64 triangles per sensor with one
                                 bounding-sphere test first (the group-level cone test
                                 of section 8, "Future Work"); never changes results */
+  uint32_t inline_max;       /* small-class rectangles of at most this many candidate
+                                rays are intersected inside the bounds pass (the early
+                                pass's inline RTIC of Alg. 1); 0 sends every rectangle
+                                through the work queue; never changes results          */
   uint64_t item_capacity;    /* initial work-queue capacity (items)                    */
   uint64_t large_capacity;   /* initial large-record queue capacity                    */
 } grca_options;

@@ -114,6 +114,7 @@ struct grca_workspace {
   unsigned long long* keys = nullptr;
   uint64_t key_cap = 0;
   Item* items = nullptr;
+  Statics* item_stats = nullptr;  // statics of each queued item (same capacity)
   uint64_t item_cap = 0;
   Item* large = nullptr;
   uint64_t large_cap = 0;
@@ -202,8 +203,10 @@ grca_status ws_reserve(grca_context* ctx, grca_workspace* ws, uint64_t rays, uin
   }
   if (items > ws->item_cap) {
     dfree(ws->items);
+    dfree(ws->item_stats);
     ws->item_cap = 0;
     HIPCHK(dmalloc(&ws->items, items));
+    HIPCHK(dmalloc(&ws->item_stats, items));
     ws->item_cap = items;
   }
   if (large > ws->large_cap) {
@@ -247,6 +250,7 @@ grca_status ws_reserve(grca_context* ctx, grca_workspace* ws, uint64_t rays, uin
     ws->out_cap = outs;
   }
   ws->bytes = ws->key_cap * 8 + (ws->item_cap + ws->large_cap) * sizeof(Item) +
+              ws->item_cap * sizeof(Statics) +
               (uint64_t)RING * (ws->sens_cap * sizeof(DevSensor) + ws->scene_cap * sizeof(DevScene)) +
               ws->scratch_cap * sizeof(Statics) + ws->out_cap * 8 + sizeof(Counters);
   return GRCA_OK;
@@ -265,7 +269,7 @@ void ws_free(grca_workspace* ws) {
   if (!ws) return;
   for (int i = 0; i < RING; ++i)
     if (ws->ev[i]) (void)hipEventSynchronize(ws->ev[i]);
-  dfree(ws->keys); dfree(ws->items); dfree(ws->large); dfree(ws->cnt);
+  dfree(ws->keys); dfree(ws->items); dfree(ws->item_stats); dfree(ws->large); dfree(ws->cnt);
   dfree(ws->dsens); dfree(ws->dscenes); dfree(ws->scratch);
   dfree(ws->out_dist); dfree(ws->out_tri);
   if (ws->cnt_host) (void)hipHostFree(ws->cnt_host);
@@ -370,6 +374,10 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
   return GRCA_OK;
 }
 
+uint32_t prep_blocks(const grca_context* ctx) {
+  return (uint32_t)std::max(1, ctx->num_cu) * 32u;  // grid-stride, 8 blocks of 256 per CU x 4
+}
+
 uint32_t persist_blocks(const grca_context* ctx) {
   const uint32_t waves = (uint32_t)std::max(1, ctx->num_cu) * ctx->opt.persist_waves_cu;
   return std::max(1u, waves / 4u);
@@ -403,11 +411,12 @@ grca_status enqueue_kernels(grca_context* ctx, grca_workspace* ws, uint32_t slot
   } else {
     HIPCHK(launch_bounds(dscenes, (uint32_t)P.scenes.size(), P.total_blocks, o.bounds_block,
                          dsens, o.small_channels, o.small_rays, ws->items, icap, ws->large, lcap,
-                         ws->cnt, o.group_cull, st));
+                         ws->cnt, o.group_cull, o.inline_max, ws->keys, st));
     const uint32_t pb = persist_blocks(ctx);
     HIPCHK(launch_expand(dscenes, dsens, ws->large, ws->items, icap, lcap, o.row_chunk, ws->cnt,
                          pb, st));
-    HIPCHK(launch_isect(dscenes, dsens, ws->items, icap, ws->cnt, ws->keys, pb, st));
+    HIPCHK(launch_isect(dscenes, dsens, ws->items, ws->item_stats, icap, ws->cnt, ws->keys, pb,
+                        prep_blocks(ctx), st));
   }
   HIPCHK(launch_resolve(ws->keys, n, dist, tri, st));
   HIPCHK(hipMemcpyAsync(ws->cnt_host + slot, ws->cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -451,7 +460,7 @@ grca_status ws_drain(grca_context* ctx, grca_workspace* ws) {
       uint64_t items = ws->item_cap, large = ws->large_cap;
       rc = grown_caps(ctx, ws->cnt_host[slot], items, large);
       if (rc != GRCA_OK) { R.live = false; return rc; }
-      dfree(ws->items); ws->item_cap = 0;
+      dfree(ws->items); dfree(ws->item_stats); ws->item_cap = 0;
       dfree(ws->large); ws->large_cap = 0;
       rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
       if (rc != GRCA_OK) { R.live = false; return rc; }
@@ -503,6 +512,7 @@ extern "C" grca_status grca_create(int hip_device, grca_context** out) {
   ctx->opt.bounds_block = 256;
   ctx->opt.persist_waves_cu = 16;
   ctx->opt.group_cull = 1;
+  ctx->opt.inline_max = 16;
   ctx->opt.item_capacity = 1u << 20;
   ctx->opt.large_capacity = 1u << 16;
   ctx->def_ws = new grca_workspace();
@@ -1119,6 +1129,7 @@ extern "C" grca_status grca_set_options(grca_context* ctx, const grca_options* o
   if (b != 64 && b != 128 && b != 256 && b != 512 && b != 1024)
     return fail(ctx, GRCA_ERR_INVALID_ARG, "bounds_block must be 64, 128, 256, 512 or 1024");
   if (o->group_cull > 1) return fail(ctx, GRCA_ERR_INVALID_ARG, "group_cull must be 0 or 1");
+  if (o->inline_max > 4096) return fail(ctx, GRCA_ERR_INVALID_ARG, "inline_max outside [0, 4096]");
   if (o->persist_waves_cu < 1 || o->persist_waves_cu > 32)
     return fail(ctx, GRCA_ERR_INVALID_ARG, "persist_waves_cu outside [1, 32]");
   if (o->item_capacity < 64 || o->item_capacity > 0xFFFFFFF0ull ||
@@ -1210,12 +1221,13 @@ grca_status enqueue_frame(grca_context* ctx, grca_frame* fr, const Plan& P, hipS
   if (ev) HIPCHK(hipEventRecord(ev[2], st));
   HIPCHK(launch_bounds(ws->dscenes, (uint32_t)P.scenes.size(), P.total_blocks, o.bounds_block,
                        ws->dsens, o.small_channels, o.small_rays, ws->items, icap, ws->large,
-                       lcap, ws->cnt, o.group_cull, st));
+                       lcap, ws->cnt, o.group_cull, o.inline_max, ws->keys, st));
   if (ev) HIPCHK(hipEventRecord(ev[3], st));
   HIPCHK(launch_expand(ws->dscenes, ws->dsens, ws->large, ws->items, icap, lcap, o.row_chunk,
                        ws->cnt, pb, st));
   if (ev) HIPCHK(hipEventRecord(ev[4], st));
-  HIPCHK(launch_isect(ws->dscenes, ws->dsens, ws->items, icap, ws->cnt, ws->keys, pb, st));
+  HIPCHK(launch_isect(ws->dscenes, ws->dsens, ws->items, ws->item_stats, icap, ws->cnt,
+                      ws->keys, pb, prep_blocks(ctx), st));
   if (ev) HIPCHK(hipEventRecord(ev[5], st));
   HIPCHK(launch_resolve(ws->keys, n, fr->out_dist, fr->out_tri, st));
   if (ev) HIPCHK(hipEventRecord(ev[6], st));
@@ -1364,7 +1376,7 @@ extern "C" grca_status grca_frame_synchronize(grca_frame* fr, void* hip_stream) 
       uint64_t items = ws->item_cap, large = ws->large_cap;
       grca_status rc = grown_caps(ctx, c, items, large);
       if (rc != GRCA_OK) return rc;
-      dfree(ws->items); ws->item_cap = 0;
+      dfree(ws->items); dfree(ws->item_stats); ws->item_cap = 0;
       dfree(ws->large); ws->large_cap = 0;
       rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
       if (rc != GRCA_OK) return rc;

@@ -363,17 +363,18 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
 // whole block are compacted into an LDS stage and flushed to the global
 // queue with ONE atomic reservation and coalesced stores per flush; the rare
 // large-class records are appended with one atomic per wave.
-template <int BLOCK>
+template <int BLOCK, bool INLINE>
 __global__ __launch_bounds__(BLOCK) void bounds_kernel(
     const DevScene* __restrict__ scenes, uint32_t nscenes, const DevSensor* __restrict__ sens,
     uint32_t small_c, uint32_t small_r, Item* __restrict__ items, uint32_t item_cap,
     Item* __restrict__ large, uint32_t large_cap, Counters* __restrict__ cnt,
-    uint32_t group_cull) {
+    uint32_t group_cull, uint32_t inline_max, unsigned long long* __restrict__ keys) {
   constexpr int WAVES = BLOCK / 64;
   constexpr uint32_t STAGE = 4u * BLOCK;  // <= 2 records per lane per sensor
   __shared__ Item s_items[STAGE];
   __shared__ uint32_t s_wcnt[WAVES];
   __shared__ uint32_t s_staged, s_base;
+  __shared__ unsigned long long s_rtic;
   const uint32_t w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -389,7 +390,10 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
     vx[1] = S.x[i1]; vy[1] = S.y[i1]; vz[1] = S.z[i1];
     vx[2] = S.x[i2]; vy[2] = S.y[i2]; vz[2] = S.z[i2];
   }
-  if (threadIdx.x == 0) s_staged = 0;
+  if (threadIdx.x == 0) {
+    s_staged = 0;
+    s_rtic = 0ull;
+  }
   // bounding sphere of the wave's triangles (AABB centre, max vertex distance)
   float gcx = 0.0f, gcy = 0.0f, gcz = 0.0f, grad = 0.0f;
   const bool any_active = __ballot(active) != 0ull;
@@ -415,23 +419,64 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
     grad = sqrtf(wave_max(r2));
   }
   __syncthreads();
+  unsigned long long rtic = 0ull;  // candidates tested inline by this lane
+  unsigned long long g_cull = 0ull, g_range = ~0ull, g_pole = ~0ull;
   for (uint32_t n = S.sensor_begin; n < S.sensor_end; ++n) {
+    const uint32_t ln = (n - S.sensor_begin) & 63u;
+    if (ln == 0) {
+      // group verdicts for the next 64 sensors: lane k tests sensor n + k
+      g_cull = any_active ? 0ull : ~0ull;
+      g_range = g_pole = ~0ull;
+      if (group_cull && any_active) {
+        const uint32_t ns = n + lane;
+        GroupVerdict gv{false, true, true};
+        if (ns < S.sensor_end) gv = group_test(gcx, gcy, gcz, grad, sens[ns]);
+        g_cull = __ballot(gv.culled);
+        g_range = __ballot(gv.need_range);
+        g_pole = __ballot(gv.need_pole);
+      }
+    }
     const DevSensor& s = sens[n];
-    // wave-uniform group verdict; every wave still takes part in the barriers
-    GroupVerdict gv{!any_active, true, true};
-    if (group_cull && any_active) gv = group_test(gcx, gcy, gcz, grad, s);
+    const bool culled = (g_cull >> ln) & 1ull;
     Span sp;
     bool ok = false;
-    if (!gv.culled) {
-      ok = active && span_of(vx, vy, vz, s, small_c, small_r, gv.need_range, gv.need_pole, sp);
+    if (!culled) {
+      ok = active && span_of(vx, vy, vz, s, small_c, small_r, (g_range >> ln) & 1ull,
+                             (g_pole >> ln) & 1ull, sp);
     }
     const uint32_t chan = ok ? (sp.c_from | (sp.c_count << 16)) : 0u;
     const bool is_large = ok && sp.large;
-    const bool rect0 = ok && !sp.large;
+    bool rect0 = ok && !sp.large;
     const bool rect1 = rect0 && sp.r1_count > 0;
+    // tiny single-piece rectangles: intersect right here, from the vertices
+    // already in registers (the same statics and ray test as every path)
+    const bool tiny = INLINE && rect0 && !rect1 && sp.c_count * sp.r0_count <= inline_max;
+    if (INLINE && __ballot(tiny) != 0ull) {
+      if (tiny) {
+        Statics st;
+        if (make_statics(vx[0], vy[0], vz[0], vx[1], vy[1], vz[1], vx[2], vy[2], vz[2], s, st)) {
+          for (uint32_t c = 0; c < sp.c_count; ++c) {
+            const uint32_t ch = sp.c_from + c;
+            const float2 cp = s.chan[ch];
+            for (uint32_t r = 0; r < sp.r0_count; ++r) {
+              uint32_t ray = sp.r0_start + r;
+              if (ray >= s.chi) ray -= s.chi;
+              const uint32_t gl = ch * s.chi + ray;
+              if (s.mask && !s.mask[gl]) continue;
+              const float2 ca = s.az[ray];
+              const unsigned long long key = ray_test(st, cp.x, cp.y, ca.x, ca.y, s.dmin, s.dmax,
+                                                      tri);
+              if (key != KEY_INIT) key_min(keys, s.key_offset + gl, key);
+            }
+          }
+          rtic += (unsigned long long)(sp.c_count * sp.r0_count);
+        }
+      }
+      rect0 = rect0 && !tiny;
+    }
     Item lg{tri, chan, 0u, n};
     wave_push(is_large, lg, large, large_cap, &cnt->n_large, &cnt->overflow, 2u, nullptr);
-    // block compaction of the small-class records into the LDS stage
+    // block compaction of the remaining small-class records into the LDS stage
     const unsigned long long m0 = __ballot(rect0), m1 = __ballot(rect1);
     const uint32_t c0 = (uint32_t)__popcll(m0);
     if (lane == 0) s_wcnt[w] = c0 + (uint32_t)__popcll(m1);
@@ -471,16 +516,17 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
       __syncthreads();
     }
   }
+  // one RTIC count per block
+  if (INLINE) {
+    unsigned long long r = rtic;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+    if (lane == 0 && r) atomicAdd(&s_rtic, r);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_rtic) atomicAdd(&cnt->rtic, s_rtic);
+  }
 }
 
-// ------------------------------------------------------------------ expansion
-// Per channel j (cone of elevation phi_j), the candidate azimuths are those
-// whose direction x(theta) = (cos phi cos theta, cos phi sin theta, sin phi)
-// lies on the positive side of all three edge planes, each moved outward by
-// the angular margin SIN_M:  A_k cos(theta - beta_k) >= -SIN_M - sin(phi) n_kz,
-// A_k = cos(phi) |n_k,xy|.  Each edge gives an arc (or everything / nothing);
-// their intersection is the channel's exact span, with no seam or CW/CCW
-// ambiguity.  Computed in FP64.
 // Intersection of the angular piece [p0, p1] (width <= 2 pi) with the arc
 // [xl, xh] (width <= 2 pi): up to two pieces, written to (o0) and (o1).
 __device__ inline void piece_cap_arc(bool pv, double p0, double p1, double xl, double xh,
@@ -685,6 +731,31 @@ __global__ __launch_bounds__(WPB * 64) void expand_kernel(
   }
 }
 
+// ------------------------------------------------------------------ statics of queued items
+// One thread per queued item: gather the triangle, build its FP64 statics for
+// the item's sensor and store them beside the item.  Invalid (degenerate or
+// culled back-facing) pairs get zero normals, which no ray passes.
+__global__ __launch_bounds__(256) void prep_kernel(const DevScene* __restrict__ scenes,
+                                                   const DevSensor* __restrict__ sens,
+                                                   const Item* __restrict__ items, uint32_t item_cap,
+                                                   const Counters* __restrict__ cnt,
+                                                   Statics* __restrict__ stats) {
+  const uint32_t n_items = min(cnt->n_items, item_cap);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items;
+       i += gridDim.x * blockDim.x) {
+    const Item it = items[i];
+    const DevSensor& s = sens[it.sensor];
+    const DevScene& S = scenes[s.scene];
+    const uint32_t t = it.tri;
+    const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
+    Statics st;
+    if (!make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
+                      S.z[i2], s, st))
+      st = Statics{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1.0f, 0, 0, 0};
+    stats[i] = st;
+  }
+}
+
 // ------------------------------------------------------------------ intersection
 struct ItemInfo {
   uint32_t tri, c_from, r_start, r_count;
@@ -700,8 +771,8 @@ struct ItemInfo {
 template <int WPB>
 __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     const DevScene* __restrict__ scenes, const DevSensor* __restrict__ sens,
-    const Item* __restrict__ items, uint32_t item_cap, Counters* __restrict__ cnt,
-    unsigned long long* __restrict__ keys) {
+    const Item* __restrict__ items, const Statics* __restrict__ stats, uint32_t item_cap,
+    Counters* __restrict__ cnt, unsigned long long* __restrict__ keys) {
   __shared__ Statics st_s[WPB][64];
   __shared__ ItemInfo in_s[WPB][64];
   __shared__ uint32_t pre_s[WPB][65];
@@ -724,12 +795,9 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     if (i < n_items) {
       const Item it = items[i];
       const DevSensor& s = sens[it.sensor];
-      const DevScene& S = scenes[s.scene];
       const uint32_t t = it.tri;
-      const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
-      Statics st;
-      if (make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
-                       S.z[i2], s, st)) {
+      const Statics st = stats[i];
+      if (st.h > 0.0f) {
         const uint32_t cc = it.chan >> 16, rc = it.rays >> 16;
         count = cc * rc;
         st_s[w][lane] = st;
@@ -961,13 +1029,19 @@ hipError_t launch_init(unsigned long long* keys, uint32_t n, Counters* cnt, hipS
 hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t total_blocks,
                          uint32_t block, const DevSensor* sens, uint32_t small_c,
                          uint32_t small_r, Item* items, uint32_t item_cap, Item* large,
-                         uint32_t large_cap, Counters* cnt, uint32_t group_cull, hipStream_t st) {
+                         uint32_t large_cap, Counters* cnt, uint32_t group_cull,
+                         uint32_t inline_max, unsigned long long* keys, hipStream_t st) {
   if (total_blocks == 0) return hipSuccess;
-#define GRCA_BOUNDS_CASE(B)                                                                   \
-  case B:                                                                                     \
-    hipLaunchKernelGGL(bounds_kernel<B>, dim3(total_blocks), dim3(B), 0, st, scenes, nscenes, \
-                       sens, small_c, small_r, items, item_cap, large, large_cap, cnt,        \
-                       group_cull);                                                           \
+#define GRCA_BOUNDS_CASE(B)                                                                  \
+  case B:                                                                                    \
+    if (inline_max)                                                                          \
+      hipLaunchKernelGGL((bounds_kernel<B, true>), dim3(total_blocks), dim3(B), 0, st, scenes, \
+                         nscenes, sens, small_c, small_r, items, item_cap, large, large_cap,  \
+                         cnt, group_cull, inline_max, keys);                                  \
+    else                                                                                     \
+      hipLaunchKernelGGL((bounds_kernel<B, false>), dim3(total_blocks), dim3(B), 0, st,       \
+                         scenes, nscenes, sens, small_c, small_r, items, item_cap, large,     \
+                         large_cap, cnt, group_cull, 0u, keys);                               \
     break;
   switch (block) {
     GRCA_BOUNDS_CASE(64)
@@ -991,10 +1065,13 @@ hipError_t launch_expand(const DevScene* scenes, const DevSensor* sens, const It
 }
 
 hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, const Item* items,
-                        uint32_t item_cap, Counters* cnt, unsigned long long* keys,
-                        uint32_t nblocks, hipStream_t st) {
+                        Statics* stats, uint32_t item_cap, Counters* cnt,
+                        unsigned long long* keys, uint32_t nblocks, uint32_t prep_blocks,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(prep_kernel, dim3(prep_blocks), dim3(256), 0, st, scenes, sens, items,
+                     item_cap, cnt, stats);
   hipLaunchKernelGGL(isect_kernel<4>, dim3(nblocks), dim3(256), 0, st, scenes, sens, items,
-                     item_cap, cnt, keys);
+                     stats, item_cap, cnt, keys);
   return hipGetLastError();
 }
 

@@ -29,13 +29,15 @@ hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t tota
                          uint32_t block, const DevSensor* sens, uint32_t small_c,
                          uint32_t small_r, Item* items, uint32_t item_cap, Item* large,
                          uint32_t large_cap, Counters* cnt, uint32_t group_cull,
-                         hipStream_t st);
+                         uint32_t inline_max, unsigned long long* keys, hipStream_t st);
 hipError_t launch_expand(const DevScene* scenes, const DevSensor* sens, const Item* large,
                          Item* items, uint32_t item_cap, uint32_t large_cap, uint32_t row_chunk,
                          Counters* cnt, uint32_t nblocks, hipStream_t st);
+// prep_kernel (statics of every queued item) followed by isect_kernel
 hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, const Item* items,
-                        uint32_t item_cap, Counters* cnt, unsigned long long* keys,
-                        uint32_t nblocks, hipStream_t st);
+                        Statics* stats, uint32_t item_cap, Counters* cnt,
+                        unsigned long long* keys, uint32_t nblocks, uint32_t prep_blocks,
+                        hipStream_t st);
 hipError_t launch_allpairs(const DevScene* scenes, const DevSensor* sens, uint32_t sensor,
                            uint32_t ntri, uint32_t nrays, Statics* scratch,
                            unsigned long long* keys, hipStream_t st);
