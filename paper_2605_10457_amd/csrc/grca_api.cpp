@@ -512,7 +512,7 @@ extern "C" grca_status grca_create(int hip_device, grca_context** out) {
   ctx->opt.bounds_block = 256;
   ctx->opt.persist_waves_cu = 16;
   ctx->opt.group_cull = 1;
-  ctx->opt.inline_max = 16;
+  ctx->opt.inline_max = 0;
   ctx->opt.item_capacity = 1u << 20;
   ctx->opt.large_capacity = 1u << 16;
   ctx->def_ws = new grca_workspace();
