@@ -229,6 +229,10 @@ typedef struct {
                                 rays are intersected inside the bounds pass (the early
                                 pass's inline RTIC of Alg. 1); 0 sends every rectangle
                                 through the work queue; never changes results          */
+  uint32_t isect_ticket;     /* candidate pairs per ticket of the intersection pass
+                                (a wave's unit of dynamic work), 64..2^20, multiple
+                                of 64; never changes results                          */
+  uint32_t reserved;         /* must be 0                                              */
   uint64_t item_capacity;    /* initial work-queue capacity (items)                    */
   uint64_t large_capacity;   /* initial large-record queue capacity                    */
 } grca_options;

@@ -27,9 +27,10 @@ SPACE = {
     "bounds_block": [128, 256, 512],
     "persist_waves_cu": [4, 8, 16, 24, 32],
     "group_cull": [0, 1],
+    "isect_ticket": [512, 1024, 2048, 4096, 8192],
 }
 ORDER = ["group_cull", "small_channels", "small_rays", "row_chunk", "bounds_block",
-         "persist_waves_cu"]
+         "persist_waves_cu", "isect_ticket"]
 TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
 
 

@@ -115,11 +115,12 @@ struct grca_workspace {
   uint64_t key_cap = 0;
   Item* items = nullptr;
   Statics* item_stats = nullptr;  // statics of each queued item (same capacity)
+  uint32_t* item_cs = nullptr;    // first candidate index of each queued item (same capacity)
   uint64_t item_cap = 0;
   Item* large = nullptr;
   uint64_t large_cap = 0;
-  Counters* cnt = nullptr;       // device counters (cleared by every cast's init kernel)
-  Counters* cnt_host = nullptr;  // pinned, RING slots
+  Counters* cnt = nullptr;      // device counters (cleared by every cast's init kernel)
+  Summary* cnt_host = nullptr;  // pinned, RING slots: each cast's summary
   hipEvent_t ev[RING] = {};
   CastRecord rec[RING];
   uint32_t next_slot = 0;
@@ -201,12 +202,17 @@ grca_status ws_reserve(grca_context* ctx, grca_workspace* ws, uint64_t rays, uin
     HIPCHK(dmalloc(&ws->keys, rays));
     ws->key_cap = rays;
   }
+  // queues are NSHARD equal regions
+  items = (items + NSHARD - 1) / NSHARD * NSHARD;
+  large = (large + NSHARD - 1) / NSHARD * NSHARD;
   if (items > ws->item_cap) {
     dfree(ws->items);
     dfree(ws->item_stats);
+    dfree(ws->item_cs);
     ws->item_cap = 0;
     HIPCHK(dmalloc(&ws->items, items));
     HIPCHK(dmalloc(&ws->item_stats, items));
+    HIPCHK(dmalloc(&ws->item_cs, items));
     ws->item_cap = items;
   }
   if (large > ws->large_cap) {
@@ -250,7 +256,7 @@ grca_status ws_reserve(grca_context* ctx, grca_workspace* ws, uint64_t rays, uin
     ws->out_cap = outs;
   }
   ws->bytes = ws->key_cap * 8 + (ws->item_cap + ws->large_cap) * sizeof(Item) +
-              ws->item_cap * sizeof(Statics) +
+              ws->item_cap * (sizeof(Statics) + sizeof(uint32_t)) +
               (uint64_t)RING * (ws->sens_cap * sizeof(DevSensor) + ws->scene_cap * sizeof(DevScene)) +
               ws->scratch_cap * sizeof(Statics) + ws->out_cap * 8 + sizeof(Counters);
   return GRCA_OK;
@@ -259,8 +265,8 @@ grca_status ws_reserve(grca_context* ctx, grca_workspace* ws, uint64_t rays, uin
 grca_status ws_init(grca_context* ctx, grca_workspace* ws) {
   ws->ctx = ctx;
   HIPCHK(dmalloc(&ws->cnt, 1));
-  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&ws->cnt_host), RING * sizeof(Counters)));
-  std::memset(ws->cnt_host, 0, RING * sizeof(Counters));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&ws->cnt_host), RING * sizeof(Summary)));
+  std::memset(ws->cnt_host, 0, RING * sizeof(Summary));
   for (int i = 0; i < RING; ++i) HIPCHK(hipEventCreateWithFlags(&ws->ev[i], hipEventDisableTiming));
   return GRCA_OK;
 }
@@ -269,7 +275,7 @@ void ws_free(grca_workspace* ws) {
   if (!ws) return;
   for (int i = 0; i < RING; ++i)
     if (ws->ev[i]) (void)hipEventSynchronize(ws->ev[i]);
-  dfree(ws->keys); dfree(ws->items); dfree(ws->item_stats); dfree(ws->large); dfree(ws->cnt);
+  dfree(ws->keys); dfree(ws->items); dfree(ws->item_stats); dfree(ws->item_cs); dfree(ws->large); dfree(ws->cnt);
   dfree(ws->dsens); dfree(ws->dscenes); dfree(ws->scratch);
   dfree(ws->out_dist); dfree(ws->out_tri);
   if (ws->cnt_host) (void)hipHostFree(ws->cnt_host);
@@ -284,7 +290,7 @@ void ws_free(grca_workspace* ws) {
 struct Plan {
   std::vector<DevSensor> sens;
   std::vector<DevScene> scenes;
-  uint32_t total_blocks = 0;
+  uint32_t total_tiles = 0;  // 64-triangle tiles over the cast's scenes
   uint64_t rays = 0;
   uint64_t pairs = 0;
 };
@@ -317,7 +323,7 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
   });
   P.sens.resize(n);
   P.scenes.clear();
-  uint32_t blocks = 0;
+  uint64_t tiles = 0;
   for (uint32_t k = 0; k < n; ++k) {
     const uint32_t i = order[k];
     const SensorData& S = *sd[i];
@@ -326,10 +332,10 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
       const SceneData& sc = ctx->scenes.at(sid);
       DevScene ds{};
       ds.x = sc.x; ds.y = sc.y; ds.z = sc.z; ds.idx = sc.idx; ds.ntri = sc.ntri;
-      ds.block_start = blocks;
+      ds.tile_start = tiles;
       ds.sensor_begin = k;
       ds.sensor_end = k;
-      blocks += (sc.ntri + block - 1) / block;
+      tiles += (sc.ntri + 63) / 64;
       P.scenes.push_back(ds);
     }
     DevScene& cur = P.scenes.back();
@@ -370,7 +376,8 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
     }
     P.sens[k] = d;
   }
-  P.total_blocks = blocks;
+  if (tiles >= (1ull << 32)) return fail(ctx, GRCA_ERR_INVALID_ARG, "too many triangles in one cast");
+  P.total_tiles = (uint32_t)tiles;
   return GRCA_OK;
 }
 
@@ -399,8 +406,8 @@ grca_status enqueue_kernels(grca_context* ctx, grca_workspace* ws, uint32_t slot
   HIPCHK(hipMemcpyAsync(dscenes, ws->dscenes_host + (size_t)slot * ws->scene_cap,
                         P.scenes.size() * sizeof(DevScene), hipMemcpyHostToDevice, st));
   const uint32_t n = (uint32_t)P.rays;
-  const uint32_t icap = (uint32_t)std::min<uint64_t>(ws->item_cap, 0xFFFFFFFFull);
-  const uint32_t lcap = (uint32_t)std::min<uint64_t>(ws->large_cap, 0xFFFFFFFFull);
+  const uint32_t icap = (uint32_t)(ws->item_cap / NSHARD);  // per shard
+  const uint32_t lcap = (uint32_t)(ws->large_cap / NSHARD);
   HIPCHK(launch_init(ws->keys, n, ws->cnt, st));
   if (flags & GRCA_CAST_ALL_PAIRS) {
     for (uint32_t k = 0; k < P.sens.size(); ++k) {
@@ -409,28 +416,36 @@ grca_status enqueue_kernels(grca_context* ctx, grca_workspace* ws, uint32_t slot
                              ws->scratch, ws->keys, st));
     }
   } else {
-    HIPCHK(launch_bounds(dscenes, (uint32_t)P.scenes.size(), P.total_blocks, o.bounds_block,
-                         dsens, o.small_channels, o.small_rays, ws->items, icap, ws->large, lcap,
-                         ws->cnt, o.group_cull, o.inline_max, ws->keys, st));
+    HIPCHK(launch_bounds(dscenes, (uint32_t)P.scenes.size(), P.total_tiles, o.bounds_block,
+                         dsens, o.small_channels, o.small_rays, ws->items, ws->item_cs, icap,
+                         ws->large, lcap, ws->cnt, o.group_cull, o.inline_max, ws->keys, st));
     const uint32_t pb = persist_blocks(ctx);
-    HIPCHK(launch_expand(dscenes, dsens, ws->large, ws->items, icap, lcap, o.row_chunk, ws->cnt,
-                         pb, st));
-    HIPCHK(launch_isect(dscenes, dsens, ws->items, ws->item_stats, icap, ws->cnt, ws->keys, pb,
-                        prep_blocks(ctx), st));
+    HIPCHK(launch_expand(dscenes, dsens, ws->large, ws->items, ws->item_cs, icap, lcap,
+                         o.row_chunk, ws->cnt, pb, st));
+    HIPCHK(launch_isect(dscenes, dsens, ws->items, ws->item_cs, ws->item_stats, icap,
+                        o.isect_ticket, ws->cnt, ws->keys, pb, prep_blocks(ctx), st));
   }
-  HIPCHK(launch_resolve(ws->keys, n, dist, tri, st));
-  HIPCHK(hipMemcpyAsync(ws->cnt_host + slot, ws->cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIPCHK(launch_resolve(ws->keys, n, dist, tri, ws->cnt, st));
+  HIPCHK(hipMemcpyAsync(ws->cnt_host + slot, &ws->cnt->sum, sizeof(Summary),
+                        hipMemcpyDeviceToHost, st));
   HIPCHK(hipEventRecord(ws->ev[slot], st));
   return GRCA_OK;
 }
 
 // New queue capacities after an overflow, from the requested counts.
-grca_status grown_caps(grca_context* ctx, const Counters& c, uint64_t& items, uint64_t& large) {
+// A shard that overflowed asked for max_*_shard slots; every shard gets that
+// many plus a quarter.  A large-queue overflow also grows the item queue (the
+// dropped large records' rows were never counted).
+grca_status grown_caps(grca_context* ctx, const Summary& c, uint64_t& items, uint64_t& large) {
+  const uint64_t want_i = NSHARD * ((uint64_t)c.max_items_shard + c.max_items_shard / 4 + 1024);
+  const uint64_t want_l = NSHARD * ((uint64_t)c.max_large_shard + c.max_large_shard / 4 + 16);
   if (c.overflow & 2u) {
-    large = std::max<uint64_t>(large * 2, (uint64_t)c.n_large + c.n_large / 4 + 1024);
-    items = std::max<uint64_t>(items * 2, (uint64_t)c.n_items + c.n_items / 4 + 65536);
+    large = std::max<uint64_t>(large * 2, want_l);
+    items = std::max<uint64_t>(items * 2, want_i);
   }
-  if (c.overflow & 1u) items = std::max<uint64_t>(items * 2, (uint64_t)c.n_items + c.n_items / 4 + 65536);
+  if (c.overflow & 1u) items = std::max<uint64_t>(items * 2, want_i);
+  if (c.overflow & 4u)
+    return fail(ctx, GRCA_ERR_CAPACITY, "candidate pairs of one queue shard exceed 2^32");
   if (items > 0xFFFFFFF0ull || large > 0xFFFFFFF0ull)
     return fail(ctx, GRCA_ERR_CAPACITY, "work queue would exceed 2^32 entries");
   return GRCA_OK;
@@ -460,7 +475,7 @@ grca_status ws_drain(grca_context* ctx, grca_workspace* ws) {
       uint64_t items = ws->item_cap, large = ws->large_cap;
       rc = grown_caps(ctx, ws->cnt_host[slot], items, large);
       if (rc != GRCA_OK) { R.live = false; return rc; }
-      dfree(ws->items); dfree(ws->item_stats); ws->item_cap = 0;
+      dfree(ws->items); dfree(ws->item_stats); dfree(ws->item_cs); ws->item_cap = 0;
       dfree(ws->large); ws->large_cap = 0;
       rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
       if (rc != GRCA_OK) { R.live = false; return rc; }
@@ -513,6 +528,8 @@ extern "C" grca_status grca_create(int hip_device, grca_context** out) {
   ctx->opt.persist_waves_cu = 16;
   ctx->opt.group_cull = 1;
   ctx->opt.inline_max = 0;
+  ctx->opt.isect_ticket = 2048;
+  ctx->opt.reserved = 0;
   ctx->opt.item_capacity = 1u << 20;
   ctx->opt.large_capacity = 1u << 16;
   ctx->def_ws = new grca_workspace();
@@ -1097,7 +1114,7 @@ extern "C" grca_status grca_last_stats(grca_context* ctx, grca_stats* out) {
     grca_status rc = ws_drain(ctx, ws);
     if (rc != GRCA_OK) return rc;
     if (!was_live) HIPCHK(hipEventSynchronize(ws->ev[slot]));
-    const Counters& c = ws->cnt_host[slot];
+    const Summary& c = ws->cnt_host[slot];
     const CastRecord& R = ws->rec[slot];
     out->rays = R.rays;
     out->pairs_tested = R.pairs;
@@ -1130,6 +1147,9 @@ extern "C" grca_status grca_set_options(grca_context* ctx, const grca_options* o
     return fail(ctx, GRCA_ERR_INVALID_ARG, "bounds_block must be 64, 128, 256, 512 or 1024");
   if (o->group_cull > 1) return fail(ctx, GRCA_ERR_INVALID_ARG, "group_cull must be 0 or 1");
   if (o->inline_max > 4096) return fail(ctx, GRCA_ERR_INVALID_ARG, "inline_max outside [0, 4096]");
+  if (o->isect_ticket < 64 || o->isect_ticket > (1u << 20) || o->isect_ticket % 64 != 0)
+    return fail(ctx, GRCA_ERR_INVALID_ARG, "isect_ticket must be a multiple of 64 in [64, 2^20]");
+  if (o->reserved != 0) return fail(ctx, GRCA_ERR_INVALID_ARG, "reserved must be 0");
   if (o->persist_waves_cu < 1 || o->persist_waves_cu > 32)
     return fail(ctx, GRCA_ERR_INVALID_ARG, "persist_waves_cu outside [1, 32]");
   if (o->item_capacity < 64 || o->item_capacity > 0xFFFFFFF0ull ||
@@ -1208,8 +1228,8 @@ grca_status enqueue_frame(grca_context* ctx, grca_frame* fr, const Plan& P, hipS
   grca_workspace* ws = fr->ws;
   const grca_options& o = ctx->opt;
   const uint32_t n = (uint32_t)P.rays;
-  const uint32_t icap = (uint32_t)std::min<uint64_t>(ws->item_cap, 0xFFFFFFFFull);
-  const uint32_t lcap = (uint32_t)std::min<uint64_t>(ws->large_cap, 0xFFFFFFFFull);
+  const uint32_t icap = (uint32_t)(ws->item_cap / NSHARD);  // per shard
+  const uint32_t lcap = (uint32_t)(ws->large_cap / NSHARD);
   const uint32_t pb = persist_blocks(ctx);
   if (ev) HIPCHK(hipEventRecord(ev[0], st));
   if (sc.pose_in) {
@@ -1219,19 +1239,19 @@ grca_status enqueue_frame(grca_context* ctx, grca_frame* fr, const Plan& P, hipS
   if (ev) HIPCHK(hipEventRecord(ev[1], st));
   HIPCHK(launch_init(ws->keys, n, ws->cnt, st));
   if (ev) HIPCHK(hipEventRecord(ev[2], st));
-  HIPCHK(launch_bounds(ws->dscenes, (uint32_t)P.scenes.size(), P.total_blocks, o.bounds_block,
-                       ws->dsens, o.small_channels, o.small_rays, ws->items, icap, ws->large,
-                       lcap, ws->cnt, o.group_cull, o.inline_max, ws->keys, st));
+  HIPCHK(launch_bounds(ws->dscenes, (uint32_t)P.scenes.size(), P.total_tiles, o.bounds_block,
+                       ws->dsens, o.small_channels, o.small_rays, ws->items, ws->item_cs, icap,
+                       ws->large, lcap, ws->cnt, o.group_cull, o.inline_max, ws->keys, st));
   if (ev) HIPCHK(hipEventRecord(ev[3], st));
-  HIPCHK(launch_expand(ws->dscenes, ws->dsens, ws->large, ws->items, icap, lcap, o.row_chunk,
-                       ws->cnt, pb, st));
+  HIPCHK(launch_expand(ws->dscenes, ws->dsens, ws->large, ws->items, ws->item_cs, icap, lcap,
+                       o.row_chunk, ws->cnt, pb, st));
   if (ev) HIPCHK(hipEventRecord(ev[4], st));
-  HIPCHK(launch_isect(ws->dscenes, ws->dsens, ws->items, ws->item_stats, icap, ws->cnt,
-                      ws->keys, pb, prep_blocks(ctx), st));
+  HIPCHK(launch_isect(ws->dscenes, ws->dsens, ws->items, ws->item_cs, ws->item_stats, icap,
+                      o.isect_ticket, ws->cnt, ws->keys, pb, prep_blocks(ctx), st));
   if (ev) HIPCHK(hipEventRecord(ev[5], st));
-  HIPCHK(launch_resolve(ws->keys, n, fr->out_dist, fr->out_tri, st));
+  HIPCHK(launch_resolve(ws->keys, n, fr->out_dist, fr->out_tri, ws->cnt, st));
   if (ev) HIPCHK(hipEventRecord(ev[6], st));
-  HIPCHK(hipMemcpyAsync(ws->cnt_host, ws->cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ws->cnt_host, &ws->cnt->sum, sizeof(Summary), hipMemcpyDeviceToHost, st));
   return GRCA_OK;
 }
 
@@ -1368,7 +1388,7 @@ extern "C" grca_status grca_frame_synchronize(grca_frame* fr, void* hip_stream) 
     grca_workspace* ws = fr->ws;
     for (int attempt = 0; attempt < 7; ++attempt) {
       HIPCHK(hipEventSynchronize(ws->ev[0]));
-      const Counters c = ws->cnt_host[0];
+      const Summary c = ws->cnt_host[0];
       if (!c.overflow) {
         ws->rec[0].live = false;
         return GRCA_OK;
@@ -1376,7 +1396,7 @@ extern "C" grca_status grca_frame_synchronize(grca_frame* fr, void* hip_stream) 
       uint64_t items = ws->item_cap, large = ws->large_cap;
       grca_status rc = grown_caps(ctx, c, items, large);
       if (rc != GRCA_OK) return rc;
-      dfree(ws->items); dfree(ws->item_stats); ws->item_cap = 0;
+      dfree(ws->items); dfree(ws->item_stats); dfree(ws->item_cs); ws->item_cap = 0;
       dfree(ws->large); ws->large_cap = 0;
       rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
       if (rc != GRCA_OK) return rc;

@@ -61,22 +61,48 @@ struct DevScene {
   const float* z;
   const uint32_t* idx;
   uint32_t ntri;
-  uint32_t block_start;  // first bounds-pass block of this scene
+  uint32_t tile_start;   // first 64-triangle tile of this scene in the cast
   uint32_t sensor_begin; // sensor slots [sensor_begin, sensor_end) observe it
   uint32_t sensor_end;
 };
 
+// Work queues are split into NSHARD equal regions, each with its own append
+// counter and consumer ticket on a cache line of its own.  Atomics that many
+// waves aim at one address are serialised by the memory system (about 11 ns
+// apiece on gfx950, measured), so a producer wave appends to, and a consumer
+// wave takes tickets from, the shard of its own global wave index only.
+constexpr uint32_t NSHARD = 64;
+
+struct alignas(256) Shard {
+  // Item shards: reserved slots in the low word (may exceed the shard's
+  // capacity: overflow) and reserved candidate pairs in the high word, so one
+  // 64-bit atomic keeps both in the same order.  Large-record shards use the
+  // low word only.
+  unsigned long long nc;
+  uint32_t tk;              // consumer ticket (candidates for items, records for large)
+  uint32_t rows;            // row items appended by the expansion (statistic)
+  unsigned long long rtic;  // candidate pairs executed from this shard (statistic)
+  uint32_t pad[58];
+};
+static_assert(sizeof(Shard) == 256, "one shard counter per 256-byte line");
+
+// Compact per-cast summary written at the end of a cast and copied to the host.
+struct Summary {
+  uint32_t n_items;          // item slots requested over all shards
+  uint32_t n_large;          // large-class records requested
+  uint32_t n_rows;           // of n_items: row items of the expansion
+  uint32_t overflow;         // bit 0: item queue, bit 1: large queue, bit 2: candidate space
+  uint32_t max_items_shard;  // largest request of one item shard
+  uint32_t max_large_shard;  // largest request of one large-record shard
+  unsigned long long rtic;   // candidate pairs executed
+};
+
 // Device counters of one cast, cleared by the init kernel.
 struct Counters {
-  uint32_t n_items;   // reserved item slots (may exceed capacity: overflow)
-  uint32_t n_large;   // reserved large-record slots
-  uint32_t tk_large;  // ticket of the persistent expansion kernel
-  uint32_t tk_items;  // ticket of the persistent intersection kernel
-  uint32_t n_rect;    // rectangle items written by the bounds pass
-  uint32_t n_rows;    // row items written by the expansion
-  uint32_t overflow;  // bit 0: item queue, bit 1: large queue
-  uint32_t pad;
-  unsigned long long rtic;  // candidate pairs executed
+  Shard items[NSHARD];
+  Shard large[NSHARD];
+  alignas(256) uint32_t overflow;
+  alignas(256) Summary sum;
 };
 
 // Per-(triangle, origin) statics of the ray test, all in the sensor's local

@@ -15,6 +15,8 @@
 // plus the all-pairs reference, the pose (dynamic geometry) kernel and the
 // sensor-table builder.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 
@@ -36,8 +38,9 @@ constexpr float MARGIN_AZ_POLE = 1e-6f;
 constexpr float S_POLE = 0.9999f;
 // Angular margin (sine) of the per-channel arcs of the large class.
 constexpr double SIN_M = 4e-6;
-// Work items claimed per atomic ticket by one wave of the intersection kernel.
-constexpr uint32_t ITEMS_PER_TICKET = 256;
+// Candidate pairs one queue shard may hold (item candidate starts are 32-bit;
+// staying below 2^31 keeps the intersection tickets from wrapping).
+constexpr uint32_t CAND_LIMIT = 0x80000000u;
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
 
@@ -83,14 +86,14 @@ __device__ inline void wave_push(bool want, const Item& rec, Item* q, uint32_t c
 }
 
 // ------------------------------------------------------------------ init
+static_assert(NSHARD == 64, "the summary reduces one shard per lane of a wave");
+
 __global__ void init_kernel(unsigned long long* __restrict__ keys, uint32_t n,
                             Counters* __restrict__ cnt) {
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g < n) keys[g] = KEY_INIT;
-  if (g == 0) {
-    cnt->n_items = 0; cnt->n_large = 0; cnt->tk_large = 0; cnt->tk_items = 0;
-    cnt->n_rect = 0; cnt->n_rows = 0; cnt->overflow = 0; cnt->pad = 0; cnt->rtic = 0ull;
-  }
+  constexpr uint32_t WORDS = (uint32_t)(sizeof(Counters) / sizeof(uint32_t));
+  if (g < WORDS) reinterpret_cast<uint32_t*>(cnt)[g] = 0u;
 }
 
 // ------------------------------------------------------------------ bounds
@@ -358,30 +361,87 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
   return x * q + (x < rem ? x : rem) + local;
 }
 
-// One thread per triangle; the loop over the observing sensors reads the
-// sensor descriptors with wave-uniform loads.  Small-class records of the
-// whole block are compacted into an LDS stage and flushed to the global
-// queue with ONE atomic reservation and coalesced stores per flush; the rare
-// large-class records are appended with one atomic per wave.
-template <int BLOCK, bool INLINE>
-__global__ __launch_bounds__(BLOCK) void bounds_kernel(
-    const DevScene* __restrict__ scenes, uint32_t nscenes, const DevSensor* __restrict__ sens,
-    uint32_t small_c, uint32_t small_r, Item* __restrict__ items, uint32_t item_cap,
-    Item* __restrict__ large, uint32_t large_cap, Counters* __restrict__ cnt,
+// Candidate pairs of a work item (rectangle or row).
+__device__ inline uint32_t item_candidates(const Item& it) {
+  return (it.chan >> 16) * (it.rays >> 16);
+}
+
+// Append `n` records held in an LDS stage to queue shard `sh`: ONE 64-bit
+// atomic reserves both the slots and the candidate range (slots in the low
+// word, candidates in the high word, so the two stay in the same order), then
+// each record is stored with its first candidate index.  Within a shard the
+// candidate starts therefore increase with the slot, which is what lets the
+// intersection kernel hand out equal ranges of candidates.
+__device__ inline void flush_stage(const Item* stage, uint32_t n, Shard& ctr, Item* q_items,
+                                   uint32_t* q_cs, uint32_t scap, uint32_t* overflow) {
+  const uint32_t lane = lane_id();
+  uint32_t total = 0;
+  for (uint32_t r = 0; r < n; r += 64) {
+    const uint32_t i = r + lane;
+    uint32_t c = i < n ? item_candidates(stage[i]) : 0u;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+    total += c;
+  }
+  unsigned long long old = 0ull;
+  if (lane == 0)
+    old = atomicAdd(&ctr.nc, (unsigned long long)n | ((unsigned long long)total << 32));
+  old = __shfl(old, 0, 64);
+  const uint32_t base = (uint32_t)old, cbase = (uint32_t)(old >> 32);
+  // candidate index space of the shard (2^31, so tickets cannot wrap) exhausted
+  if (cbase > CAND_LIMIT - total && lane == 0) atomicOr(overflow, 4u);
+  bool ovf = false;
+  uint32_t run = cbase;
+  for (uint32_t r = 0; r < n; r += 64) {
+    const uint32_t i = r + lane;
+    Item it{};
+    uint32_t c = 0;
+    if (i < n) {
+      it = stage[i];
+      c = item_candidates(it);
+    }
+    const uint32_t incl = wave_incl_scan(c);
+    if (i < n) {
+      const uint32_t slot = base + i;
+      if (slot < scap) {
+        q_items[slot] = it;
+        q_cs[slot] = run + incl - c;
+      } else {
+        ovf = true;
+      }
+    }
+    run += __shfl(incl, 63, 64);
+  }
+  if (__ballot(ovf) != 0ull && lane == 0) atomicOr(overflow, 1u);
+}
+
+// Bounds pass, one 64-triangle tile per wave (one triangle per lane).  For
+// every sensor observing the tile's scene the wave computes the candidate
+// span of each (triangle, sensor) pair.  Small-class records are compacted
+// into the wave's own LDS stage (no block barrier) and appended to the
+// wave's item shard when the stage fills and at the end; large-class records
+// go to the wave's large-record shard with one atomic per wave and sensor.
+template <int WPB, bool INLINE>
+__global__ __launch_bounds__(WPB * 64) void bounds_kernel(
+    const DevScene* __restrict__ scenes, uint32_t nscenes, uint32_t total_tiles,
+    const DevSensor* __restrict__ sens, uint32_t small_c, uint32_t small_r,
+    Item* __restrict__ items, uint32_t* __restrict__ item_cs, uint32_t item_scap,
+    Item* __restrict__ large, uint32_t large_scap, Counters* __restrict__ cnt,
     uint32_t group_cull, uint32_t inline_max, unsigned long long* __restrict__ keys) {
-  constexpr int WAVES = BLOCK / 64;
-  constexpr uint32_t STAGE = 4u * BLOCK;  // <= 2 records per lane per sensor
-  __shared__ Item s_items[STAGE];
-  __shared__ uint32_t s_wcnt[WAVES];
-  __shared__ uint32_t s_staged, s_base;
-  __shared__ unsigned long long s_rtic;
+  constexpr uint32_t STAGE = 256;  // records; one sensor step adds at most 128
+  __shared__ Item s_items[WPB][STAGE];
   const uint32_t w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
-  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x) * WPB + w;
+  if (tile >= total_tiles) return;  // wave-uniform
+  const uint32_t shard = tile % NSHARD;
+  Item* const stage = s_items[w];
+  uint32_t staged = 0;
+
   uint32_t sc = 0;
-  while (sc + 1 < nscenes && b >= scenes[sc + 1].block_start) ++sc;
+  while (sc + 1 < nscenes && tile >= scenes[sc + 1].tile_start) ++sc;
   const DevScene& S = scenes[sc];
-  const uint32_t tri = (b - S.block_start) * BLOCK + threadIdx.x;
+  const uint32_t tri = (tile - S.tile_start) * 64u + lane;
   const bool active = tri < S.ntri;
   float vx[3] = {0, 0, 0}, vy[3] = {0, 0, 0}, vz[3] = {0, 0, 0};
   if (active) {
@@ -390,11 +450,7 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
     vx[1] = S.x[i1]; vy[1] = S.y[i1]; vz[1] = S.z[i1];
     vx[2] = S.x[i2]; vy[2] = S.y[i2]; vz[2] = S.z[i2];
   }
-  if (threadIdx.x == 0) {
-    s_staged = 0;
-    s_rtic = 0ull;
-  }
-  // bounding sphere of the wave's triangles (AABB centre, max vertex distance)
+  // bounding sphere of the tile's triangles (AABB centre, max vertex distance)
   float gcx = 0.0f, gcy = 0.0f, gcz = 0.0f, grad = 0.0f;
   const bool any_active = __ballot(active) != 0ull;
   if (group_cull && any_active) {
@@ -418,7 +474,6 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
     }
     grad = sqrtf(wave_max(r2));
   }
-  __syncthreads();
   unsigned long long rtic = 0ull;  // candidates tested inline by this lane
   unsigned long long g_cull = 0ull, g_range = ~0ull, g_pole = ~0ull;
   for (uint32_t n = S.sensor_begin; n < S.sensor_end; ++n) {
@@ -436,14 +491,11 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
         g_pole = __ballot(gv.need_pole);
       }
     }
+    if ((g_cull >> ln) & 1ull) continue;  // wave-uniform
     const DevSensor& s = sens[n];
-    const bool culled = (g_cull >> ln) & 1ull;
     Span sp;
-    bool ok = false;
-    if (!culled) {
-      ok = active && span_of(vx, vy, vz, s, small_c, small_r, (g_range >> ln) & 1ull,
-                             (g_pole >> ln) & 1ull, sp);
-    }
+    const bool ok = active && span_of(vx, vy, vz, s, small_c, small_r, (g_range >> ln) & 1ull,
+                                      (g_pole >> ln) & 1ull, sp);
     const uint32_t chan = ok ? (sp.c_from | (sp.c_count << 16)) : 0u;
     const bool is_large = ok && sp.large;
     bool rect0 = ok && !sp.large;
@@ -464,8 +516,8 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
               const uint32_t gl = ch * s.chi + ray;
               if (s.mask && !s.mask[gl]) continue;
               const float2 ca = s.az[ray];
-              const unsigned long long key = ray_test(st, cp.x, cp.y, ca.x, ca.y, s.dmin, s.dmax,
-                                                      tri);
+              const unsigned long long key =
+                  ray_test(st, cp.x, cp.y, ca.x, ca.y, s.dmin, s.dmax, tri);
               if (key != KEY_INIT) key_min(keys, s.key_offset + gl, key);
             }
           }
@@ -474,56 +526,37 @@ __global__ __launch_bounds__(BLOCK) void bounds_kernel(
       }
       rect0 = rect0 && !tiny;
     }
-    Item lg{tri, chan, 0u, n};
-    wave_push(is_large, lg, large, large_cap, &cnt->n_large, &cnt->overflow, 2u, nullptr);
-    // block compaction of the remaining small-class records into the LDS stage
+    const Item lg{tri, chan, 0u, n};
+    wave_push(is_large, lg, large + (size_t)shard * large_scap, large_scap,
+              reinterpret_cast<uint32_t*>(&cnt->large[shard].nc), &cnt->overflow, 2u, nullptr);
+    // wave compaction of the small-class records into the LDS stage
     const unsigned long long m0 = __ballot(rect0), m1 = __ballot(rect1);
-    const uint32_t c0 = (uint32_t)__popcll(m0);
-    if (lane == 0) s_wcnt[w] = c0 + (uint32_t)__popcll(m1);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t acc = s_staged;
-#pragma unroll
-      for (int i = 0; i < WAVES; ++i) {
-        const uint32_t t = s_wcnt[i];
-        s_wcnt[i] = acc;
-        acc += t;
-      }
-      s_staged = acc;
+    const uint32_t c0 = (uint32_t)__popcll(m0), c1 = (uint32_t)__popcll(m1);
+    if (c0 == 0u) continue;
+    if (staged + c0 + c1 > STAGE) {
+      wave_sync();
+      flush_stage(stage, staged, cnt->items[shard], items + (size_t)shard * item_scap,
+                  item_cs + (size_t)shard * item_scap, item_scap, &cnt->overflow);
+      wave_sync();
+      staged = 0;
     }
-    __syncthreads();
-    const uint32_t wb = s_wcnt[w];
     const unsigned long long lt = __lanemask_lt();
-    if (rect0) s_items[wb + (uint32_t)__popcll(m0 & lt)] =
+    if (rect0) stage[staged + (uint32_t)__popcll(m0 & lt)] =
         Item{tri, chan, sp.r0_start | (sp.r0_count << 16), n};
-    if (rect1) s_items[wb + c0 + (uint32_t)__popcll(m1 & lt)] =
+    if (rect1) stage[staged + c0 + (uint32_t)__popcll(m1 & lt)] =
         Item{tri, chan, sp.r1_start | (sp.r1_count << 16), n};
-    __syncthreads();
-    const uint32_t staged = s_staged;
-    if (staged > STAGE - 2u * BLOCK || (n + 1 == S.sensor_end && staged > 0)) {
-      if (threadIdx.x == 0) s_base = atomicAdd(&cnt->n_items, staged);
-      __syncthreads();
-      const uint32_t base = s_base;
-      bool ovf = false;
-      for (uint32_t i = threadIdx.x; i < staged; i += BLOCK) {
-        const uint32_t slot = base + i;
-        if (slot < item_cap) items[slot] = s_items[i];
-        else ovf = true;
-      }
-      if (ovf) atomicOr(&cnt->overflow, 1u);
-      __syncthreads();
-      if (threadIdx.x == 0) s_staged = 0;
-      __syncthreads();
-    }
+    staged += c0 + c1;
   }
-  // one RTIC count per block
+  if (staged > 0u) {
+    wave_sync();
+    flush_stage(stage, staged, cnt->items[shard], items + (size_t)shard * item_scap,
+                item_cs + (size_t)shard * item_scap, item_scap, &cnt->overflow);
+  }
   if (INLINE) {
     unsigned long long r = rtic;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
-    if (lane == 0 && r) atomicAdd(&s_rtic, r);
-    __syncthreads();
-    if (threadIdx.x == 0 && s_rtic) atomicAdd(&cnt->rtic, s_rtic);
+    if (lane == 0 && r) atomicAdd(&cnt->items[shard].rtic, r);
   }
 }
 
@@ -649,110 +682,155 @@ __device__ inline ChannelPieces channel_pieces(const double (&nrm)[3][3], const 
   return P;
 }
 
+// The shards a persistent consumer wave serves: shard (global wave index mod
+// NSHARD), or, on a grid of fewer than NSHARD waves, every shard congruent to
+// the wave index.  Each shard is drained by its own waves through the shard's
+// ticket, so no counter is shared by more than a few dozen waves.
+struct ShardWalk {
+  uint32_t first, step;
+};
+
+__device__ inline ShardWalk shard_walk(uint32_t wpb) {
+  const uint32_t gw = blockIdx.x * wpb + (threadIdx.x >> 6);
+  const uint32_t nw = gridDim.x * wpb;
+  const uint32_t step = nw < NSHARD ? nw : NSHARD;
+  return ShardWalk{gw % step, step};
+}
+
+// One wave per large-class record: lanes take the record's channels, 64 at a
+// time; each lane intersects the azimuth arcs of the three edge planes on its
+// channel and emits the resulting ray ranges, chopped into row items of at
+// most row_chunk rays, to the wave's item shard.
 template <int WPB>
 __global__ __launch_bounds__(WPB * 64) void expand_kernel(
     const DevScene* __restrict__ scenes, const DevSensor* __restrict__ sens,
-    const Item* __restrict__ large, Item* __restrict__ items, uint32_t item_cap,
-    uint32_t large_cap, uint32_t row_chunk, Counters* __restrict__ cnt) {
+    const Item* __restrict__ large, Item* __restrict__ items, uint32_t* __restrict__ item_cs,
+    uint32_t item_scap, uint32_t large_scap, uint32_t row_chunk, Counters* __restrict__ cnt) {
   const uint32_t lane = lane_id();
-  const uint32_t n_large = min(cnt->n_large, large_cap);
-  for (;;) {
-    uint32_t rec = 0;
-    if (lane == 0) rec = atomicAdd(&cnt->tk_large, 1u);
-    rec = __shfl(rec, 0, 64);
-    if (rec >= n_large) break;
-    const Item L = large[rec];
-    const DevSensor& s = sens[L.sensor];
-    const DevScene& S = scenes[s.scene];
-    const uint32_t t = L.tri;
-    const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
-    Statics st;
-    double nrm[3][3];
-    if (!make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
-                      S.z[i2], s, st, nrm))
-      continue;
-    double beta[3], hxy[3];
+  const ShardWalk sw = shard_walk(WPB);
+  const uint32_t out_shard = sw.first;
+  Item* const q_items = items + (size_t)out_shard * item_scap;
+  uint32_t* const q_cs = item_cs + (size_t)out_shard * item_scap;
+  uint32_t rows = 0;  // row items this wave appended (statistic)
+  for (uint32_t sh = sw.first; sh < NSHARD; sh += sw.step) {
+    const uint32_t n_large = min((uint32_t)cnt->large[sh].nc, large_scap);
+    const Item* const q_large = large + (size_t)sh * large_scap;
+    for (;;) {
+      uint32_t rec = 0;
+      if (lane == 0) rec = atomicAdd(&cnt->large[sh].tk, 1u);
+      rec = __shfl(rec, 0, 64);
+      if (rec >= n_large) break;
+      const Item L = q_large[rec];
+      const DevSensor& s = sens[L.sensor];
+      const DevScene& S = scenes[s.scene];
+      const uint32_t t = L.tri;
+      const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
+      Statics st;
+      double nrm[3][3];
+      if (!make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
+                        S.z[i2], s, st, nrm))
+        continue;
+      double beta[3], hxy[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      beta[k] = atan2(nrm[k][1], nrm[k][0]);
-      hxy[k] = sqrt(nrm[k][0] * nrm[k][0] + nrm[k][1] * nrm[k][1]);
-    }
-    const uint32_t c_from = L.chan & 0xFFFFu, c_count = L.chan >> 16;
-    for (uint32_t base = 0; base < c_count; base += 64) {
-      const uint32_t j = c_from + base + lane;
-      const bool act = base + lane < c_count;
-      // up to 4 pieces x 2 index ranges per channel, in fixed slots
-      uint32_t rs[8], rc[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) rs[i] = rc[i] = 0;
-      if (act) {
-        const double2 cs = s.chan_d[j];
-        const ChannelPieces P = channel_pieces(nrm, beta, hxy, cs.x, cs.y);
-        if (P.whole) {
-          rc[0] = s.chi;
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            piece_ranges(s, P.v[i], P.lo[i], P.hi[i], rs[2 * i], rc[2 * i], rs[2 * i + 1],
-                         rc[2 * i + 1]);
-        }
+      for (int k = 0; k < 3; ++k) {
+        beta[k] = atan2(nrm[k][1], nrm[k][0]);
+        hxy[k] = sqrt(nrm[k][0] * nrm[k][0] + nrm[k][1] * nrm[k][1]);
       }
-      // count row items (ranges chopped into row_chunk rays)
-      uint32_t nitems = 0;
+      const uint32_t c_from = L.chan & 0xFFFFu, c_count = L.chan >> 16;
+      for (uint32_t base = 0; base < c_count; base += 64) {
+        const uint32_t j = c_from + base + lane;
+        const bool act = base + lane < c_count;
+        // up to 4 pieces x 2 index ranges per channel, in fixed slots
+        uint32_t rs[8], rc[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) nitems += (rc[i] + row_chunk - 1) / row_chunk;
-      const uint32_t incl = wave_incl_scan(nitems);
-      const uint32_t total = __shfl(incl, 63, 64);
-      if (total == 0) continue;
-      uint32_t wbase = 0;
-      if (lane == 63) {
-        wbase = atomicAdd(&cnt->n_items, total);
-        atomicAdd(&cnt->n_rows, total);
-      }
-      wbase = __shfl(wbase, 63, 64);
-      uint32_t slot = wbase + incl - nitems;
-      bool ovf = false;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        for (uint32_t o = 0; o < rc[i]; o += row_chunk) {
-          const uint32_t c = min(row_chunk, rc[i] - o);
-          uint32_t r0 = rs[i] + o;
-          if (r0 >= s.chi) r0 -= s.chi;
-          if (slot < item_cap) {
-            items[slot] = Item{t, j | (1u << 16), r0 | (c << 16), L.sensor};
+        for (int i = 0; i < 8; ++i) rs[i] = rc[i] = 0;
+        if (act) {
+          const double2 cs = s.chan_d[j];
+          const ChannelPieces P = channel_pieces(nrm, beta, hxy, cs.x, cs.y);
+          if (P.whole) {
+            rc[0] = s.chi;
           } else {
-            ovf = true;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              piece_ranges(s, P.v[i], P.lo[i], P.hi[i], rs[2 * i], rc[2 * i], rs[2 * i + 1],
+                           rc[2 * i + 1]);
           }
-          ++slot;
         }
+        // count row items (ranges chopped into row_chunk rays) and their candidates
+        uint32_t nitems = 0, ncand = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          nitems += (rc[i] + row_chunk - 1) / row_chunk;
+          ncand += rc[i];
+        }
+        const uint32_t incl = wave_incl_scan(nitems);
+        const uint32_t cincl = wave_incl_scan(ncand);
+        const uint32_t total = __shfl(incl, 63, 64);
+        const uint32_t ctotal = __shfl(cincl, 63, 64);
+        if (total == 0) continue;
+        unsigned long long old = 0ull;
+        if (lane == 63)
+          old = atomicAdd(&cnt->items[out_shard].nc,
+                          (unsigned long long)total | ((unsigned long long)ctotal << 32));
+        old = __shfl(old, 63, 64);
+        rows += total;
+        uint32_t slot = (uint32_t)old + incl - nitems;
+        uint32_t cs = (uint32_t)(old >> 32) + cincl - ncand;
+        if ((uint32_t)(old >> 32) > CAND_LIMIT - ctotal && lane == 63)
+          atomicOr(&cnt->overflow, 4u);
+        bool ovf = false;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          for (uint32_t o = 0; o < rc[i]; o += row_chunk) {
+            const uint32_t c = min(row_chunk, rc[i] - o);
+            uint32_t r0 = rs[i] + o;
+            if (r0 >= s.chi) r0 -= s.chi;
+            if (slot < item_scap) {
+              q_items[slot] = Item{t, j | (1u << 16), r0 | (c << 16), L.sensor};
+              q_cs[slot] = cs;
+            } else {
+              ovf = true;
+            }
+            ++slot;
+            cs += c;
+          }
+        }
+        if (ovf) atomicOr(&cnt->overflow, 1u);
       }
-      if (ovf) atomicOr(&cnt->overflow, 1u);
     }
   }
+  if (lane == 0 && rows) atomicAdd(&cnt->items[out_shard].rows, rows);
 }
 
 // ------------------------------------------------------------------ statics of queued items
 // One thread per queued item: gather the triangle, build its FP64 statics for
 // the item's sensor and store them beside the item.  Invalid (degenerate or
-// culled back-facing) pairs get zero normals, which no ray passes.
+// culled back-facing) pairs get zero normals and h = -1, which no ray passes.
+// Block b serves shard b mod NSHARD (the blocks of one shard stride over it).
 __global__ __launch_bounds__(256) void prep_kernel(const DevScene* __restrict__ scenes,
                                                    const DevSensor* __restrict__ sens,
-                                                   const Item* __restrict__ items, uint32_t item_cap,
+                                                   const Item* __restrict__ items,
+                                                   uint32_t item_scap,
                                                    const Counters* __restrict__ cnt,
                                                    Statics* __restrict__ stats) {
-  const uint32_t n_items = min(cnt->n_items, item_cap);
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items;
-       i += gridDim.x * blockDim.x) {
-    const Item it = items[i];
-    const DevSensor& s = sens[it.sensor];
-    const DevScene& S = scenes[s.scene];
-    const uint32_t t = it.tri;
-    const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
-    Statics st;
-    if (!make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
-                      S.z[i2], s, st))
-      st = Statics{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1.0f, 0, 0, 0};
-    stats[i] = st;
+  const uint32_t step = gridDim.x < NSHARD ? gridDim.x : NSHARD;
+  const uint32_t per = gridDim.x / step, sub = blockIdx.x / step;
+  if (sub >= per) return;
+  for (uint32_t sh = blockIdx.x % step; sh < NSHARD; sh += step) {
+    const uint32_t n = min((uint32_t)cnt->items[sh].nc, item_scap);
+    const size_t off = (size_t)sh * item_scap;
+    for (uint32_t i = sub * 256u + threadIdx.x; i < n; i += per * 256u) {
+      const Item it = items[off + i];
+      const DevSensor& s = sens[it.sensor];
+      const DevScene& S = scenes[s.scene];
+      const uint32_t t = it.tri;
+      const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
+      Statics st;
+      if (!make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
+                        S.z[i2], s, st))
+        st = Statics{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1.0f, 0, 0, 0};
+      stats[off + i] = st;
+    }
   }
 }
 
@@ -765,107 +843,151 @@ struct ItemInfo {
   const float2* az;
   const uint8_t* mask;
   float inv_rc;
-  uint32_t pad;
+  uint32_t skip;  // candidates of the item that precede the current ticket
 };
 
+// Last slot i in [0, n) of a shard with cs[i] <= a (cs increasing, cs[0] = 0
+// <= a): a 64-way search, one probe per lane per round.
+__device__ inline uint32_t find_owner(const uint32_t* __restrict__ cs, uint32_t n, uint32_t a) {
+  const uint32_t lane = lane_id();
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1u) {
+    const uint32_t step = (hi - lo + 63u) / 64u;
+    const uint32_t p = lo + lane * step;
+    const bool le = p < hi && cs[p] <= a;  // lane 0 probes lo: always true
+    const unsigned long long m = __ballot(le);
+    lo += (uint32_t)(63 - __clzll((long long)m)) * step;
+    hi = min(lo + step, hi);
+  }
+  return lo;
+}
+
+// Persistent intersection with candidate-balanced tickets.  Every queued item
+// knows the index of its first candidate pair within its shard, so a ticket
+// is a fixed range [a, b) of candidate pairs: the wave finds the item holding
+// candidate a, then stages the items overlapping [a, b) 64 at a time (lane k
+// holds item k: statics and sensor fields in LDS, clipped to the ticket) and
+// walks the FLATTENED list of their candidates, 64 pairs per step.  Every
+// ticket costs the same whatever the sizes of the items in it.
 template <int WPB>
 __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     const DevScene* __restrict__ scenes, const DevSensor* __restrict__ sens,
-    const Item* __restrict__ items, const Statics* __restrict__ stats, uint32_t item_cap,
+    const Item* __restrict__ items, const uint32_t* __restrict__ item_cs,
+    const Statics* __restrict__ stats, uint32_t item_scap, uint32_t ticket_cands,
     Counters* __restrict__ cnt, unsigned long long* __restrict__ keys) {
   __shared__ Statics st_s[WPB][64];
   __shared__ ItemInfo in_s[WPB][64];
   __shared__ uint32_t pre_s[WPB][65];
   const uint32_t w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
-  const uint32_t n_items = min(cnt->n_items, item_cap);
-  uint32_t ticket = 0, sub = ITEMS_PER_TICKET;
-  for (;;) {
-    // one ticket covers ITEMS_PER_TICKET items, processed 64 at a time
-    if (sub == ITEMS_PER_TICKET) {
-      if (lane == 0) ticket = atomicAdd(&cnt->tk_items, ITEMS_PER_TICKET);
-      ticket = __shfl(ticket, 0, 64);
-      sub = 0;
-    }
-    const uint32_t base = ticket + sub;
-    sub += 64;
-    if (base >= n_items) break;
-    const uint32_t i = base + lane;
-    uint32_t count = 0;
-    if (i < n_items) {
-      const Item it = items[i];
-      const DevSensor& s = sens[it.sensor];
-      const uint32_t t = it.tri;
-      const Statics st = stats[i];
-      if (st.h > 0.0f) {
-        const uint32_t cc = it.chan >> 16, rc = it.rays >> 16;
-        count = cc * rc;
-        st_s[w][lane] = st;
-        ItemInfo inf;
-        inf.tri = t;
-        inf.c_from = it.chan & 0xFFFFu;
-        inf.r_start = it.rays & 0xFFFFu;
-        inf.r_count = rc;
-        inf.chi = s.chi;
-        inf.key_offset = s.key_offset;
-        inf.dmin = s.dmin;
-        inf.dmax = s.dmax;
-        inf.chan = s.chan;
-        inf.az = s.az;
-        inf.mask = s.mask;
-        inf.inv_rc = 1.0f / (float)rc;
-        inf.pad = 0;
-        in_s[w][lane] = inf;
-      }
-    }
-    const uint32_t incl = wave_incl_scan(count);
-    pre_s[w][lane + 1] = incl;
-    if (lane == 0) pre_s[w][0] = 0;
-    const uint32_t total = __shfl(incl, 63, 64);
-    if (lane == 0 && total) atomicAdd(&cnt->rtic, (unsigned long long)total);
-    wave_sync();
-    int cur = -1;
-    Statics st;
-    ItemInfo inf;
-    for (uint32_t f = lane; f < total; f += 64) {
-      // owner = last item whose prefix start <= f (pre_s[w][64] == total > f).
-      // f grows with each step, so the owner never moves backwards: keep it
-      // while its range still covers f, else bisect the items after it.
-      uint32_t lo;
-      if (cur >= 0 && pre_s[w][cur + 1] > f) {
-        lo = (uint32_t)cur;
-      } else {
-        lo = cur >= 0 ? (uint32_t)cur + 1u : 0u;
-        uint32_t hi = 64;
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (pre_s[w][mid] <= f) lo = mid; else hi = mid;
+  const ShardWalk sw = shard_walk(WPB);
+  unsigned long long rtic = 0ull;  // wave-uniform
+  for (uint32_t sh = sw.first; sh < NSHARD; sh += sw.step) {
+    const unsigned long long nc = cnt->items[sh].nc;
+    const uint32_t n_items = min((uint32_t)nc, item_scap);
+    const uint32_t n_cand = (uint32_t)(nc >> 32);
+    if (n_items == 0u || n_cand > CAND_LIMIT) continue;  // the latter is reported as overflow
+    const size_t off = (size_t)sh * item_scap;
+    const Item* const q = items + off;
+    const uint32_t* const qcs = item_cs + off;
+    const Statics* const qst = stats + off;
+    for (;;) {
+      uint32_t a = 0;
+      if (lane == 0) a = atomicAdd(&cnt->items[sh].tk, ticket_cands);
+      a = __shfl(a, 0, 64);
+      if (a >= n_cand) break;
+      const uint32_t b = n_cand - a > ticket_cands ? a + ticket_cands : n_cand;
+      for (uint32_t ib = find_owner(qcs, n_items, a); ib < n_items; ib += 64u) {
+        const uint32_t i = ib + lane;
+        uint32_t count = 0;
+        bool past = i >= n_items;  // this lane's item starts at or after b
+        if (!past) {
+          const uint32_t c0 = qcs[i];
+          past = c0 >= b;
+          if (!past) {
+            const Item it = q[i];
+            const uint32_t rc = it.rays >> 16;
+            const uint64_t e = (uint64_t)c0 + (uint64_t)((it.chan >> 16) * rc);
+            const uint32_t lo = max(c0, a);
+            const uint32_t hi = (uint32_t)min<uint64_t>(e, (uint64_t)b);
+            if (hi > lo) {
+              const Statics st = qst[i];
+              if (st.h > 0.0f) {
+                const DevSensor& s = sens[it.sensor];
+                count = hi - lo;
+                st_s[w][lane] = st;
+                ItemInfo inf;
+                inf.tri = it.tri;
+                inf.c_from = it.chan & 0xFFFFu;
+                inf.r_start = it.rays & 0xFFFFu;
+                inf.r_count = rc;
+                inf.chi = s.chi;
+                inf.key_offset = s.key_offset;
+                inf.dmin = s.dmin;
+                inf.dmax = s.dmax;
+                inf.chan = s.chan;
+                inf.az = s.az;
+                inf.mask = s.mask;
+                inf.inv_rc = 1.0f / (float)rc;
+                inf.skip = lo - c0;  // candidates of the item before this ticket
+                in_s[w][lane] = inf;
+              }
+            }
+          }
         }
-        cur = (int)lo;
-        st = st_s[w][lo];
-        inf = in_s[w][lo];
+        const bool last = __ballot(past) != 0ull;
+        const uint32_t incl = wave_incl_scan(count);
+        pre_s[w][lane + 1] = incl;
+        if (lane == 0) pre_s[w][0] = 0;
+        const uint32_t total = __shfl(incl, 63, 64);
+        rtic += total;
+        wave_sync();
+        int cur = -1;
+        Statics st;
+        ItemInfo inf;
+        for (uint32_t f = lane; f < total; f += 64) {
+          // owner = last item whose prefix start <= f (pre_s[w][64] == total > f).
+          // f grows with each step, so the owner never moves backwards: keep it
+          // while its range still covers f, else bisect the items after it.
+          uint32_t lo;
+          if (cur >= 0 && pre_s[w][cur + 1] > f) {
+            lo = (uint32_t)cur;
+          } else {
+            lo = cur >= 0 ? (uint32_t)cur + 1u : 0u;
+            uint32_t hi = 64;
+            while (hi - lo > 1) {
+              const uint32_t mid = (lo + hi) >> 1;
+              if (pre_s[w][mid] <= f) lo = mid; else hi = mid;
+            }
+            cur = (int)lo;
+            st = st_s[w][lo];
+            inf = in_s[w][lo];
+          }
+          const uint32_t local = f - pre_s[w][lo] + inf.skip;
+          uint32_t c = 0;
+          if (local >= inf.r_count) {
+            c = (uint32_t)((float)local * inf.inv_rc);
+            if (c * inf.r_count > local) --c;
+            else if ((c + 1) * inf.r_count <= local) ++c;
+          }
+          const uint32_t r = local - c * inf.r_count;
+          const uint32_t ch = inf.c_from + c;
+          uint32_t ray = inf.r_start + r;
+          if (ray >= inf.chi) ray -= inf.chi;
+          const uint32_t gl = ch * inf.chi + ray;
+          if (inf.mask && !inf.mask[gl]) continue;
+          const float2 cp = inf.chan[ch];
+          const float2 ca = inf.az[ray];
+          const unsigned long long key = ray_test(st, cp.x, cp.y, ca.x, ca.y, inf.dmin, inf.dmax,
+                                                  inf.tri);
+          if (key != KEY_INIT) key_min(keys, inf.key_offset + gl, key);
+        }
+        wave_sync();
+        if (last) break;
       }
-      const uint32_t local = f - pre_s[w][lo];
-      uint32_t c = 0;
-      if (local >= inf.r_count) {
-        c = (uint32_t)((float)local * inf.inv_rc);
-        if (c * inf.r_count > local) --c;
-        else if ((c + 1) * inf.r_count <= local) ++c;
-      }
-      const uint32_t r = local - c * inf.r_count;
-      const uint32_t ch = inf.c_from + c;
-      uint32_t ray = inf.r_start + r;
-      if (ray >= inf.chi) ray -= inf.chi;
-      const uint32_t gl = ch * inf.chi + ray;
-      if (inf.mask && !inf.mask[gl]) continue;
-      const float2 cp = inf.chan[ch];
-      const float2 ca = inf.az[ray];
-      const unsigned long long key = ray_test(st, cp.x, cp.y, ca.x, ca.y, inf.dmin, inf.dmax,
-                                              inf.tri);
-      if (key != KEY_INIT) key_min(keys, inf.key_offset + gl, key);
     }
-    wave_sync();
   }
+  if (lane == 0 && rtic) atomicAdd(&cnt->items[sw.first].rtic, rtic);
 }
 
 // ------------------------------------------------------------------ all pairs
@@ -919,8 +1041,31 @@ __global__ __launch_bounds__(256) void allpairs_kernel(const DevSensor* __restri
 
 // ------------------------------------------------------------------ resolve
 __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint32_t n,
-                               float* __restrict__ dist, uint32_t* __restrict__ tri) {
+                               float* __restrict__ dist, uint32_t* __restrict__ tri,
+                               Counters* __restrict__ cnt) {
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x < 64) {
+    // the cast's summary: totals and per-shard maxima of the queue counters
+    const uint32_t l = threadIdx.x;
+    uint32_t ni = (uint32_t)cnt->items[l].nc, nl = (uint32_t)cnt->large[l].nc;
+    uint32_t nr = cnt->items[l].rows;
+    unsigned long long rt = cnt->items[l].rtic;
+    uint32_t mi = ni, ml = nl;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      ni += __shfl_xor(ni, o, 64);
+      nl += __shfl_xor(nl, o, 64);
+      nr += __shfl_xor(nr, o, 64);
+      rt += __shfl_xor(rt, o, 64);
+      mi = max(mi, (uint32_t)__shfl_xor(mi, o, 64));
+      ml = max(ml, (uint32_t)__shfl_xor(ml, o, 64));
+    }
+    if (l == 0) {
+      Summary& S = cnt->sum;
+      S.n_items = ni; S.n_large = nl; S.n_rows = nr; S.overflow = cnt->overflow;
+      S.max_items_shard = mi; S.max_large_shard = ml; S.rtic = rt;
+    }
+  }
   if (g >= n) return;
   const unsigned long long k = keys[g];
   const uint32_t hi = (uint32_t)(k >> 32);
@@ -1021,28 +1166,32 @@ __global__ void copy_range_kernel(const float* __restrict__ src, float* __restri
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 hipError_t launch_init(unsigned long long* keys, uint32_t n, Counters* cnt, hipStream_t st) {
-  const uint32_t nb = cdiv(n > 0 ? n : 1, 256);
+  constexpr uint32_t WORDS = (uint32_t)(sizeof(Counters) / sizeof(uint32_t));
+  const uint32_t nb = cdiv(n > WORDS ? n : WORDS, 256);
   hipLaunchKernelGGL(init_kernel, dim3(nb), dim3(256), 0, st, keys, n, cnt);
   return hipGetLastError();
 }
 
-hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t total_blocks,
-                         uint32_t block, const DevSensor* sens, uint32_t small_c,
-                         uint32_t small_r, Item* items, uint32_t item_cap, Item* large,
-                         uint32_t large_cap, Counters* cnt, uint32_t group_cull,
+hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t total_tiles,
+                         uint32_t block, const DevSensor* sens, uint32_t small_c, uint32_t small_r,
+                         Item* items, uint32_t* item_cs, uint32_t item_scap, Item* large,
+                         uint32_t large_scap, Counters* cnt, uint32_t group_cull,
                          uint32_t inline_max, unsigned long long* keys, hipStream_t st) {
-  if (total_blocks == 0) return hipSuccess;
-#define GRCA_BOUNDS_CASE(B)                                                                  \
-  case B:                                                                                    \
-    if (inline_max)                                                                          \
-      hipLaunchKernelGGL((bounds_kernel<B, true>), dim3(total_blocks), dim3(B), 0, st, scenes, \
-                         nscenes, sens, small_c, small_r, items, item_cap, large, large_cap,  \
-                         cnt, group_cull, inline_max, keys);                                  \
-    else                                                                                     \
-      hipLaunchKernelGGL((bounds_kernel<B, false>), dim3(total_blocks), dim3(B), 0, st,       \
-                         scenes, nscenes, sens, small_c, small_r, items, item_cap, large,     \
-                         large_cap, cnt, group_cull, 0u, keys);                               \
-    break;
+  if (total_tiles == 0) return hipSuccess;
+#define GRCA_BOUNDS_CASE(B)                                                                   \
+  case B: {                                                                                   \
+    constexpr uint32_t W = B / 64;                                                            \
+    const uint32_t nb = cdiv(total_tiles, W);                                                 \
+    if (inline_max)                                                                           \
+      hipLaunchKernelGGL((bounds_kernel<W, true>), dim3(nb), dim3(B), 0, st, scenes, nscenes,  \
+                         total_tiles, sens, small_c, small_r, items, item_cs, item_scap, large, \
+                         large_scap, cnt, group_cull, inline_max, keys);                       \
+    else                                                                                      \
+      hipLaunchKernelGGL((bounds_kernel<W, false>), dim3(nb), dim3(B), 0, st, scenes, nscenes, \
+                         total_tiles, sens, small_c, small_r, items, item_cs, item_scap, large, \
+                         large_scap, cnt, group_cull, 0u, keys);                               \
+    break;                                                                                    \
+  }
   switch (block) {
     GRCA_BOUNDS_CASE(64)
     GRCA_BOUNDS_CASE(128)
@@ -1057,21 +1206,21 @@ hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t tota
 }
 
 hipError_t launch_expand(const DevScene* scenes, const DevSensor* sens, const Item* large,
-                         Item* items, uint32_t item_cap, uint32_t large_cap, uint32_t row_chunk,
-                         Counters* cnt, uint32_t nblocks, hipStream_t st) {
+                         Item* items, uint32_t* item_cs, uint32_t item_scap, uint32_t large_scap,
+                         uint32_t row_chunk, Counters* cnt, uint32_t nblocks, hipStream_t st) {
   hipLaunchKernelGGL(expand_kernel<4>, dim3(nblocks), dim3(256), 0, st, scenes, sens, large,
-                     items, item_cap, large_cap, row_chunk, cnt);
+                     items, item_cs, item_scap, large_scap, row_chunk, cnt);
   return hipGetLastError();
 }
 
 hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, const Item* items,
-                        Statics* stats, uint32_t item_cap, Counters* cnt,
-                        unsigned long long* keys, uint32_t nblocks, uint32_t prep_blocks,
-                        hipStream_t st) {
+                        const uint32_t* item_cs, Statics* stats, uint32_t item_scap,
+                        uint32_t ticket_cands, Counters* cnt, unsigned long long* keys,
+                        uint32_t nblocks, uint32_t prep_blocks, hipStream_t st) {
   hipLaunchKernelGGL(prep_kernel, dim3(prep_blocks), dim3(256), 0, st, scenes, sens, items,
-                     item_cap, cnt, stats);
+                     item_scap, cnt, stats);
   hipLaunchKernelGGL(isect_kernel<4>, dim3(nblocks), dim3(256), 0, st, scenes, sens, items,
-                     stats, item_cap, cnt, keys);
+                     item_cs, stats, item_scap, ticket_cands, cnt, keys);
   return hipGetLastError();
 }
 
@@ -1088,9 +1237,9 @@ hipError_t launch_allpairs(const DevScene* scenes, const DevSensor* sens, uint32
 }
 
 hipError_t launch_resolve(const unsigned long long* keys, uint32_t n, float* dist, uint32_t* tri,
-                          hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(resolve_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, keys, n, dist, tri);
+                          Counters* cnt, hipStream_t st) {
+  hipLaunchKernelGGL(resolve_kernel, dim3(cdiv(n > 0 ? n : 1, 256)), dim3(256), 0, st, keys, n,
+                     dist, tri, cnt);
   return hipGetLastError();
 }
 

@@ -25,24 +25,29 @@ struct DeformParam {
 };
 
 hipError_t launch_init(unsigned long long* keys, uint32_t n, Counters* cnt, hipStream_t st);
-hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t total_blocks,
-                         uint32_t block, const DevSensor* sens, uint32_t small_c,
-                         uint32_t small_r, Item* items, uint32_t item_cap, Item* large,
-                         uint32_t large_cap, Counters* cnt, uint32_t group_cull,
+// Queues (items, statics, large records) are NSHARD regions of `*_scap`
+// entries each; `total_tiles` counts 64-triangle tiles over the cast's scenes.
+// `item_cs` holds each item's first candidate index within its shard.
+hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t total_tiles,
+                         uint32_t block, const DevSensor* sens, uint32_t small_c, uint32_t small_r,
+                         Item* items, uint32_t* item_cs, uint32_t item_scap, Item* large,
+                         uint32_t large_scap, Counters* cnt, uint32_t group_cull,
                          uint32_t inline_max, unsigned long long* keys, hipStream_t st);
 hipError_t launch_expand(const DevScene* scenes, const DevSensor* sens, const Item* large,
-                         Item* items, uint32_t item_cap, uint32_t large_cap, uint32_t row_chunk,
-                         Counters* cnt, uint32_t nblocks, hipStream_t st);
-// prep_kernel (statics of every queued item) followed by isect_kernel
+                         Item* items, uint32_t* item_cs, uint32_t item_scap, uint32_t large_scap,
+                         uint32_t row_chunk, Counters* cnt, uint32_t nblocks, hipStream_t st);
+// prep_kernel (statics of every queued item) followed by isect_kernel, whose
+// tickets are ranges of `ticket_cands` candidate pairs
 hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, const Item* items,
-                        Statics* stats, uint32_t item_cap, Counters* cnt,
-                        unsigned long long* keys, uint32_t nblocks, uint32_t prep_blocks,
-                        hipStream_t st);
+                        const uint32_t* item_cs, Statics* stats, uint32_t item_scap,
+                        uint32_t ticket_cands, Counters* cnt, unsigned long long* keys,
+                        uint32_t nblocks, uint32_t prep_blocks, hipStream_t st);
 hipError_t launch_allpairs(const DevScene* scenes, const DevSensor* sens, uint32_t sensor,
                            uint32_t ntri, uint32_t nrays, Statics* scratch,
                            unsigned long long* keys, hipStream_t st);
+// also writes the cast's Summary from the queue counters
 hipError_t launch_resolve(const unsigned long long* keys, uint32_t n, float* dist, uint32_t* tri,
-                          hipStream_t st);
+                          Counters* cnt, hipStream_t st);
 hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* rx, const float* ry,
                        const float* rz, const float* nx, const float* ny, const float* nz,
                        const float* phase, const DeformParam* groups, const double* pose_in,

@@ -75,6 +75,7 @@ class Options(ctypes.Structure):
                 ("row_chunk", ctypes.c_uint32), ("bounds_block", ctypes.c_uint32),
                 ("persist_waves_cu", ctypes.c_uint32), ("group_cull", ctypes.c_uint32),
                 ("inline_max", ctypes.c_uint32),
+                ("isect_ticket", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("item_capacity", ctypes.c_uint64),
                 ("large_capacity", ctypes.c_uint64)]
 
