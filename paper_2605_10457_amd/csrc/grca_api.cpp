@@ -57,7 +57,7 @@ struct SensorData {
   float2* chan = nullptr;
   double2* chan_d = nullptr;
   float* sin_tab = nullptr;
-  uint16_t* lut = nullptr;
+  ChanBin* lut = nullptr;
   float2* az = nullptr;
   uint8_t* mask = nullptr;
   uint32_t lut_size = 0;
@@ -361,7 +361,7 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
     d.theta_start_d = theta0;
     d.inv_dtheta_d = 1.0 / S.dtheta;
     d.period_idx_d = kTwoPi / S.dtheta;
-    d.chan = S.chan; d.chan_d = S.chan_d; d.sin_tab = S.sin_tab; d.lut = S.lut; d.az = S.az;
+    d.chan = S.chan; d.chan_d = S.chan_d; d.sin_tab = S.sin_tab; d.bins = S.lut; d.az = S.az;
     d.mask = S.mask;
     d.az_noise = S.az_noise;
     d.cull_back = 0;
@@ -961,8 +961,15 @@ extern "C" grca_status grca_sensor_config(grca_context* ctx, uint32_t sensor_id,
     sd.az_noise = az_noise;
     sd.desc.azimuth_offset_rad = nullptr;
     sd.desc.ray_mask = nullptr;
-    uint32_t lut = std::max<uint32_t>(512, 4 * s->num_channels);
-    sd.lut_size = std::min<uint32_t>(lut, 1u << 16);
+    // bins of at most a quarter of the smallest gap between channel sines, so
+    // that a channel search is almost always one table load (at most 16384)
+    double min_gap = 2.0;
+    for (uint32_t j = 0; j + 1 < s->num_channels; ++j)
+      min_gap = std::min(min_gap, std::sin((double)s->channel_elevation_rad[j + 1]) -
+                                      std::sin((double)s->channel_elevation_rad[j]));
+    double want = std::max(512.0, 4.0 * s->num_channels);
+    if (min_gap > 0.0) want = std::max(want, std::ceil(8.0 / min_gap));
+    sd.lut_size = (uint32_t)std::min(want, 16384.0);
     const uint32_t g = s->num_channels, c = s->rays_per_channel;
     auto cleanup = [&]() { free_sensor(sd); };
     hipError_t e = hipSuccess;

@@ -31,6 +31,14 @@ struct Item {
   uint32_t sensor; // sensor slot of the cast
 };
 
+// One bin of the sine -> channel lookup: the first channel j whose sine is
+// >= the bin's lower edge -1 + 2b/lut_size, and the sines of channels j, j+1,
+// j+2 (+inf past the last channel), so that a search usually needs one load.
+struct ChanBin {
+  uint32_t j;
+  float s0, s1, s2;
+};
+
 // Per-cast sensor descriptor (device memory, read with wave-uniform indices).
 struct DevSensor {
   float o[3], f[3], r[3], u[3];
@@ -48,7 +56,7 @@ struct DevSensor {
   const float2* chan;   // (cos phi_j, sin phi_j), FP32
   const double2* chan_d; // (cos phi_j, sin phi_j), FP64
   const float* sin_tab; // sin phi_j (FP32, equal to chan[j].y), ascending
-  const uint16_t* lut;  // lut[b] = first j with sin_tab[j] >= -1 + 2b/lut_size
+  const ChanBin* bins;  // lut_size bins of the sine -> channel lookup
   const float2* az;     // (cos theta_R, sin theta_R), FP32 (offsets included)
   const uint8_t* mask;  // optional active-ray mask at C * chi + R (nullptr: all on)
   float az_noise;       // max |azimuth offset| (radians), widens every azimuth span

@@ -33,7 +33,7 @@ constexpr float PI_F = 3.14159265358979323846f;
 // budget): elevation margin in sine units, azimuth margin in radians, and
 // the |sin(elevation)| beyond which the azimuth arc is taken as the full turn.
 constexpr float ETA_SIN = 4e-6f;
-constexpr float MARGIN_AZ = 1e-5f;
+constexpr float MARGIN_AZ = 2e-5f;
 constexpr float MARGIN_AZ_POLE = 1e-6f;
 constexpr float S_POLE = 0.9999f;
 // Angular margin (sine) of the per-channel arcs of the large class.
@@ -43,6 +43,22 @@ constexpr double SIN_M = 4e-6;
 constexpr uint32_t CAND_LIMIT = 0x80000000u;
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
+
+// Lane 0's value, as a wave-uniform (scalar) value (every lane active).
+__device__ inline uint32_t first_lane(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ inline unsigned long long first_lane(unsigned long long v) {
+  return (unsigned long long)first_lane((uint32_t)v) |
+         ((unsigned long long)first_lane((uint32_t)(v >> 32)) << 32);
+}
+
+// Index of the calling wave within its block, as a wave-uniform (scalar)
+// value: everything derived from it (tile, scene, sensor loop) then stays in
+// scalar registers and scalar loads.
+__device__ inline uint32_t wave_id() {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -108,13 +124,43 @@ __device__ inline uint32_t chan_search(const DevSensor& s, float x, bool strict)
   const float fb = (x + 1.0f) * (0.5f * (float)s.lut_size);
   int b = (fb > 0.0f) ? (int)fminf(fb, (float)(s.lut_size - 1)) : 0;
   b = b > 0 ? b - 1 : 0;  // one bin early: the FP32 bin index may round up
-  uint32_t j = s.lut[b];
+  const ChanBin e = s.bins[b];
+  uint32_t j = e.j;
   if (strict) {
-    while (j < s.gamma && s.sin_tab[j] <= x) ++j;
+    j += (uint32_t)(e.s0 <= x) + (uint32_t)(e.s1 <= x) + (uint32_t)(e.s2 <= x);
+    if (e.s2 <= x)  // channels closer than the bins: walk on
+      while (j < s.gamma && s.sin_tab[j] <= x) ++j;
   } else {
-    while (j < s.gamma && s.sin_tab[j] < x) ++j;
+    j += (uint32_t)(e.s0 < x) + (uint32_t)(e.s1 < x) + (uint32_t)(e.s2 < x);
+    if (e.s2 < x)
+      while (j < s.gamma && s.sin_tab[j] < x) ++j;
   }
   return j;
+}
+
+// atan2(y, x) in FP32 for the bounds pass, |error| <= 5e-7 rad for mx > 0
+// (libm's atan2f is within about 2.4e-7): reduction to t = min(|x|,|y|) /
+// max(|x|,|y|) in [0, 1] with the hardware reciprocal, atan(t) = t P(t^2)
+// with P of degree 7, then the reflections of the octant.  The coefficients
+// were fitted to atan on [0, 1] by least squares reweighted toward the
+// minimax (Lawson) error; tests/test_atan_bound.py checks the bound.
+__device__ inline float atan2_bounded(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+  const float u = t * t;
+  float p = -0.00405456498f;
+  p = fmaf(p, u, 0.0218629558f);
+  p = fmaf(p, u, -0.0559123345f);
+  p = fmaf(p, u, 0.0964219868f);
+  p = fmaf(p, u, -0.139086306f);
+  p = fmaf(p, u, 0.199465662f);
+  p = fmaf(p, u, -0.333298594f);
+  p = fmaf(p, u, 0.999999344f);
+  float r = p * t;
+  if (ay > ax) r = 1.57079637f - r;
+  if (x < 0.0f) r = 3.14159274f - r;
+  return y < 0.0f ? -r : r;
 }
 
 // Conservative candidate span of one (triangle, sensor) pair, FP32.
@@ -147,7 +193,7 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
       rc2 = fmaxf(rc2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
     }
     // |c| - r_c > D_max  <=>  |c|^2 > (D_max + r_c)^2 (both sides non-negative)
-    const float reach = dmax * (1.0f + 1e-5f) + 1e-6f + sqrtf(rc2) * 1.0001f;
+    const float reach = dmax * (1.0f + 1e-5f) + 1e-6f + __builtin_amdgcn_sqrtf(rc2) * 1.0001f;
     if (fmaf(cx, cx, fmaf(cy, cy, cz * cz)) > reach * reach * (1.0f + 1e-5f)) return false;
   }
   const float r2min = fminf(r2[0], fminf(r2[1], r2[2]));
@@ -182,7 +228,7 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
     if (need_pole) {
       // The projection can only surround the axis if its bounding box holds
       // the origin (margin well above the FP32 error of the local coordinates).
-      const float mg = 1e-6f * sqrtf(fmaxf(r2[0], fmaxf(r2[1], r2[2])));
+      const float mg = 1e-6f * __builtin_amdgcn_sqrtf(fmaxf(r2[0], fmaxf(r2[1], r2[2])));
       const bool box_out = (x[0] > mg && x[1] > mg && x[2] > mg) ||
                            (x[0] < -mg && x[1] < -mg && x[2] < -mg) ||
                            (y[0] > mg && y[1] > mg && y[2] > mg) ||
@@ -198,7 +244,7 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
           const float dxl = fmaf(ex, s.f[0], fmaf(ey, s.f[1], ez * s.f[2]));
           const float dyl = fmaf(ex, s.r[0], fmaf(ey, s.r[1], ez * s.r[2]));
           e[k] = x[k] * dyl - y[k] * dxl;
-          tol[k] = 4e-6f * sqrtf(r2[k]) * (fabsf(dxl) + fabsf(dyl));
+          tol[k] = 4e-6f * __builtin_amdgcn_sqrtf(r2[k]) * (fabsf(dxl) + fabsf(dyl));
         }
         const bool in_pos = e[0] >= -tol[0] && e[1] >= -tol[1] && e[2] >= -tol[2];
         const bool in_neg = e[0] <= tol[0] && e[1] <= tol[1] && e[2] <= tol[2];
@@ -225,9 +271,9 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
   const uint32_t chi = s.chi;
   sp.r1_start = 0; sp.r1_count = 0;
   if (!full) {
-    const float t0 = atan2f(y[0], x[0]);
-    float d1 = atan2f(y[1], x[1]) - t0;
-    float d2 = atan2f(y[2], x[2]) - t0;
+    const float t0 = atan2_bounded(y[0], x[0]);
+    float d1 = atan2_bounded(y[1], x[1]) - t0;
+    float d2 = atan2_bounded(y[2], x[2]) - t0;
     if (d1 > PI_F) d1 -= TWO_PI_F;
     if (d1 < -PI_F) d1 += TWO_PI_F;
     if (d2 > PI_F) d2 -= TWO_PI_F;
@@ -237,8 +283,10 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
     if (hi - lo > PI_F - 1e-3f) {
       full = true;
     } else {
-      const float cmin_el = sqrtf(fmaxf(1.0f - smax_abs * smax_abs, 0.0f));
-      const float m = MARGIN_AZ + MARGIN_AZ_POLE / fmaxf(cmin_el, 1e-3f) + s.az_noise;
+      // margin terms only: the hardware square root and reciprocal (1 ulp) suffice
+      const float cmin_el = __builtin_amdgcn_sqrtf(fmaxf(1.0f - smax_abs * smax_abs, 0.0f));
+      const float m = MARGIN_AZ + MARGIN_AZ_POLE * __builtin_amdgcn_rcpf(fmaxf(cmin_el, 1e-3f)) +
+                      s.az_noise;
       float a = t0 + lo - m - s.theta_start;
       a -= TWO_PI_F * floorf(a * (1.0f / TWO_PI_F));
       if (a < 0.0f) a = 0.0f;
@@ -251,7 +299,8 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
         int cnt = rb - ra + 1;
         if (cnt <= 0) return false;
         if (cnt > (int)chi) cnt = (int)chi;
-        sp.r0_start = (uint32_t)ra % chi;
+        // a lies in [0, 2 pi] up to rounding, so ra lies in [0, chi + 1]
+        sp.r0_start = (uint32_t)ra >= chi ? (uint32_t)ra - chi : (uint32_t)ra;
         sp.r0_count = (uint32_t)cnt;
       } else {
         sp.r0_count = 0;
@@ -366,51 +415,34 @@ __device__ inline uint32_t item_candidates(const Item& it) {
   return (it.chan >> 16) * (it.rays >> 16);
 }
 
-// Append `n` records held in an LDS stage to queue shard `sh`: ONE 64-bit
-// atomic reserves both the slots and the candidate range (slots in the low
-// word, candidates in the high word, so the two stay in the same order), then
-// each record is stored with its first candidate index.  Within a shard the
+// Append the `n` records of an LDS stage to an item shard: ONE 64-bit atomic
+// reserves both the slots and the candidate range (slots in the low word,
+// candidates in the high word, so the two stay in the same order); each
+// record is stored with its first candidate index, the stage's running
+// candidate prefix `pre[i]` plus the reserved base.  Within a shard the
 // candidate starts therefore increase with the slot, which is what lets the
 // intersection kernel hand out equal ranges of candidates.
-__device__ inline void flush_stage(const Item* stage, uint32_t n, Shard& ctr, Item* q_items,
-                                   uint32_t* q_cs, uint32_t scap, uint32_t* overflow) {
+__device__ inline void flush_stage(const Item* stage, const uint32_t* pre, uint32_t n,
+                                   uint32_t cands, Shard& ctr, Item* q_items, uint32_t* q_cs,
+                                   uint32_t scap, uint32_t* overflow) {
   const uint32_t lane = lane_id();
-  uint32_t total = 0;
-  for (uint32_t r = 0; r < n; r += 64) {
-    const uint32_t i = r + lane;
-    uint32_t c = i < n ? item_candidates(stage[i]) : 0u;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
-    total += c;
-  }
   unsigned long long old = 0ull;
-  if (lane == 0)
-    old = atomicAdd(&ctr.nc, (unsigned long long)n | ((unsigned long long)total << 32));
-  old = __shfl(old, 0, 64);
+  if (lane == 0) {
+    old = atomicAdd(&ctr.nc, (unsigned long long)n | ((unsigned long long)cands << 32));
+    // candidate index space of the shard (2^31, so tickets cannot wrap) exhausted
+    if ((uint32_t)(old >> 32) > CAND_LIMIT - cands) atomicOr(overflow, 4u);
+  }
+  old = first_lane(old);
   const uint32_t base = (uint32_t)old, cbase = (uint32_t)(old >> 32);
-  // candidate index space of the shard (2^31, so tickets cannot wrap) exhausted
-  if (cbase > CAND_LIMIT - total && lane == 0) atomicOr(overflow, 4u);
   bool ovf = false;
-  uint32_t run = cbase;
-  for (uint32_t r = 0; r < n; r += 64) {
-    const uint32_t i = r + lane;
-    Item it{};
-    uint32_t c = 0;
-    if (i < n) {
-      it = stage[i];
-      c = item_candidates(it);
+  for (uint32_t i = lane; i < n; i += 64) {
+    const uint32_t slot = base + i;
+    if (slot < scap) {
+      q_items[slot] = stage[i];
+      q_cs[slot] = cbase + pre[i];
+    } else {
+      ovf = true;
     }
-    const uint32_t incl = wave_incl_scan(c);
-    if (i < n) {
-      const uint32_t slot = base + i;
-      if (slot < scap) {
-        q_items[slot] = it;
-        q_cs[slot] = run + incl - c;
-      } else {
-        ovf = true;
-      }
-    }
-    run += __shfl(incl, 63, 64);
   }
   if (__ballot(ovf) != 0ull && lane == 0) atomicOr(overflow, 1u);
 }
@@ -430,13 +462,16 @@ __global__ __launch_bounds__(WPB * 64) void bounds_kernel(
     uint32_t group_cull, uint32_t inline_max, unsigned long long* __restrict__ keys) {
   constexpr uint32_t STAGE = 256;  // records; one sensor step adds at most 128
   __shared__ Item s_items[WPB][STAGE];
-  const uint32_t w = threadIdx.x >> 6;
+  __shared__ uint32_t s_pre[WPB][STAGE];  // candidates staged before each record
+  const uint32_t w = wave_id();
   const uint32_t lane = lane_id();
   const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x) * WPB + w;
   if (tile >= total_tiles) return;  // wave-uniform
   const uint32_t shard = tile % NSHARD;
   Item* const stage = s_items[w];
-  uint32_t staged = 0;
+  uint32_t* const pre = s_pre[w];
+  uint32_t staged = 0, staged_c = 0;  // records and their candidates in the stage
+  const bool pack_scan = small_c * small_r <= 1023u;
 
   uint32_t sc = 0;
   while (sc + 1 < nscenes && tile >= scenes[sc + 1].tile_start) ++sc;
@@ -535,22 +570,46 @@ __global__ __launch_bounds__(WPB * 64) void bounds_kernel(
     if (c0 == 0u) continue;
     if (staged + c0 + c1 > STAGE) {
       wave_sync();
-      flush_stage(stage, staged, cnt->items[shard], items + (size_t)shard * item_scap,
-                  item_cs + (size_t)shard * item_scap, item_scap, &cnt->overflow);
+      flush_stage(stage, pre, staged, staged_c, cnt->items[shard],
+                  items + (size_t)shard * item_scap, item_cs + (size_t)shard * item_scap,
+                  item_scap, &cnt->overflow);
       wave_sync();
       staged = 0;
+      staged_c = 0;
+    }
+    // candidate prefix of the new records: the rect0 records first, then rect1
+    const uint32_t k0 = rect0 ? sp.c_count * sp.r0_count : 0u;
+    const uint32_t k1 = rect1 ? sp.c_count * sp.r1_count : 0u;
+    uint32_t i0, i1, t0, t1;
+    if (pack_scan) {  // both counts <= 1023: one scan of (k0 | k1 << 16)
+      const uint32_t pk = wave_incl_scan(k0 | (k1 << 16));
+      const uint32_t tt = __shfl(pk, 63, 64);
+      i0 = pk & 0xFFFFu; i1 = pk >> 16; t0 = tt & 0xFFFFu; t1 = tt >> 16;
+    } else {
+      i0 = wave_incl_scan(k0);
+      i1 = wave_incl_scan(k1);
+      t0 = __shfl(i0, 63, 64);
+      t1 = __shfl(i1, 63, 64);
     }
     const unsigned long long lt = __lanemask_lt();
-    if (rect0) stage[staged + (uint32_t)__popcll(m0 & lt)] =
-        Item{tri, chan, sp.r0_start | (sp.r0_count << 16), n};
-    if (rect1) stage[staged + c0 + (uint32_t)__popcll(m1 & lt)] =
-        Item{tri, chan, sp.r1_start | (sp.r1_count << 16), n};
+    if (rect0) {
+      const uint32_t slot = staged + (uint32_t)__popcll(m0 & lt);
+      stage[slot] = Item{tri, chan, sp.r0_start | (sp.r0_count << 16), n};
+      pre[slot] = staged_c + i0 - k0;
+    }
+    if (rect1) {
+      const uint32_t slot = staged + c0 + (uint32_t)__popcll(m1 & lt);
+      stage[slot] = Item{tri, chan, sp.r1_start | (sp.r1_count << 16), n};
+      pre[slot] = staged_c + t0 + i1 - k1;
+    }
     staged += c0 + c1;
+    staged_c += t0 + t1;
   }
   if (staged > 0u) {
     wave_sync();
-    flush_stage(stage, staged, cnt->items[shard], items + (size_t)shard * item_scap,
-                item_cs + (size_t)shard * item_scap, item_scap, &cnt->overflow);
+    flush_stage(stage, pre, staged, staged_c, cnt->items[shard],
+                items + (size_t)shard * item_scap, item_cs + (size_t)shard * item_scap,
+                item_scap, &cnt->overflow);
   }
   if (INLINE) {
     unsigned long long r = rtic;
@@ -691,7 +750,7 @@ struct ShardWalk {
 };
 
 __device__ inline ShardWalk shard_walk(uint32_t wpb) {
-  const uint32_t gw = blockIdx.x * wpb + (threadIdx.x >> 6);
+  const uint32_t gw = blockIdx.x * wpb + wave_id();
   const uint32_t nw = gridDim.x * wpb;
   const uint32_t step = nw < NSHARD ? nw : NSHARD;
   return ShardWalk{gw % step, step};
@@ -718,7 +777,7 @@ __global__ __launch_bounds__(WPB * 64) void expand_kernel(
     for (;;) {
       uint32_t rec = 0;
       if (lane == 0) rec = atomicAdd(&cnt->large[sh].tk, 1u);
-      rec = __shfl(rec, 0, 64);
+      rec = first_lane(rec);
       if (rec >= n_large) break;
       const Item L = q_large[rec];
       const DevSensor& s = sens[L.sensor];
@@ -878,7 +937,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
   __shared__ Statics st_s[WPB][64];
   __shared__ ItemInfo in_s[WPB][64];
   __shared__ uint32_t pre_s[WPB][65];
-  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t w = wave_id();
   const uint32_t lane = lane_id();
   const ShardWalk sw = shard_walk(WPB);
   unsigned long long rtic = 0ull;  // wave-uniform
@@ -894,7 +953,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     for (;;) {
       uint32_t a = 0;
       if (lane == 0) a = atomicAdd(&cnt->items[sh].tk, ticket_cands);
-      a = __shfl(a, 0, 64);
+      a = first_lane(a);
       if (a >= n_cand) break;
       const uint32_t b = n_cand - a > ticket_cands ? a + ticket_cands : n_cand;
       for (uint32_t ib = find_owner(qcs, n_items, a); ib < n_items; ib += 64u) {
@@ -1126,7 +1185,7 @@ __global__ void sensor_tables_kernel(const float* __restrict__ elev, uint32_t ga
 }
 
 __global__ void sensor_lut_kernel(const float* __restrict__ sin_tab, uint32_t gamma,
-                                  uint32_t lut_size, uint16_t* __restrict__ lut) {
+                                  uint32_t lut_size, ChanBin* __restrict__ bins) {
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= lut_size) return;
   const float edge = -1.0f + 2.0f * (float)b / (float)lut_size;
@@ -1135,7 +1194,13 @@ __global__ void sensor_lut_kernel(const float* __restrict__ sin_tab, uint32_t ga
     const uint32_t mid = (lo + hi) >> 1;
     if (sin_tab[mid] < edge) lo = mid + 1; else hi = mid;
   }
-  lut[b] = (uint16_t)lo;
+  const float inf = __builtin_huge_valf();
+  ChanBin e;
+  e.j = lo;
+  e.s0 = lo < gamma ? sin_tab[lo] : inf;
+  e.s1 = lo + 1 < gamma ? sin_tab[lo + 1] : inf;
+  e.s2 = lo + 2 < gamma ? sin_tab[lo + 2] : inf;
+  bins[b] = e;
 }
 
 // ------------------------------------------------------------------ input checks
@@ -1255,7 +1320,7 @@ hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* r
 
 hipError_t launch_sensor_tables(const float* elev, uint32_t gamma, uint32_t chi, double dtheta,
                                 const float* az_off, float2* chan, double2* chan_d,
-                                float* sin_tab, float2* az, uint32_t lut_size, uint16_t* lut,
+                                float* sin_tab, float2* az, uint32_t lut_size, ChanBin* lut,
                                 hipStream_t st) {
   const uint32_t n = gamma > chi ? gamma : chi;
   hipLaunchKernelGGL(sensor_tables_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, elev, gamma,

@@ -54,7 +54,7 @@ hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* r
                        float* x, float* y, float* z, hipStream_t st);
 hipError_t launch_sensor_tables(const float* elev, uint32_t gamma, uint32_t chi, double dtheta,
                                 const float* az_off, float2* chan, double2* chan_d,
-                                float* sin_tab, float2* az, uint32_t lut_size, uint16_t* lut,
+                                float* sin_tab, float2* az, uint32_t lut_size, ChanBin* lut,
                                 hipStream_t st);
 hipError_t launch_validate(const float* xyz, uint32_t nv, const uint32_t* idx, uint64_t nidx,
                            uint32_t* bad, hipStream_t st);
