@@ -114,7 +114,6 @@ struct grca_workspace {
   unsigned long long* keys = nullptr;
   uint64_t key_cap = 0;
   Item* items = nullptr;
-  Statics* item_stats = nullptr;  // statics of each queued item (same capacity)
   uint32_t* item_cs = nullptr;    // first candidate index of each queued item (same capacity)
   uint64_t item_cap = 0;
   Item* large = nullptr;
@@ -207,11 +206,9 @@ grca_status ws_reserve(grca_context* ctx, grca_workspace* ws, uint64_t rays, uin
   large = (large + NSHARD - 1) / NSHARD * NSHARD;
   if (items > ws->item_cap) {
     dfree(ws->items);
-    dfree(ws->item_stats);
     dfree(ws->item_cs);
     ws->item_cap = 0;
     HIPCHK(dmalloc(&ws->items, items));
-    HIPCHK(dmalloc(&ws->item_stats, items));
     HIPCHK(dmalloc(&ws->item_cs, items));
     ws->item_cap = items;
   }
@@ -256,7 +253,7 @@ grca_status ws_reserve(grca_context* ctx, grca_workspace* ws, uint64_t rays, uin
     ws->out_cap = outs;
   }
   ws->bytes = ws->key_cap * 8 + (ws->item_cap + ws->large_cap) * sizeof(Item) +
-              ws->item_cap * (sizeof(Statics) + sizeof(uint32_t)) +
+              ws->item_cap * sizeof(uint32_t) +
               (uint64_t)RING * (ws->sens_cap * sizeof(DevSensor) + ws->scene_cap * sizeof(DevScene)) +
               ws->scratch_cap * sizeof(Statics) + ws->out_cap * 8 + sizeof(Counters);
   return GRCA_OK;
@@ -275,7 +272,7 @@ void ws_free(grca_workspace* ws) {
   if (!ws) return;
   for (int i = 0; i < RING; ++i)
     if (ws->ev[i]) (void)hipEventSynchronize(ws->ev[i]);
-  dfree(ws->keys); dfree(ws->items); dfree(ws->item_stats); dfree(ws->item_cs); dfree(ws->large); dfree(ws->cnt);
+  dfree(ws->keys); dfree(ws->items); dfree(ws->item_cs); dfree(ws->large); dfree(ws->cnt);
   dfree(ws->dsens); dfree(ws->dscenes); dfree(ws->scratch);
   dfree(ws->out_dist); dfree(ws->out_tri);
   if (ws->cnt_host) (void)hipHostFree(ws->cnt_host);
@@ -381,10 +378,6 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
   return GRCA_OK;
 }
 
-uint32_t prep_blocks(const grca_context* ctx) {
-  return (uint32_t)std::max(1, ctx->num_cu) * 32u;  // grid-stride, 8 blocks of 256 per CU x 4
-}
-
 uint32_t persist_blocks(const grca_context* ctx) {
   const uint32_t waves = (uint32_t)std::max(1, ctx->num_cu) * ctx->opt.persist_waves_cu;
   return std::max(1u, waves / 4u);
@@ -422,8 +415,8 @@ grca_status enqueue_kernels(grca_context* ctx, grca_workspace* ws, uint32_t slot
     const uint32_t pb = persist_blocks(ctx);
     HIPCHK(launch_expand(dscenes, dsens, ws->large, ws->items, ws->item_cs, icap, lcap,
                          o.row_chunk, ws->cnt, pb, st));
-    HIPCHK(launch_isect(dscenes, dsens, ws->items, ws->item_cs, ws->item_stats, icap,
-                        o.isect_ticket, ws->cnt, ws->keys, pb, prep_blocks(ctx), st));
+    HIPCHK(launch_isect(dscenes, dsens, ws->items, ws->item_cs, icap, o.isect_ticket, ws->cnt,
+                        ws->keys, pb, st));
   }
   HIPCHK(launch_resolve(ws->keys, n, dist, tri, ws->cnt, st));
   HIPCHK(hipMemcpyAsync(ws->cnt_host + slot, &ws->cnt->sum, sizeof(Summary),
@@ -475,7 +468,7 @@ grca_status ws_drain(grca_context* ctx, grca_workspace* ws) {
       uint64_t items = ws->item_cap, large = ws->large_cap;
       rc = grown_caps(ctx, ws->cnt_host[slot], items, large);
       if (rc != GRCA_OK) { R.live = false; return rc; }
-      dfree(ws->items); dfree(ws->item_stats); dfree(ws->item_cs); ws->item_cap = 0;
+      dfree(ws->items); dfree(ws->item_cs); ws->item_cap = 0;
       dfree(ws->large); ws->large_cap = 0;
       rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
       if (rc != GRCA_OK) { R.live = false; return rc; }
@@ -1253,8 +1246,8 @@ grca_status enqueue_frame(grca_context* ctx, grca_frame* fr, const Plan& P, hipS
   HIPCHK(launch_expand(ws->dscenes, ws->dsens, ws->large, ws->items, ws->item_cs, icap, lcap,
                        o.row_chunk, ws->cnt, pb, st));
   if (ev) HIPCHK(hipEventRecord(ev[4], st));
-  HIPCHK(launch_isect(ws->dscenes, ws->dsens, ws->items, ws->item_cs, ws->item_stats, icap,
-                      o.isect_ticket, ws->cnt, ws->keys, pb, prep_blocks(ctx), st));
+  HIPCHK(launch_isect(ws->dscenes, ws->dsens, ws->items, ws->item_cs, icap, o.isect_ticket,
+                      ws->cnt, ws->keys, pb, st));
   if (ev) HIPCHK(hipEventRecord(ev[5], st));
   HIPCHK(launch_resolve(ws->keys, n, fr->out_dist, fr->out_tri, ws->cnt, st));
   if (ev) HIPCHK(hipEventRecord(ev[6], st));
@@ -1403,7 +1396,7 @@ extern "C" grca_status grca_frame_synchronize(grca_frame* fr, void* hip_stream) 
       uint64_t items = ws->item_cap, large = ws->large_cap;
       grca_status rc = grown_caps(ctx, c, items, large);
       if (rc != GRCA_OK) return rc;
-      dfree(ws->items); dfree(ws->item_stats); dfree(ws->item_cs); ws->item_cap = 0;
+      dfree(ws->items); dfree(ws->item_cs); ws->item_cap = 0;
       dfree(ws->large); ws->large_cap = 0;
       rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
       if (rc != GRCA_OK) return rc;

@@ -9,8 +9,9 @@
 //   expand_kernel    persistent: per large record, per channel, the exact
 //                    azimuth arc(s) of the channel cone inside the triangle
 //                    -> per-channel row items
-//   isect_kernel     persistent: 64 items per wave, flattened candidates,
-//                    FP32 ray test, 64-bit atomic minimum on packed keys
+//   isect_kernel     persistent, candidate-balanced tickets: FP64 statics per
+//                    item, flattened candidates, FP32 ray test, 64-bit atomic
+//                    minimum on packed keys
 //   resolve_kernel   keys -> (distance, triangle id)                (bookend)
 // plus the all-pairs reference, the pose (dynamic geometry) kernel and the
 // sensor-table builder.
@@ -203,10 +204,12 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
     // a vertex (numerically) at the origin: no usable extent, take everything
     s_lo = -1.0f; s_hi = 1.0f; full = true;
   } else {
+    // r2 >= 1e-24 is a normal float: the hardware reciprocal square root
+    // (1 ulp) needs no denormal scaling
     float inv[3], sn[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      inv[k] = rsqrtf(r2[k]);
+      inv[k] = __builtin_amdgcn_rsqf(r2[k]);
       sn[k] = z[k] * inv[k];
     }
     s_lo = fminf(sn[0], fminf(sn[1], sn[2]));
@@ -221,7 +224,7 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
       const float c = fmaf(x[k], x[k1], fmaf(y[k], y[k1], z[k] * z[k1])) * inv[k] * inv[k1];
       cmin = fminf(cmin, c);
     }
-    const float kb = rsqrtf(fmaxf(0.5f * (1.0f + cmin), 1e-12f)) * (1.0f + 1e-6f);
+    const float kb = __builtin_amdgcn_rsqf(fmaxf(0.5f * (1.0f + cmin), 1e-12f)) * (1.0f + 1e-6f);
     if (s_hi > 0.0f) s_hi = fminf(s_hi * kb, 1.0f);
     if (s_lo < 0.0f) s_lo = fmaxf(s_lo * kb, -1.0f);
     // Vertical axis through the origin vs the triangle's horizontal projection.
@@ -380,8 +383,9 @@ __device__ inline GroupVerdict group_test(float cx, float cy, float cz, float ra
   const uint32_t j = chan_search(s, s_lo, false);
   if (j >= s.gamma || s.sin_tab[j] > s_hi) { v.culled = true; return v; }
   if (!s.wrap && hc > 2.0f * r) {
-    const float beta = asinf(fminf(r / hc, 1.0f)) + 1e-4f + s.az_noise;
-    const float az = atan2f(lr, lf);
+    // asin(x) <= 1.0472 x for x = r / hc < 1/2
+    const float beta = 1.0472f * (r / hc) + 1e-4f + s.az_noise;
+    const float az = atan2_bounded(lr, lf);
     const float half = 0.5f * (float)(s.chi - 1) / s.inv_dtheta;
     const float mid = s.theta_start + half;
     float d = az - mid;
@@ -861,38 +865,6 @@ __global__ __launch_bounds__(WPB * 64) void expand_kernel(
   if (lane == 0 && rows) atomicAdd(&cnt->items[out_shard].rows, rows);
 }
 
-// ------------------------------------------------------------------ statics of queued items
-// One thread per queued item: gather the triangle, build its FP64 statics for
-// the item's sensor and store them beside the item.  Invalid (degenerate or
-// culled back-facing) pairs get zero normals and h = -1, which no ray passes.
-// Block b serves shard b mod NSHARD (the blocks of one shard stride over it).
-__global__ __launch_bounds__(256) void prep_kernel(const DevScene* __restrict__ scenes,
-                                                   const DevSensor* __restrict__ sens,
-                                                   const Item* __restrict__ items,
-                                                   uint32_t item_scap,
-                                                   const Counters* __restrict__ cnt,
-                                                   Statics* __restrict__ stats) {
-  const uint32_t step = gridDim.x < NSHARD ? gridDim.x : NSHARD;
-  const uint32_t per = gridDim.x / step, sub = blockIdx.x / step;
-  if (sub >= per) return;
-  for (uint32_t sh = blockIdx.x % step; sh < NSHARD; sh += step) {
-    const uint32_t n = min((uint32_t)cnt->items[sh].nc, item_scap);
-    const size_t off = (size_t)sh * item_scap;
-    for (uint32_t i = sub * 256u + threadIdx.x; i < n; i += per * 256u) {
-      const Item it = items[off + i];
-      const DevSensor& s = sens[it.sensor];
-      const DevScene& S = scenes[s.scene];
-      const uint32_t t = it.tri;
-      const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
-      Statics st;
-      if (!make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
-                        S.z[i2], s, st))
-        st = Statics{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1.0f, 0, 0, 0};
-      stats[off + i] = st;
-    }
-  }
-}
-
 // ------------------------------------------------------------------ intersection
 struct ItemInfo {
   uint32_t tri, c_from, r_start, r_count;
@@ -925,15 +897,16 @@ __device__ inline uint32_t find_owner(const uint32_t* __restrict__ cs, uint32_t 
 // knows the index of its first candidate pair within its shard, so a ticket
 // is a fixed range [a, b) of candidate pairs: the wave finds the item holding
 // candidate a, then stages the items overlapping [a, b) 64 at a time (lane k
-// holds item k: statics and sensor fields in LDS, clipped to the ticket) and
-// walks the FLATTENED list of their candidates, 64 pairs per step.  Every
-// ticket costs the same whatever the sizes of the items in it.
+// gathers item k's triangle, builds the pair's FP64 statics and keeps them
+// with the sensor fields in LDS, clipped to the ticket) and walks the
+// FLATTENED list of their candidates, 64 pairs per step.  Every ticket costs
+// the same whatever the sizes of the items in it.  Invalid pairs (degenerate,
+// or back-facing under single-sided casting) contribute no candidates.
 template <int WPB>
 __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     const DevScene* __restrict__ scenes, const DevSensor* __restrict__ sens,
-    const Item* __restrict__ items, const uint32_t* __restrict__ item_cs,
-    const Statics* __restrict__ stats, uint32_t item_scap, uint32_t ticket_cands,
-    Counters* __restrict__ cnt, unsigned long long* __restrict__ keys) {
+    const Item* __restrict__ items, const uint32_t* __restrict__ item_cs, uint32_t item_scap,
+    uint32_t ticket_cands, Counters* __restrict__ cnt, unsigned long long* __restrict__ keys) {
   __shared__ Statics st_s[WPB][64];
   __shared__ ItemInfo in_s[WPB][64];
   __shared__ uint32_t pre_s[WPB][65];
@@ -949,7 +922,6 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     const size_t off = (size_t)sh * item_scap;
     const Item* const q = items + off;
     const uint32_t* const qcs = item_cs + off;
-    const Statics* const qst = stats + off;
     for (;;) {
       uint32_t a = 0;
       if (lane == 0) a = atomicAdd(&cnt->items[sh].tk, ticket_cands);
@@ -970,9 +942,15 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
             const uint32_t lo = max(c0, a);
             const uint32_t hi = (uint32_t)min<uint64_t>(e, (uint64_t)b);
             if (hi > lo) {
-              const Statics st = qst[i];
-              if (st.h > 0.0f) {
-                const DevSensor& s = sens[it.sensor];
+              // the pair's statics, built here in FP64 from the gathered triangle
+              const DevSensor& s = sens[it.sensor];
+              const DevScene& S = scenes[s.scene];
+              const uint32_t t = it.tri;
+              const uint32_t v0 = S.idx[3ull * t], v1 = S.idx[3ull * t + 1],
+                             v2 = S.idx[3ull * t + 2];
+              Statics st;
+              if (make_statics(S.x[v0], S.y[v0], S.z[v0], S.x[v1], S.y[v1], S.z[v1], S.x[v2],
+                               S.y[v2], S.z[v2], s, st)) {
                 count = hi - lo;
                 st_s[w][lane] = st;
                 ItemInfo inf;
@@ -1279,13 +1257,11 @@ hipError_t launch_expand(const DevScene* scenes, const DevSensor* sens, const It
 }
 
 hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, const Item* items,
-                        const uint32_t* item_cs, Statics* stats, uint32_t item_scap,
-                        uint32_t ticket_cands, Counters* cnt, unsigned long long* keys,
-                        uint32_t nblocks, uint32_t prep_blocks, hipStream_t st) {
-  hipLaunchKernelGGL(prep_kernel, dim3(prep_blocks), dim3(256), 0, st, scenes, sens, items,
-                     item_scap, cnt, stats);
+                        const uint32_t* item_cs, uint32_t item_scap, uint32_t ticket_cands,
+                        Counters* cnt, unsigned long long* keys, uint32_t nblocks,
+                        hipStream_t st) {
   hipLaunchKernelGGL(isect_kernel<4>, dim3(nblocks), dim3(256), 0, st, scenes, sens, items,
-                     item_cs, stats, item_scap, ticket_cands, cnt, keys);
+                     item_cs, item_scap, ticket_cands, cnt, keys);
   return hipGetLastError();
 }
 

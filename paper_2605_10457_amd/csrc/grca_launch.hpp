@@ -36,12 +36,11 @@ hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t tota
 hipError_t launch_expand(const DevScene* scenes, const DevSensor* sens, const Item* large,
                          Item* items, uint32_t* item_cs, uint32_t item_scap, uint32_t large_scap,
                          uint32_t row_chunk, Counters* cnt, uint32_t nblocks, hipStream_t st);
-// prep_kernel (statics of every queued item) followed by isect_kernel, whose
-// tickets are ranges of `ticket_cands` candidate pairs
+// intersection; its tickets are ranges of `ticket_cands` candidate pairs
 hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, const Item* items,
-                        const uint32_t* item_cs, Statics* stats, uint32_t item_scap,
-                        uint32_t ticket_cands, Counters* cnt, unsigned long long* keys,
-                        uint32_t nblocks, uint32_t prep_blocks, hipStream_t st);
+                        const uint32_t* item_cs, uint32_t item_scap, uint32_t ticket_cands,
+                        Counters* cnt, unsigned long long* keys, uint32_t nblocks,
+                        hipStream_t st);
 hipError_t launch_allpairs(const DevScene* scenes, const DevSensor* sens, uint32_t sensor,
                            uint32_t ntri, uint32_t nrays, Statics* scratch,
                            unsigned long long* keys, hipStream_t st);
