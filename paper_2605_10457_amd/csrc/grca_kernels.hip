@@ -274,22 +274,37 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
   const uint32_t chi = s.chi;
   sp.r1_start = 0; sp.r1_count = 0;
   if (!full) {
+    // Azimuth of vertex 0, and the offsets of vertices 1 and 2 from it.  An
+    // offset of tangent t = cross / dot with |t| <= 0.1 lies in
+    // [t - |t|^3/3, t + |t|^3/3] (atan's alternating series), so small
+    // triangles need one atan2 instead of three; other offsets take the full
+    // atan2 difference, wrapped to (-pi, pi].
     const float t0 = atan2_bounded(y[0], x[0]);
-    float d1 = atan2_bounded(y[1], x[1]) - t0;
-    float d2 = atan2_bounded(y[2], x[2]) - t0;
-    if (d1 > PI_F) d1 -= TWO_PI_F;
-    if (d1 < -PI_F) d1 += TWO_PI_F;
-    if (d2 > PI_F) d2 -= TWO_PI_F;
-    if (d2 < -PI_F) d2 += TWO_PI_F;
-    const float lo = fminf(0.0f, fminf(d1, d2));
-    const float hi = fmaxf(0.0f, fmaxf(d1, d2));
+    float lo = 0.0f, hi = 0.0f;
+#pragma unroll
+    for (int k = 1; k < 3; ++k) {
+      const float cr = fmaf(x[0], y[k], -(y[0] * x[k]));
+      const float dt = fmaf(x[0], x[k], y[0] * y[k]);
+      if (dt > 0.0f && fabsf(cr) <= 0.1f * dt) {
+        const float t = cr * __builtin_amdgcn_rcpf(dt);
+        const float c3 = fabsf(t) * t * t * (1.0f / 3.0f);
+        lo = fminf(lo, t - c3);
+        hi = fmaxf(hi, t + c3);
+      } else {
+        float d = atan2_bounded(y[k], x[k]) - t0;
+        if (d > PI_F) d -= TWO_PI_F;
+        if (d < -PI_F) d += TWO_PI_F;
+        lo = fminf(lo, d);
+        hi = fmaxf(hi, d);
+      }
+    }
     if (hi - lo > PI_F - 1e-3f) {
       full = true;
     } else {
-      // margin terms only: the hardware square root and reciprocal (1 ulp) suffice
-      const float cmin_el = __builtin_amdgcn_sqrtf(fmaxf(1.0f - smax_abs * smax_abs, 0.0f));
-      const float m = MARGIN_AZ + MARGIN_AZ_POLE * __builtin_amdgcn_rcpf(fmaxf(cmin_el, 1e-3f)) +
-                      s.az_noise;
+      // 1 / max(cos(max |elevation|), 1e-3) by the hardware reciprocal square
+      // root (1 ulp suffices for a margin term)
+      const float inv_cos = __builtin_amdgcn_rsqf(fmaxf(fmaf(-smax_abs, smax_abs, 1.0f), 1e-6f));
+      const float m = MARGIN_AZ + MARGIN_AZ_POLE * inv_cos + s.az_noise;
       float a = t0 + lo - m - s.theta_start;
       a -= TWO_PI_F * floorf(a * (1.0f / TWO_PI_F));
       if (a < 0.0f) a = 0.0f;
@@ -457,8 +472,10 @@ __device__ inline void flush_stage(const Item* stage, const uint32_t* pre, uint3
 // into the wave's own LDS stage (no block barrier) and appended to the
 // wave's item shard when the stage fills and at the end; large-class records
 // go to the wave's large-record shard with one atomic per wave and sensor.
+// The plain variant is held to 64 VGPRs (8 waves per SIMD; no spills): the
+// pass is VALU-bound with memory waits that more resident waves hide.
 template <int WPB, bool INLINE>
-__global__ __launch_bounds__(WPB * 64) void bounds_kernel(
+__global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
     const DevScene* __restrict__ scenes, uint32_t nscenes, uint32_t total_tiles,
     const DevSensor* __restrict__ sens, uint32_t small_c, uint32_t small_r,
     Item* __restrict__ items, uint32_t* __restrict__ item_cs, uint32_t item_scap,
