@@ -120,12 +120,18 @@ struct Span {
   bool large;
 };
 
-// first j with sin_tab[j] >= x (strict = false) or > x (strict = true)
-__device__ inline uint32_t chan_search(const DevSensor& s, float x, bool strict) {
+// Bin of the sine -> channel lookup for sine x, one bin early: the FP32 bin
+// index may round up.
+__device__ inline uint32_t chan_bin(const DevSensor& s, float x) {
   const float fb = (x + 1.0f) * (0.5f * (float)s.lut_size);
-  int b = (fb > 0.0f) ? (int)fminf(fb, (float)(s.lut_size - 1)) : 0;
-  b = b > 0 ? b - 1 : 0;  // one bin early: the FP32 bin index may round up
-  const ChanBin e = s.bins[b];
+  const int b = (fb > 0.0f) ? (int)fminf(fb, (float)(s.lut_size - 1)) : 0;
+  return b > 0 ? (uint32_t)(b - 1) : 0u;
+}
+
+// first j with sin_tab[j] >= x (strict = false) or > x (strict = true), from
+// the bin's entry e
+__device__ inline uint32_t chan_resolve(const DevSensor& s, const ChanBin& e, float x,
+                                        bool strict) {
   uint32_t j = e.j;
   if (strict) {
     j += (uint32_t)(e.s0 <= x) + (uint32_t)(e.s1 <= x) + (uint32_t)(e.s2 <= x);
@@ -137,6 +143,10 @@ __device__ inline uint32_t chan_search(const DevSensor& s, float x, bool strict)
       while (j < s.gamma && s.sin_tab[j] < x) ++j;
   }
   return j;
+}
+
+__device__ inline uint32_t chan_search(const DevSensor& s, float x, bool strict) {
+  return chan_resolve(s, s.bins[chan_bin(s, x)], x, strict);
 }
 
 // atan2(y, x) in FP32 for the bounds pass, |error| <= 5e-7 rad for mx > 0
@@ -264,8 +274,11 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
   const float smax_abs = fmaxf(fabsf(s_lo), fabsf(s_hi));
   s_lo -= ETA_SIN;
   s_hi += ETA_SIN;
-  const uint32_t c_from = chan_search(s, s_lo, false);
-  const uint32_t c_end = chan_search(s, s_hi, true);
+  // both bin loads in flight together
+  const ChanBin e_lo = s.bins[chan_bin(s, s_lo)];
+  const ChanBin e_hi = s.bins[chan_bin(s, s_hi)];
+  const uint32_t c_from = chan_resolve(s, e_lo, s_lo, false);
+  const uint32_t c_end = chan_resolve(s, e_hi, s_hi, true);
   if (c_from >= c_end) return false;
   sp.c_from = c_from;
   sp.c_count = c_end - c_from;
