@@ -904,8 +904,20 @@ struct ItemInfo {
   const float2* az;
   const uint8_t* mask;
   float inv_rc;
-  uint32_t skip;  // candidates of the item that precede the current ticket
+  int32_t bias;  // item-local candidate index = batch position + bias
 };
+
+// Inclusive prefix maximum over the wave (identity -1) with DPP row shifts
+// and row broadcasts: no LDS round trips.
+__device__ inline int wave_incl_max(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return v;
+}
 
 // Last slot i in [0, n) of a shard with cs[i] <= a (cs increasing, cs[0] = 0
 // <= a): a 64-way search, one probe per lane per round.
@@ -939,7 +951,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     uint32_t ticket_cands, Counters* __restrict__ cnt, unsigned long long* __restrict__ keys) {
   __shared__ Statics st_s[WPB][64];
   __shared__ ItemInfo in_s[WPB][64];
-  __shared__ uint32_t pre_s[WPB][65];
+  __shared__ int mark_s[WPB][64];
   const uint32_t w = wave_id();
   const uint32_t lane = lane_id();
   const ShardWalk sw = shard_walk(WPB);
@@ -960,7 +972,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
       const uint32_t b = n_cand - a > ticket_cands ? a + ticket_cands : n_cand;
       for (uint32_t ib = find_owner(qcs, n_items, a); ib < n_items; ib += 64u) {
         const uint32_t i = ib + lane;
-        uint32_t count = 0;
+        uint32_t count = 0, skip = 0;
         bool past = i >= n_items;  // this lane's item starts at or after b
         if (!past) {
           const uint32_t c0 = qcs[i];
@@ -996,41 +1008,42 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
                 inf.az = s.az;
                 inf.mask = s.mask;
                 inf.inv_rc = 1.0f / (float)rc;
-                inf.skip = lo - c0;  // candidates of the item before this ticket
+                inf.bias = 0;
                 in_s[w][lane] = inf;
+                skip = lo - c0;  // candidates of the item before this ticket
               }
             }
           }
         }
         const bool last = __ballot(past) != 0ull;
         const uint32_t incl = wave_incl_scan(count);
-        pre_s[w][lane + 1] = incl;
-        if (lane == 0) pre_s[w][0] = 0;
+        const uint32_t excl = incl - count;  // batch position of this item's first candidate
+        if (count) in_s[w][lane].bias = (int32_t)skip - (int32_t)excl;
         const uint32_t total = __shfl(incl, 63, 64);
         rtic += total;
-        wave_sync();
-        int cur = -1;
+        // Owner of batch position p: the last item with a candidate whose first
+        // position is <= p.  Per window of 64 positions, each item starting in
+        // the window marks its slot, and a prefix maximum spreads the marks;
+        // positions before the first mark keep the previous window's owner.
+        int carry = -1, cur = -1;
         Statics st;
         ItemInfo inf;
-        for (uint32_t f = lane; f < total; f += 64) {
-          // owner = last item whose prefix start <= f (pre_s[w][64] == total > f).
-          // f grows with each step, so the owner never moves backwards: keep it
-          // while its range still covers f, else bisect the items after it.
-          uint32_t lo;
-          if (cur >= 0 && pre_s[w][cur + 1] > f) {
-            lo = (uint32_t)cur;
-          } else {
-            lo = cur >= 0 ? (uint32_t)cur + 1u : 0u;
-            uint32_t hi = 64;
-            while (hi - lo > 1) {
-              const uint32_t mid = (lo + hi) >> 1;
-              if (pre_s[w][mid] <= f) lo = mid; else hi = mid;
-            }
-            cur = (int)lo;
-            st = st_s[w][lo];
-            inf = in_s[w][lo];
+        for (uint32_t base = 0; base < total; base += 64) {
+          mark_s[w][lane] = -1;
+          wave_sync();
+          if (count && excl >= base && excl - base < 64u) mark_s[w][excl - base] = (int)lane;
+          wave_sync();
+          const int own = max(wave_incl_max(mark_s[w][lane]), carry);
+          carry = __builtin_amdgcn_readlane(own, 63);
+          wave_sync();
+          const uint32_t f = base + lane;
+          if (f >= total) continue;
+          if (own != cur) {
+            cur = own;
+            st = st_s[w][own];
+            inf = in_s[w][own];
           }
-          const uint32_t local = f - pre_s[w][lo] + inf.skip;
+          const uint32_t local = (uint32_t)((int32_t)f + inf.bias);
           uint32_t c = 0;
           if (local >= inf.r_count) {
             c = (uint32_t)((float)local * inf.inv_rc);
