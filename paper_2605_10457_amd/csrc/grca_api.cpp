@@ -415,8 +415,8 @@ grca_status enqueue_kernels(grca_context* ctx, grca_workspace* ws, uint32_t slot
     const uint32_t pb = persist_blocks(ctx);
     HIPCHK(launch_expand(dscenes, dsens, ws->large, ws->items, ws->item_cs, icap, lcap,
                          o.row_chunk, ws->cnt, pb, st));
-    HIPCHK(launch_isect(dscenes, dsens, ws->items, ws->item_cs, icap, o.isect_ticket, ws->cnt,
-                        ws->keys, pb, st));
+    HIPCHK(launch_isect(dscenes, dsens, (uint32_t)P.sens.size(), ws->items, ws->item_cs, icap,
+                        o.isect_ticket, ws->cnt, ws->keys, pb, st));
   }
   HIPCHK(launch_resolve(ws->keys, n, dist, tri, ws->cnt, st));
   HIPCHK(hipMemcpyAsync(ws->cnt_host + slot, &ws->cnt->sum, sizeof(Summary),
@@ -1246,8 +1246,8 @@ grca_status enqueue_frame(grca_context* ctx, grca_frame* fr, const Plan& P, hipS
   HIPCHK(launch_expand(ws->dscenes, ws->dsens, ws->large, ws->items, ws->item_cs, icap, lcap,
                        o.row_chunk, ws->cnt, pb, st));
   if (ev) HIPCHK(hipEventRecord(ev[4], st));
-  HIPCHK(launch_isect(ws->dscenes, ws->dsens, ws->items, ws->item_cs, icap, o.isect_ticket,
-                      ws->cnt, ws->keys, pb, st));
+  HIPCHK(launch_isect(ws->dscenes, ws->dsens, (uint32_t)P.sens.size(), ws->items, ws->item_cs,
+                      icap, o.isect_ticket, ws->cnt, ws->keys, pb, st));
   if (ev) HIPCHK(hipEventRecord(ev[5], st));
   HIPCHK(launch_resolve(ws->keys, n, fr->out_dist, fr->out_tri, ws->cnt, st));
   if (ev) HIPCHK(hipEventRecord(ev[6], st));

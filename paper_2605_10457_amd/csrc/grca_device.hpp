@@ -128,8 +128,11 @@ struct Statics {
   float h, pad0, pad1, pad2;
 };
 
+// `s` is any sensor record with the frame o, f, r, u and cull_back (the
+// device descriptor, or its copy in LDS).
+template <class SensorT>
 __device__ inline bool make_statics(float ax, float ay, float az_, float bx, float by, float bz,
-                                    float cx, float cy, float cz, const DevSensor& s,
+                                    float cx, float cy, float cz, const SensorT& s,
                                     Statics& st, double (*nrm_out)[3] = nullptr) {
   // FP64 throughout, rounded once to FP32 at the end.
   const double ox = s.o[0], oy = s.o[1], oz = s.o[2];

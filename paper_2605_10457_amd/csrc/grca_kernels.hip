@@ -896,15 +896,54 @@ __global__ __launch_bounds__(WPB * 64) void expand_kernel(
 }
 
 // ------------------------------------------------------------------ intersection
+// LDS record of a staged item (24 B; its statics' twelve normal components
+// sit in a separate array of float4s).
 struct ItemInfo {
-  uint32_t tri, c_from, r_start, r_count;
-  uint32_t chi, key_offset;
-  float dmin, dmax;
+  uint32_t tri;
+  uint32_t cr;    // c_from | r_start << 16
+  uint32_t rs;    // r_count | sensor slot << 16
+  int32_t bias;   // item-local candidate index = batch position + bias
+  float inv_rc;   // 1 / r_count
+  float h;        // origin-to-plane distance of the statics
+};
+
+// What the intersection needs of a sensor and its scene, cached in LDS for
+// the first 64 sensor slots of the cast.
+struct IsectSensor {
   const float2* chan;
   const float2* az;
   const uint8_t* mask;
-  float inv_rc;
-  int32_t bias;  // item-local candidate index = batch position + bias
+  const uint32_t* idx;
+  const float* x;
+  const float* y;
+  const float* z;
+  float o[3], f[3], r[3], u[3];
+  int32_t cull_back;
+  uint32_t chi, key_offset;
+  float dmin, dmax;
+};
+
+__device__ inline IsectSensor isect_sensor(const DevScene* scenes, const DevSensor& s) {
+  const DevScene& S = scenes[s.scene];
+  IsectSensor q;
+  q.chan = s.chan; q.az = s.az; q.mask = s.mask;
+  q.idx = S.idx; q.x = S.x; q.y = S.y; q.z = S.z;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    q.o[k] = s.o[k]; q.f[k] = s.f[k]; q.r[k] = s.r[k]; q.u[k] = s.u[k];
+  }
+  q.cull_back = s.cull_back;
+  q.chi = s.chi; q.key_offset = s.key_offset; q.dmin = s.dmin; q.dmax = s.dmax;
+  return q;
+}
+
+// The sensor fields the candidate loop keeps in registers.
+struct CandSensor {
+  const float2* chan;
+  const float2* az;
+  const uint8_t* mask;
+  uint32_t chi, key_offset;
+  float dmin, dmax;
 };
 
 // Inclusive prefix maximum over the wave (identity -1) with DPP row shifts
@@ -947,13 +986,18 @@ __device__ inline uint32_t find_owner(const uint32_t* __restrict__ cs, uint32_t 
 template <int WPB>
 __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     const DevScene* __restrict__ scenes, const DevSensor* __restrict__ sens,
-    const Item* __restrict__ items, const uint32_t* __restrict__ item_cs, uint32_t item_scap,
-    uint32_t ticket_cands, Counters* __restrict__ cnt, unsigned long long* __restrict__ keys) {
-  __shared__ Statics st_s[WPB][64];
+    uint32_t nsens, const Item* __restrict__ items, const uint32_t* __restrict__ item_cs,
+    uint32_t item_scap, uint32_t ticket_cands, Counters* __restrict__ cnt,
+    unsigned long long* __restrict__ keys) {
+  __shared__ float4 st_s[WPB][3][64];  // the staged items' normals n0, n1, n2, N
   __shared__ ItemInfo in_s[WPB][64];
   __shared__ int mark_s[WPB][64];
+  __shared__ IsectSensor sen_s[64];
   const uint32_t w = wave_id();
   const uint32_t lane = lane_id();
+  if (threadIdx.x < min(nsens, 64u))
+    sen_s[threadIdx.x] = isect_sensor(scenes, sens[threadIdx.x]);
+  __syncthreads();
   const ShardWalk sw = shard_walk(WPB);
   unsigned long long rtic = 0ull;  // wave-uniform
   for (uint32_t sh = sw.first; sh < NSHARD; sh += sw.step) {
@@ -973,45 +1017,42 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
       for (uint32_t ib = find_owner(qcs, n_items, a); ib < n_items; ib += 64u) {
         const uint32_t i = ib + lane;
         uint32_t count = 0, skip = 0;
-        bool past = i >= n_items;  // this lane's item starts at or after b
+        // the item and its first candidate index, both loads in flight together
+        uint32_t c0 = 0xFFFFFFFFu;
+        Item it{};
+        if (i < n_items) {
+          c0 = qcs[i];
+          it = q[i];
+        }
+        const bool past = i >= n_items || c0 >= b;  // this lane's item starts at or after b
         if (!past) {
-          const uint32_t c0 = qcs[i];
-          past = c0 >= b;
-          if (!past) {
-            const Item it = q[i];
-            const uint32_t rc = it.rays >> 16;
-            const uint64_t e = (uint64_t)c0 + (uint64_t)((it.chan >> 16) * rc);
-            const uint32_t lo = max(c0, a);
-            const uint32_t hi = (uint32_t)min<uint64_t>(e, (uint64_t)b);
-            if (hi > lo) {
-              // the pair's statics, built here in FP64 from the gathered triangle
-              const DevSensor& s = sens[it.sensor];
-              const DevScene& S = scenes[s.scene];
-              const uint32_t t = it.tri;
-              const uint32_t v0 = S.idx[3ull * t], v1 = S.idx[3ull * t + 1],
-                             v2 = S.idx[3ull * t + 2];
-              Statics st;
-              if (make_statics(S.x[v0], S.y[v0], S.z[v0], S.x[v1], S.y[v1], S.z[v1], S.x[v2],
-                               S.y[v2], S.z[v2], s, st)) {
-                count = hi - lo;
-                st_s[w][lane] = st;
-                ItemInfo inf;
-                inf.tri = it.tri;
-                inf.c_from = it.chan & 0xFFFFu;
-                inf.r_start = it.rays & 0xFFFFu;
-                inf.r_count = rc;
-                inf.chi = s.chi;
-                inf.key_offset = s.key_offset;
-                inf.dmin = s.dmin;
-                inf.dmax = s.dmax;
-                inf.chan = s.chan;
-                inf.az = s.az;
-                inf.mask = s.mask;
-                inf.inv_rc = 1.0f / (float)rc;
-                inf.bias = 0;
-                in_s[w][lane] = inf;
-                skip = lo - c0;  // candidates of the item before this ticket
-              }
+          const uint32_t rc = it.rays >> 16;
+          const uint64_t e = (uint64_t)c0 + (uint64_t)((it.chan >> 16) * rc);
+          const uint32_t lo = max(c0, a);
+          const uint32_t hi = (uint32_t)min<uint64_t>(e, (uint64_t)b);
+          if (hi > lo) {
+            // the pair's statics, built here in FP64 from the gathered triangle
+            const IsectSensor sq = it.sensor < 64u ? sen_s[it.sensor]
+                                                   : isect_sensor(scenes, sens[it.sensor]);
+            const uint32_t t = it.tri;
+            const uint32_t v0 = sq.idx[3ull * t], v1 = sq.idx[3ull * t + 1],
+                           v2 = sq.idx[3ull * t + 2];
+            Statics st;
+            if (make_statics(sq.x[v0], sq.y[v0], sq.z[v0], sq.x[v1], sq.y[v1], sq.z[v1],
+                             sq.x[v2], sq.y[v2], sq.z[v2], sq, st)) {
+              count = hi - lo;
+              st_s[w][0][lane] = make_float4(st.n0x, st.n0y, st.n0z, st.n1x);
+              st_s[w][1][lane] = make_float4(st.n1y, st.n1z, st.n2x, st.n2y);
+              st_s[w][2][lane] = make_float4(st.n2z, st.Nx, st.Ny, st.Nz);
+              ItemInfo inf;
+              inf.tri = it.tri;
+              inf.cr = (it.chan & 0xFFFFu) | (it.rays << 16);
+              inf.rs = rc | (it.sensor << 16);
+              inf.bias = 0;
+              inf.inv_rc = 1.0f / (float)rc;
+              inf.h = st.h;
+              in_s[w][lane] = inf;
+              skip = lo - c0;  // candidates of the item before this ticket
             }
           }
         }
@@ -1028,6 +1069,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
         int carry = -1, cur = -1;
         Statics st;
         ItemInfo inf;
+        CandSensor sn;
         for (uint32_t base = 0; base < total; base += 64) {
           mark_s[w][lane] = -1;
           wave_sync();
@@ -1040,27 +1082,38 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
           if (f >= total) continue;
           if (own != cur) {
             cur = own;
-            st = st_s[w][own];
+            const float4 a0 = st_s[w][0][own], a1 = st_s[w][1][own], a2 = st_s[w][2][own];
             inf = in_s[w][own];
+            st = Statics{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
+                         a2.x, a2.y, a2.z, a2.w, inf.h, 0.0f, 0.0f, 0.0f};
+            const uint32_t sid = inf.rs >> 16;
+            if (sid < 64u) {
+              const IsectSensor& q2 = sen_s[sid];
+              sn = CandSensor{q2.chan, q2.az, q2.mask, q2.chi, q2.key_offset, q2.dmin, q2.dmax};
+            } else {
+              const DevSensor& s2 = sens[sid];
+              sn = CandSensor{s2.chan, s2.az, s2.mask, s2.chi, s2.key_offset, s2.dmin, s2.dmax};
+            }
           }
+          const uint32_t r_count = inf.rs & 0xFFFFu;
           const uint32_t local = (uint32_t)((int32_t)f + inf.bias);
           uint32_t c = 0;
-          if (local >= inf.r_count) {
+          if (local >= r_count) {
             c = (uint32_t)((float)local * inf.inv_rc);
-            if (c * inf.r_count > local) --c;
-            else if ((c + 1) * inf.r_count <= local) ++c;
+            if (c * r_count > local) --c;
+            else if ((c + 1) * r_count <= local) ++c;
           }
-          const uint32_t r = local - c * inf.r_count;
-          const uint32_t ch = inf.c_from + c;
-          uint32_t ray = inf.r_start + r;
-          if (ray >= inf.chi) ray -= inf.chi;
-          const uint32_t gl = ch * inf.chi + ray;
-          if (inf.mask && !inf.mask[gl]) continue;
-          const float2 cp = inf.chan[ch];
-          const float2 ca = inf.az[ray];
-          const unsigned long long key = ray_test(st, cp.x, cp.y, ca.x, ca.y, inf.dmin, inf.dmax,
+          const uint32_t r = local - c * r_count;
+          const uint32_t ch = (inf.cr & 0xFFFFu) + c;
+          uint32_t ray = (inf.cr >> 16) + r;
+          if (ray >= sn.chi) ray -= sn.chi;
+          const uint32_t gl = ch * sn.chi + ray;
+          if (sn.mask && !sn.mask[gl]) continue;
+          const float2 cp = sn.chan[ch];
+          const float2 ca = sn.az[ray];
+          const unsigned long long key = ray_test(st, cp.x, cp.y, ca.x, ca.y, sn.dmin, sn.dmax,
                                                   inf.tri);
-          if (key != KEY_INIT) key_min(keys, inf.key_offset + gl, key);
+          if (key != KEY_INIT) key_min(keys, sn.key_offset + gl, key);
         }
         wave_sync();
         if (last) break;
@@ -1299,11 +1352,11 @@ hipError_t launch_expand(const DevScene* scenes, const DevSensor* sens, const It
   return hipGetLastError();
 }
 
-hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, const Item* items,
-                        const uint32_t* item_cs, uint32_t item_scap, uint32_t ticket_cands,
-                        Counters* cnt, unsigned long long* keys, uint32_t nblocks,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(isect_kernel<4>, dim3(nblocks), dim3(256), 0, st, scenes, sens, items,
+hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, uint32_t nsens,
+                        const Item* items, const uint32_t* item_cs, uint32_t item_scap,
+                        uint32_t ticket_cands, Counters* cnt, unsigned long long* keys,
+                        uint32_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(isect_kernel<4>, dim3(nblocks), dim3(256), 0, st, scenes, sens, nsens, items,
                      item_cs, item_scap, ticket_cands, cnt, keys);
   return hipGetLastError();
 }

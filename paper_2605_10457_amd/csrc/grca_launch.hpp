@@ -37,10 +37,10 @@ hipError_t launch_expand(const DevScene* scenes, const DevSensor* sens, const It
                          Item* items, uint32_t* item_cs, uint32_t item_scap, uint32_t large_scap,
                          uint32_t row_chunk, Counters* cnt, uint32_t nblocks, hipStream_t st);
 // intersection; its tickets are ranges of `ticket_cands` candidate pairs
-hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, const Item* items,
-                        const uint32_t* item_cs, uint32_t item_scap, uint32_t ticket_cands,
-                        Counters* cnt, unsigned long long* keys, uint32_t nblocks,
-                        hipStream_t st);
+hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, uint32_t nsens,
+                        const Item* items, const uint32_t* item_cs, uint32_t item_scap,
+                        uint32_t ticket_cands, Counters* cnt, unsigned long long* keys,
+                        uint32_t nblocks, hipStream_t st);
 hipError_t launch_allpairs(const DevScene* scenes, const DevSensor* sens, uint32_t sensor,
                            uint32_t ntri, uint32_t nrays, Statics* scratch,
                            unsigned long long* keys, hipStream_t st);
