@@ -32,8 +32,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rays/s + frame ms, 8×(128×4096) LiDARs on 22M tris; batched vs plain; p99"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3          # published MI355X vector FP32
+# FP32 vector peak without packed-FP32 instructions (the build disables them):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.  The published
+# 157.3 TFLOP/s counts the packed (2-wide) FMA.
+FP32_PEAK_TFLOPS = 78.6
 FLOPS_PER_RTIC = 22               # ray test: 2 mul (direction) + 4 dot products x 5 flops
+# Candidate span of one (triangle, origin) pair on the common path (no range
+# or pole test, azimuth offsets by the series bound): transform 54, |p|^2 15,
+# sines 6, edge bulge 27, margins 2, channel bins 4, atan2 of vertex 0 20,
+# offsets of vertices 1-2 28, full-turn test 1, azimuth margin 6, ray-index
+# range 12 (add/sub/mul/rsq/rcp = 1, fma = 2; compares, min/max not counted).
+FLOPS_PER_SPAN = 175
 
 
 def log(msg):
@@ -280,13 +289,17 @@ def main():
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                 "traffic": load_traffic("isect_kernel"),
                 "work": f"{FLOPS_PER_RTIC} FP32 flops x {stats['rtic']} RTIC per launch"}
+    elif dom == "bounds":
+        # VALU-bound: FP32 flops of the spans the pass computed
+        flops = FLOPS_PER_SPAN * stats["pairs_evaluated"]
+        achieved = flops / (stage_ms["bounds"] * 1e-3) / 1e12
+        roof = {"kernel": "bounds_kernel", "bound": "alu", "achieved": achieved,
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                "traffic": load_traffic("bounds_kernel"),
+                "work": f"{FLOPS_PER_SPAN} FP32 flops x {stats['pairs_evaluated']} "
+                        f"(triangle, origin) spans per launch"}
     else:
-        # bounds/binning: per triangle 12 B of indices + its share of the unique
-        # vertices (12 B each) read once for all 8 origins, + 16 B per record
-        recs = stats["rect_items"] + stats["large_records"]
-        nbytes = 12 * sc.num_triangles + 12 * sc.num_vertices + 16 * recs
-        if dom == "expand":
-            nbytes = 16 * stats["large_records"] + 16 * stats["row_items"]
+        nbytes = 20 * stats["large_records"] + 20 * stats["row_items"]
         achieved = nbytes / (stage_ms[dom] * 1e-3) / 1e9
         roof = {"kernel": f"{dom}_kernel", "bound": "hbm", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -347,7 +360,8 @@ def main():
         "host_wall_ms_per_frame": wall_batched * 1e3 / args.steps,
         "stage_ms": stage_ms,
         "rtic_per_frame": stats["rtic"], "rtic_per_s": rtic_s,
-        "work": {k: stats[k] for k in ("pairs_tested", "rect_items", "large_records", "row_items")},
+        "work": {k: stats[k] for k in ("pairs_tested", "pairs_evaluated", "rect_items",
+                                       "large_records", "row_items")},
         "range_sweep": sweep,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -206,6 +206,9 @@ typedef struct {
   uint64_t row_items;     /* per-channel work items expanded from large records      */
   uint64_t rtic;          /* ray-triangle intersection checks executed               */
   uint32_t recasts;       /* overflow-driven recasts                                 */
+  uint32_t reserved;
+  uint64_t pairs_evaluated; /* of pairs_tested: those not culled by a tile's bounding-
+                               sphere test, whose span the bounds pass computed      */
 } grca_stats;
 grca_status grca_last_stats(grca_context* ctx, grca_stats* out);
 

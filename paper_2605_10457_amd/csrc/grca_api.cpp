@@ -1123,6 +1123,7 @@ extern "C" grca_status grca_last_stats(grca_context* ctx, grca_stats* out) {
     out->row_items = c.n_rows;
     out->rtic = c.rtic;
     out->recasts = R.recasts;
+    out->pairs_evaluated = c.pairs;
     return GRCA_OK;
   })
 }

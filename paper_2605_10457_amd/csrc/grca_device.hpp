@@ -90,7 +90,8 @@ struct alignas(256) Shard {
   uint32_t tk;              // consumer ticket (candidates for items, records for large)
   uint32_t rows;            // row items appended by the expansion (statistic)
   unsigned long long rtic;  // candidate pairs executed from this shard (statistic)
-  uint32_t pad[58];
+  unsigned long long pairs; // (triangle, origin) spans computed (statistic)
+  uint32_t pad[56];
 };
 static_assert(sizeof(Shard) == 256, "one shard counter per 256-byte line");
 
@@ -103,6 +104,7 @@ struct Summary {
   uint32_t max_items_shard;  // largest request of one item shard
   uint32_t max_large_shard;  // largest request of one large-record shard
   unsigned long long rtic;   // candidate pairs executed
+  unsigned long long pairs;  // (triangle, origin) spans computed
 };
 
 // Device counters of one cast, cleared by the init kernel.

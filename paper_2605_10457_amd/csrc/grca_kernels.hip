@@ -545,6 +545,8 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
   }
   unsigned long long rtic = 0ull;  // candidates tested inline by this lane
   unsigned long long g_cull = 0ull, g_range = ~0ull, g_pole = ~0ull;
+  const uint32_t n_active = (uint32_t)__popcll(__ballot(active));
+  uint32_t evaluated = 0;  // spans computed by this wave (wave-uniform statistic)
   for (uint32_t n = S.sensor_begin; n < S.sensor_end; ++n) {
     const uint32_t ln = (n - S.sensor_begin) & 63u;
     if (ln == 0) {
@@ -561,6 +563,7 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
       }
     }
     if ((g_cull >> ln) & 1ull) continue;  // wave-uniform
+    evaluated += n_active;
     const DevSensor& s = sens[n];
     Span sp;
     const bool ok = active && span_of(vx, vy, vz, s, small_c, small_r, (g_range >> ln) & 1ull,
@@ -645,6 +648,7 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
                 items + (size_t)shard * item_scap, item_cs + (size_t)shard * item_scap,
                 item_scap, &cnt->overflow);
   }
+  if (lane == 0 && evaluated) atomicAdd(&cnt->items[shard].pairs, (unsigned long long)evaluated);
   if (INLINE) {
     unsigned long long r = rtic;
 #pragma unroll
@@ -1182,7 +1186,7 @@ __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint
     const uint32_t l = threadIdx.x;
     uint32_t ni = (uint32_t)cnt->items[l].nc, nl = (uint32_t)cnt->large[l].nc;
     uint32_t nr = cnt->items[l].rows;
-    unsigned long long rt = cnt->items[l].rtic;
+    unsigned long long rt = cnt->items[l].rtic, pr = cnt->items[l].pairs;
     uint32_t mi = ni, ml = nl;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -1190,13 +1194,14 @@ __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint
       nl += __shfl_xor(nl, o, 64);
       nr += __shfl_xor(nr, o, 64);
       rt += __shfl_xor(rt, o, 64);
+      pr += __shfl_xor(pr, o, 64);
       mi = max(mi, (uint32_t)__shfl_xor(mi, o, 64));
       ml = max(ml, (uint32_t)__shfl_xor(ml, o, 64));
     }
     if (l == 0) {
       Summary& S = cnt->sum;
       S.n_items = ni; S.n_large = nl; S.n_rows = nr; S.overflow = cnt->overflow;
-      S.max_items_shard = mi; S.max_large_shard = ml; S.rtic = rt;
+      S.max_items_shard = mi; S.max_large_shard = ml; S.rtic = rt; S.pairs = pr;
     }
   }
   if (g >= n) return;
