@@ -127,7 +127,10 @@ def main():
     ap.add_argument("--ranges", default="10,50,100",
                     help="range_max values (m) of the range-culling sweep ('' to skip)")
     ap.add_argument("--range-steps", type=int, default=10)
-    ap.add_argument("--tuning", default=None, help="JSON file of grca options")
+    ap.add_argument("--tuning", default="auto",
+                    help="JSON file of grca options; 'auto' (default) takes the autotuner's "
+                         "saved result for this GPU and workload if there is one, 'none' the "
+                         "library defaults")
     ap.add_argument("--opt", action="append", default=[], help="option override k=v")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device copy first (scale reference for PMC byte counters)")
@@ -163,8 +166,17 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = grca.Context(0)
     opts = {"item_capacity": 96 << 20, "large_capacity": 8 << 20}
-    if args.tuning and os.path.exists(args.tuning):
+    tuning = None
+    if args.tuning == "auto":
+        from paper_2605_10457_amd import autotune
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        t = autotune.load(arch, wl.name)
+        if t and t.get("signature") == autotune.signature(wl):
+            opts.update(t["options"])
+            tuning = f"{arch}_{wl.name}.json (autotuner)"
+    elif args.tuning and args.tuning != "none" and os.path.exists(args.tuning):
         opts.update(json.load(open(args.tuning)).get("options", {}))
+        tuning = args.tuning
     for kv in args.opt:
         k, v = kv.split("=")
         opts[k] = int(v)
@@ -350,6 +362,7 @@ def main():
                                f"{sc.num_triangles} tris ({sc.n_dynamic_tris} dynamic: 20 rigid "
                                "vehicle proxies with full-instant pose + 10 deforming grids), "
                                f"range 0.05-{args.range_max:g} m; batched hipGraph frame",
+                   "tuning": tuning,
                    "rays_per_frame": n_rays, "triangles": sc.num_triangles,
                    "dynamic_triangles": sc.n_dynamic_tris, "sensors": n_sens},
         "frame_ms": {"batched": {"mean": mean_b, "p50": pct(b_ms, 50), "p99": pct(b_ms, 99)},
