@@ -29,7 +29,8 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 struct SceneData {
   uint32_t nv = 0, ntri = 0;
   float *x = nullptr, *y = nullptr, *z = nullptr;
-  uint32_t* idx = nullptr;
+  uint32_t* idx = nullptr;   // index triples in tile order (Morton within dynamic groups)
+  uint32_t* orig = nullptr;  // caller triangle id of each stored slot
   // rigid instances
   uint32_t n_inst = 0;
   std::vector<uint32_t> inst_start, inst_count;
@@ -79,7 +80,7 @@ void dfree(T*& p) {
 }
 
 void free_scene(SceneData& s) {
-  dfree(s.x); dfree(s.y); dfree(s.z); dfree(s.idx);
+  dfree(s.x); dfree(s.y); dfree(s.z); dfree(s.idx); dfree(s.orig);
   dfree(s.rr_x); dfree(s.rr_y); dfree(s.rr_z); dfree(s.rigid_blocks);
   dfree(s.dr_x); dfree(s.dr_y); dfree(s.dr_z);
   dfree(s.dn_x); dfree(s.dn_y); dfree(s.dn_z); dfree(s.dphase);
@@ -92,6 +93,27 @@ void free_scene(SceneData& s) {
 
 void free_sensor(SensorData& s) {
   dfree(s.chan); dfree(s.chan_d); dfree(s.sin_tab); dfree(s.lut); dfree(s.az); dfree(s.mask);
+}
+
+// Store the scene's triangles in tile order: Morton order of the centroids
+// within each dynamic group (static geometry, each rigid instance, each
+// deforming range), so that the bounds pass's 64-triangle tiles are compact
+// and its tile-sphere test culls more.  `orig` keeps the caller's ids.
+hipError_t reorder_scene_dev(SceneData& sc, hipStream_t st) {
+  if (sc.ntri < 2 || sc.nv == 0) return hipSuccess;
+  uint32_t* vg = nullptr;
+  hipError_t e = dmalloc(&vg, sc.nv);
+  if (e != hipSuccess) return e;
+  e = launch_fill(vg, sc.nv, 0u, st);
+  for (uint32_t i = 0; e == hipSuccess && i < sc.n_inst; ++i)
+    e = launch_fill(vg + sc.inst_start[i], sc.inst_count[i], 1u + i, st);
+  for (uint32_t g = 0; e == hipSuccess && g < sc.n_groups; ++g)
+    e = launch_fill(vg + sc.groups[g].vertex_start, sc.groups[g].vertex_count,
+                    1u + sc.n_inst + g, st);
+  if (e == hipSuccess) e = order_triangles(sc.idx, sc.orig, sc.ntri, sc.x, sc.y, sc.z, sc.nv, vg, st);
+  (void)hipStreamSynchronize(st);
+  dfree(vg);
+  return e;
 }
 
 }  // namespace
@@ -328,7 +350,8 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
     if (k == 0 || sd[order[k - 1]]->desc.scene_id != sid) {
       const SceneData& sc = ctx->scenes.at(sid);
       DevScene ds{};
-      ds.x = sc.x; ds.y = sc.y; ds.z = sc.z; ds.idx = sc.idx; ds.ntri = sc.ntri;
+      ds.x = sc.x; ds.y = sc.y; ds.z = sc.z; ds.idx = sc.idx; ds.orig = sc.orig;
+      ds.ntri = sc.ntri;
       ds.tile_start = tiles;
       ds.sensor_begin = k;
       ds.sensor_end = k;
@@ -550,6 +573,13 @@ extern "C" const char* grca_last_error(const grca_context* ctx) {
 }
 
 // =============================================================== scenes
+grca_status reorder_scene(grca_context* ctx, SceneData& sc, hipStream_t st) {
+  const hipError_t e = reorder_scene_dev(sc, st);
+  if (e != hipSuccess)
+    return fail(ctx, GRCA_ERR_DEVICE, std::string("triangle tile order: ") + hipGetErrorString(e));
+  return GRCA_OK;
+}
+
 extern "C" grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id,
                                          const float* vertices_xyz, uint32_t num_vertices,
                                          const uint32_t* indices, uint32_t num_triangles,
@@ -599,12 +629,12 @@ extern "C" grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id,
       // topology change drops dynamic-geometry declarations
       HIPCHK(hipStreamSynchronize(st));
       SceneData keep;
-      keep.x = sc.x; keep.y = sc.y; keep.z = sc.z; keep.idx = sc.idx;
+      keep.x = sc.x; keep.y = sc.y; keep.z = sc.z; keep.idx = sc.idx; keep.orig = sc.orig;
       keep.nv = sc.nv; keep.ntri = sc.ntri;
-      sc.x = sc.y = sc.z = nullptr; sc.idx = nullptr;
+      sc.x = sc.y = sc.z = nullptr; sc.idx = nullptr; sc.orig = nullptr;
       free_scene(sc);
       sc = SceneData();
-      sc.x = keep.x; sc.y = keep.y; sc.z = keep.z; sc.idx = keep.idx;
+      sc.x = keep.x; sc.y = keep.y; sc.z = keep.z; sc.idx = keep.idx; sc.orig = keep.orig;
       sc.nv = keep.nv; sc.ntri = keep.ntri;
     }
     if (realloc_v) {
@@ -628,14 +658,21 @@ extern "C" grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id,
       if (sc.ntri != num_triangles || !sc.idx) {
         HIPCHK(hipStreamSynchronize(st));
         dfree(sc.idx);
+        dfree(sc.orig);
         HIPCHK(dmalloc(&sc.idx, 3ull * std::max(1u, num_triangles)));
+        HIPCHK(dmalloc(&sc.orig, std::max(1u, num_triangles)));
       }
       if (num_triangles)
         HIPCHK(hipMemcpyAsync(sc.idx, indices, 12ull * num_triangles,
                               dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+      HIPCHK(launch_iota(sc.orig, num_triangles, st));
       sc.ntri = num_triangles;
     }
     sc.nv = num_vertices;
+    if (!vonly) {
+      grca_status rc = reorder_scene(ctx, sc, st);
+      if (rc != GRCA_OK) return rc;
+    }
     if (tmp) {
       HIPCHK(hipStreamSynchronize(st));
       dfree(tmp);
@@ -773,7 +810,7 @@ extern "C" grca_status grca_scene_set_rigid(grca_context* ctx, uint32_t scene_id
     rc = ensure_pose_block(ctx, sc);
     if (rc != GRCA_OK) return rc;
     HIPCHK(hipStreamSynchronize(st));
-    return GRCA_OK;
+    return reorder_scene(ctx, sc, st);
   })
 }
 
@@ -845,7 +882,7 @@ extern "C" grca_status grca_scene_set_deform(grca_context* ctx, uint32_t scene_i
     rc = ensure_pose_block(ctx, sc);
     if (rc != GRCA_OK) return rc;
     HIPCHK(hipStreamSynchronize(st));
-    return GRCA_OK;
+    return reorder_scene(ctx, sc, st);
   })
 }
 

@@ -67,7 +67,8 @@ struct DevScene {
   const float* x;
   const float* y;
   const float* z;
-  const uint32_t* idx;
+  const uint32_t* idx;   // index triples in tile order
+  const uint32_t* orig;  // caller triangle id of each stored slot (keys and outputs use it)
   uint32_t ntri;
   uint32_t tile_start;   // first 64-triangle tile of this scene in the cast
   uint32_t sensor_begin; // sensor slots [sensor_begin, sensor_end) observe it

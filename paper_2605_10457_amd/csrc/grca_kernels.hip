@@ -589,7 +589,7 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
               if (s.mask && !s.mask[gl]) continue;
               const float2 ca = s.az[ray];
               const unsigned long long key =
-                  ray_test(st, cp.x, cp.y, ca.x, ca.y, s.dmin, s.dmax, tri);
+                  ray_test(st, cp.x, cp.y, ca.x, ca.y, s.dmin, s.dmax, S.orig[tri]);
               if (key != KEY_INIT) key_min(keys, s.key_offset + gl, key);
             }
           }
@@ -918,6 +918,7 @@ struct IsectSensor {
   const float2* az;
   const uint8_t* mask;
   const uint32_t* idx;
+  const uint32_t* orig;
   const float* x;
   const float* y;
   const float* z;
@@ -931,7 +932,7 @@ __device__ inline IsectSensor isect_sensor(const DevScene* scenes, const DevSens
   const DevScene& S = scenes[s.scene];
   IsectSensor q;
   q.chan = s.chan; q.az = s.az; q.mask = s.mask;
-  q.idx = S.idx; q.x = S.x; q.y = S.y; q.z = S.z;
+  q.idx = S.idx; q.orig = S.orig; q.x = S.x; q.y = S.y; q.z = S.z;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     q.o[k] = s.o[k]; q.f[k] = s.f[k]; q.r[k] = s.r[k]; q.u[k] = s.u[k];
@@ -1049,7 +1050,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
               st_s[w][1][lane] = make_float4(st.n1y, st.n1z, st.n2x, st.n2y);
               st_s[w][2][lane] = make_float4(st.n2z, st.Nx, st.Ny, st.Nz);
               ItemInfo inf;
-              inf.tri = it.tri;
+              inf.tri = sq.orig[it.tri];  // keys carry the caller's triangle id
               inf.cr = (it.chan & 0xFFFFu) | (it.rays << 16);
               inf.rs = rc | (it.sensor << 16);
               inf.bias = 0;
@@ -1140,7 +1141,7 @@ __global__ void statics_kernel(const DevScene* __restrict__ scenes, const DevSen
                     S.z[i2], s, st)) {
     st = Statics{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1.0f, 0, 0, 0};
   }
-  out[t] = st;
+  out[S.orig[t]] = st;  // the all-pairs pass walks the caller's triangle ids
 }
 
 // One thread per ray, loop over a chunk of triangles; every ray is tested

@@ -61,4 +61,14 @@ hipError_t launch_soa(const float* xyz, uint32_t nv, float* x, float* y, float* 
                       hipStream_t st);
 hipError_t launch_copy(const float* src, float* dst, uint32_t n, hipStream_t st);
 
+// Tile order of a scene (grca_order.hip): rewrites idx (3 x ntri) in Morton
+// order of triangle centroids within each dynamic group (vgroup[v] = group of
+// vertex v) and permutes orig (caller triangle id of each slot) alike.
+// Synchronises `st`; allocates and frees its own temporaries.
+hipError_t order_triangles(uint32_t* idx, uint32_t* orig, uint32_t ntri, const float* x,
+                           const float* y, const float* z, uint32_t nv, const uint32_t* vgroup,
+                           hipStream_t st);
+hipError_t launch_iota(uint32_t* a, uint32_t n, hipStream_t st);
+hipError_t launch_fill(uint32_t* a, uint32_t n, uint32_t v, hipStream_t st);
+
 }  // namespace grca
