@@ -207,8 +207,11 @@ typedef struct {
   uint64_t rtic;          /* ray-triangle intersection checks executed               */
   uint32_t recasts;       /* overflow-driven recasts                                 */
   uint32_t reserved;
-  uint64_t pairs_evaluated; /* of pairs_tested: those not culled by a tile's bounding-
-                               sphere test, whose span the bounds pass computed      */
+  uint64_t pairs_evaluated; /* of pairs_tested: those whose span the bounds pass
+                               computed (kept by the tile's and by the triangle's own
+                               bounding-sphere test)                                 */
+  uint64_t sphere_tests;    /* of pairs_tested: those not culled by the tile's bounding-
+                               sphere test, tested against the triangle's own sphere */
 } grca_stats;
 grca_status grca_last_stats(grca_context* ctx, grca_stats* out);
 

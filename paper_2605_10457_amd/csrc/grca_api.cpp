@@ -62,6 +62,7 @@ struct SensorData {
   float2* az = nullptr;
   uint8_t* mask = nullptr;
   uint32_t lut_size = 0;
+  float elev0 = 0.0f, inv_delev = 1.0f, elev_tol = 0.0f;  // channel grid (bounds pass)
   double dtheta = 0.0;
   float az_noise = 0.0f;
   bool wrap = false;
@@ -97,7 +98,7 @@ void free_sensor(SensorData& s) {
 
 // Store the scene's triangles in tile order: Morton order of the centroids
 // within each dynamic group (static geometry, each rigid instance, each
-// deforming range), so that the bounds pass's 64-triangle tiles are compact
+// deforming range), so that the bounds pass's tiles and their halves are compact
 // and its tile-sphere test culls more.  `orig` keeps the caller's ids.
 hipError_t reorder_scene_dev(SceneData& sc, hipStream_t st) {
   if (sc.ntri < 2 || sc.nv == 0) return hipSuccess;
@@ -309,7 +310,7 @@ void ws_free(grca_workspace* ws) {
 struct Plan {
   std::vector<DevSensor> sens;
   std::vector<DevScene> scenes;
-  uint32_t total_tiles = 0;  // 64-triangle tiles over the cast's scenes
+  uint32_t total_tiles = 0;  // bounds tiles (BOUNDS_TILE triangles) over the cast's scenes
   uint64_t rays = 0;
   uint64_t pairs = 0;
 };
@@ -355,7 +356,7 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
       ds.tile_start = tiles;
       ds.sensor_begin = k;
       ds.sensor_end = k;
-      tiles += (sc.ntri + 63) / 64;
+      tiles += (sc.ntri + BOUNDS_TILE - 1) / BOUNDS_TILE;
       P.scenes.push_back(ds);
     }
     DevScene& cur = P.scenes.back();
@@ -383,6 +384,9 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
     d.period_idx_d = kTwoPi / S.dtheta;
     d.chan = S.chan; d.chan_d = S.chan_d; d.sin_tab = S.sin_tab; d.bins = S.lut; d.az = S.az;
     d.mask = S.mask;
+    d.elev0 = S.elev0;
+    d.inv_delev = S.inv_delev;
+    d.elev_tol = S.elev_tol;
     d.az_noise = S.az_noise;
     d.cull_back = 0;
     if (flags & GRCA_CULL_BACKFACE) {
@@ -985,6 +989,20 @@ extern "C" grca_status grca_sensor_config(grca_context* ctx, uint32_t sensor_id,
     SensorData sd;
     sd.desc = *s;
     sd.elev.assign(s->channel_elevation_rad, s->channel_elevation_rad + s->num_channels);
+    {
+      // the channel elevations as a uniform grid (exact for evenly spaced
+      // tables) and the largest distance of a channel from it
+      const uint32_t g = s->num_channels;
+      const double e0 = (double)sd.elev[0];
+      const double step = g > 1 ? ((double)sd.elev[g - 1] - e0) / (double)(g - 1) : 1.0;
+      double tol = 0.0;
+      for (uint32_t j = 0; j < g; ++j)
+        tol = std::max(tol, std::fabs((double)sd.elev[j] - (e0 + (double)j * step)));
+      sd.elev0 = sd.elev[0];
+      sd.inv_delev = (float)(1.0 / step);
+      // + the FP32 rounding of 1 / step over the whole table
+      sd.elev_tol = (float)(tol * (1.0 + 1e-6) + 1e-6);
+    }
     sd.desc.channel_elevation_rad = nullptr;
     sd.dtheta = (double)s->fov_rad / (double)s->rays_per_channel;
     sd.wrap = std::fabs((double)s->fov_rad - kTwoPi) <= 1e-6;
@@ -1161,6 +1179,7 @@ extern "C" grca_status grca_last_stats(grca_context* ctx, grca_stats* out) {
     out->rtic = c.rtic;
     out->recasts = R.recasts;
     out->pairs_evaluated = c.pairs;
+    out->sphere_tests = c.tests;
     return GRCA_OK;
   })
 }

@@ -39,7 +39,8 @@ struct ChanBin {
   float s0, s1, s2;
 };
 
-// Per-cast sensor descriptor (device memory, read with wave-uniform indices).
+// Per-cast sensor descriptor (device memory; read with wave-uniform indices,
+// except in the span phase of the bounds pass, where each lane reads its own).
 struct DevSensor {
   float o[3], f[3], r[3], u[3];
   float dmin, dmax;
@@ -60,8 +61,13 @@ struct DevSensor {
   const float2* az;     // (cos theta_R, sin theta_R), FP32 (offsets included)
   const uint8_t* mask;  // optional active-ray mask at C * chi + R (nullptr: all on)
   float az_noise;       // max |azimuth offset| (radians), widens every azimuth span
-  uint32_t pad1;
+  // the channel elevations as a uniform grid, for the first test of the
+  // bounds pass: every channel j lies within elev_tol of elev0 + j / inv_delev
+  float elev0, inv_delev, elev_tol;
 };
+
+// Triangles per tile of the bounds pass: one wave, two triangles per lane.
+constexpr uint32_t BOUNDS_TILE = 128;
 
 struct DevScene {
   const float* x;
@@ -70,7 +76,7 @@ struct DevScene {
   const uint32_t* idx;   // index triples in tile order
   const uint32_t* orig;  // caller triangle id of each stored slot (keys and outputs use it)
   uint32_t ntri;
-  uint32_t tile_start;   // first 64-triangle tile of this scene in the cast
+  uint32_t tile_start;   // first bounds tile (BOUNDS_TILE triangles) of this scene in the cast
   uint32_t sensor_begin; // sensor slots [sensor_begin, sensor_end) observe it
   uint32_t sensor_end;
 };
@@ -92,7 +98,8 @@ struct alignas(256) Shard {
   uint32_t rows;            // row items appended by the expansion (statistic)
   unsigned long long rtic;  // candidate pairs executed from this shard (statistic)
   unsigned long long pairs; // (triangle, origin) spans computed (statistic)
-  uint32_t pad[56];
+  unsigned long long tests; // (triangle, origin) bounding-sphere tests (statistic)
+  uint32_t pad[54];
 };
 static_assert(sizeof(Shard) == 256, "one shard counter per 256-byte line");
 
@@ -106,6 +113,7 @@ struct Summary {
   uint32_t max_large_shard;  // largest request of one large-record shard
   unsigned long long rtic;   // candidate pairs executed
   unsigned long long pairs;  // (triangle, origin) spans computed
+  unsigned long long tests;  // (triangle, origin) bounding-sphere tests
 };
 
 // Device counters of one cast, cleared by the init kernel.

@@ -49,6 +49,9 @@ __device__ inline uint32_t lane_id() { return __lane_id(); }
 __device__ inline uint32_t first_lane(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
+__device__ inline float first_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
 __device__ inline unsigned long long first_lane(unsigned long long v) {
   return (unsigned long long)first_lane((uint32_t)v) |
          ((unsigned long long)first_lane((uint32_t)(v >> 32)) << 32);
@@ -128,6 +131,13 @@ __device__ inline uint32_t chan_bin(const DevSensor& s, float x) {
   return b > 0 ? (uint32_t)(b - 1) : 0u;
 }
 
+// A bin as one 16-byte load (a field-by-field read under conditions can
+// become a chain of dependent loads).
+__device__ inline ChanBin load_bin(const ChanBin* p) {
+  const uint4 q = *reinterpret_cast<const uint4*>(p);
+  return ChanBin{q.x, __uint_as_float(q.y), __uint_as_float(q.z), __uint_as_float(q.w)};
+}
+
 // first j with sin_tab[j] >= x (strict = false) or > x (strict = true), from
 // the bin's entry e
 __device__ inline uint32_t chan_resolve(const DevSensor& s, const ChanBin& e, float x,
@@ -146,7 +156,7 @@ __device__ inline uint32_t chan_resolve(const DevSensor& s, const ChanBin& e, fl
 }
 
 __device__ inline uint32_t chan_search(const DevSensor& s, float x, bool strict) {
-  return chan_resolve(s, s.bins[chan_bin(s, x)], x, strict);
+  return chan_resolve(s, load_bin(s.bins + chan_bin(s, x)), x, strict);
 }
 
 // atan2(y, x) in FP32 for the bounds pass, |error| <= 5e-7 rad for mx > 0
@@ -187,6 +197,36 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
     y[k] = fmaf(dx, s.r[0], fmaf(dy, s.r[1], dz * s.r[2]));
     z[k] = fmaf(dx, s.u[0], fmaf(dy, s.u[1], dz * s.u[2]));
     r2[k] = fmaf(x[k], x[k], fmaf(y[k], y[k], z[k] * z[k]));
+  }
+  // Vertical axis through the origin vs the triangle's horizontal projection
+  // (first, so that the world-space vertices and the sensor's f and r are
+  // not needed past this point).
+  bool pole = false;
+  if (need_pole) {
+    // The projection can only surround the axis if its bounding box holds
+    // the origin (margin well above the FP32 error of the local coordinates).
+    const float mg = 1e-6f * __builtin_amdgcn_sqrtf(fmaxf(r2[0], fmaxf(r2[1], r2[2])));
+    const bool box_out = (x[0] > mg && x[1] > mg && x[2] > mg) ||
+                         (x[0] < -mg && x[1] < -mg && x[2] < -mg) ||
+                         (y[0] > mg && y[1] > mg && y[2] > mg) ||
+                         (y[0] < -mg && y[1] < -mg && y[2] < -mg);
+    if (!box_out) {
+      // 2D edge functions q_k x (q_{k+1} - q_k), the edge taken from the
+      // world-space vertex difference so that no cancellation sets the error
+      float e[3], tol[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int k1 = (k + 1) % 3;
+        const float ex = vx[k1] - vx[k], ey = vy[k1] - vy[k], ez = vz[k1] - vz[k];
+        const float dxl = fmaf(ex, s.f[0], fmaf(ey, s.f[1], ez * s.f[2]));
+        const float dyl = fmaf(ex, s.r[0], fmaf(ey, s.r[1], ez * s.r[2]));
+        e[k] = x[k] * dyl - y[k] * dxl;
+        tol[k] = 4e-6f * __builtin_amdgcn_sqrtf(r2[k]) * (fabsf(dxl) + fabsf(dyl));
+      }
+      const bool in_pos = e[0] >= -tol[0] && e[1] >= -tol[1] && e[2] >= -tol[2];
+      const bool in_neg = e[0] <= tol[0] && e[1] <= tol[1] && e[2] <= tol[2];
+      pole = in_pos || in_neg;
+    }
   }
   // range prefilter: the triangle lies inside the blind ball (convex), or its
   // bounding sphere lies beyond range_max.
@@ -237,46 +277,22 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
     const float kb = __builtin_amdgcn_rsqf(fmaxf(0.5f * (1.0f + cmin), 1e-12f)) * (1.0f + 1e-6f);
     if (s_hi > 0.0f) s_hi = fminf(s_hi * kb, 1.0f);
     if (s_lo < 0.0f) s_lo = fmaxf(s_lo * kb, -1.0f);
-    // Vertical axis through the origin vs the triangle's horizontal projection.
-    if (need_pole) {
-      // The projection can only surround the axis if its bounding box holds
-      // the origin (margin well above the FP32 error of the local coordinates).
-      const float mg = 1e-6f * __builtin_amdgcn_sqrtf(fmaxf(r2[0], fmaxf(r2[1], r2[2])));
-      const bool box_out = (x[0] > mg && x[1] > mg && x[2] > mg) ||
-                           (x[0] < -mg && x[1] < -mg && x[2] < -mg) ||
-                           (y[0] > mg && y[1] > mg && y[2] > mg) ||
-                           (y[0] < -mg && y[1] < -mg && y[2] < -mg);
-      if (!box_out) {
-        // 2D edge functions q_k x (q_{k+1} - q_k), the edge taken from the
-        // world-space vertex difference so that no cancellation sets the error
-        float e[3], tol[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const int k1 = (k + 1) % 3;
-          const float ex = vx[k1] - vx[k], ey = vy[k1] - vy[k], ez = vz[k1] - vz[k];
-          const float dxl = fmaf(ex, s.f[0], fmaf(ey, s.f[1], ez * s.f[2]));
-          const float dyl = fmaf(ex, s.r[0], fmaf(ey, s.r[1], ez * s.r[2]));
-          e[k] = x[k] * dyl - y[k] * dxl;
-          tol[k] = 4e-6f * __builtin_amdgcn_sqrtf(r2[k]) * (fabsf(dxl) + fabsf(dyl));
-        }
-        const bool in_pos = e[0] >= -tol[0] && e[1] >= -tol[1] && e[2] >= -tol[2];
-        const bool in_neg = e[0] <= tol[0] && e[1] <= tol[1] && e[2] <= tol[2];
-        if (in_pos || in_neg) {
-          full = true;
-          const bool up = z[0] > 0.0f && z[1] > 0.0f && z[2] > 0.0f;
-          const bool dn = z[0] < 0.0f && z[1] < 0.0f && z[2] < 0.0f;
-          if (!dn) s_hi = 1.0f;
-          if (!up) s_lo = -1.0f;
-        }
-      }
+    // the projection surrounds the vertical axis: every elevation on the
+    // side(s) of the horizon the triangle reaches
+    if (pole) {
+      full = true;
+      const bool up = z[0] > 0.0f && z[1] > 0.0f && z[2] > 0.0f;
+      const bool dn = z[0] < 0.0f && z[1] < 0.0f && z[2] < 0.0f;
+      if (!dn) s_hi = 1.0f;
+      if (!up) s_lo = -1.0f;
     }
   }
   const float smax_abs = fmaxf(fabsf(s_lo), fabsf(s_hi));
   s_lo -= ETA_SIN;
   s_hi += ETA_SIN;
   // both bin loads in flight together
-  const ChanBin e_lo = s.bins[chan_bin(s, s_lo)];
-  const ChanBin e_hi = s.bins[chan_bin(s, s_hi)];
+  const ChanBin e_lo = load_bin(s.bins + chan_bin(s, s_lo));
+  const ChanBin e_hi = load_bin(s.bins + chan_bin(s, s_hi));
   const uint32_t c_from = chan_resolve(s, e_lo, s_lo, false);
   const uint32_t c_end = chan_resolve(s, e_hi, s_hi, true);
   if (c_from >= c_end) return false;
@@ -369,22 +385,38 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
   return true;
 }
 
-// Group-level culling (the "group" extension of the cone-triangle test to a
-// whole group of triangles): the wave's 64 consecutive triangles are bounded
-// by a sphere (centre c, radius rad, wave-uniform).  Returns true when no
-// ray of sensor `s` can reach anything inside the sphere: it lies beyond
-// range_max, or the band of elevations it subtends holds no channel, or (on
-// a partial-FOV sensor) the azimuths it subtends miss the field of view.
-// Conservative: any doubt (sphere near the origin, wide angles) keeps the group.
+// Sphere culling (the "group" extension of the cone-triangle test): a group
+// of triangles, a 64-triangle half of a bounds tile or a single triangle, is bounded
+// by a sphere (centre c, radius rad).  The verdict is `culled` when no ray of
+// sensor `s` can reach anything inside the sphere: it lies beyond range_max,
+// or the band of elevations it subtends holds no channel, or (AZ, on a
+// partial-FOV sensor) the azimuths it subtends miss the field of view.
+// Conservative: any doubt (sphere near the origin, wide angles) keeps it.
 struct GroupVerdict {
   bool culled;      // no ray of the sensor can reach the group
   bool need_range;  // the group straddles range_min or range_max: test triangles
   bool need_pole;   // the group touches the vertical axis through the origin
 };
 
-__device__ inline GroupVerdict group_test(float cx, float cy, float cz, float rad,
-                                          const DevSensor& s) {
-  GroupVerdict v{false, true, true};
+// A bounding sphere (centre c, radius rad) against sensor `s`, without
+// memory access besides the sensor's fields and without branches (so that
+// the fields are read together); about 70 FP32 operations, 100 with AZ.
+// Culled when the sphere lies beyond range_max, when no channel elevation
+// lies within alpha of the elevation of c, or (AZ, partial field of view)
+// when the azimuths it subtends miss the field of view.  For
+// sin(alpha) = r / D <= 1/2 every point of the sphere is within the angle
+// alpha <= asin(r / D) <= (r / D)(1 + (r / D)^2 / 3) of c's direction, so its
+// elevation is within alpha of c's; its azimuth is within asin(r / h) <=
+// 1.0472 r / h of c's when r / h <= 1/2 (h: c's distance from the vertical
+// axis).  The channels are taken as the uniform grid elev0 + j / inv_delev,
+// widened by elev_tol (the table's largest distance from that grid); the
+// margins cover the FP32 error of c's angles and of the ray test.
+// need_range: the sphere straddles range_min or range_max; need_pole: it
+// touches the vertical axis through the origin.  Used for the halves of a
+// bounds tile (AZ) and for single triangles.
+template <bool AZ>
+__device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float rad,
+                                           const DevSensor& s) {
   const float dx = cx - s.o[0], dy = cy - s.o[1], dz = cz - s.o[2];
   const float lf = fmaf(dx, s.f[0], fmaf(dy, s.f[1], dz * s.f[2]));
   const float lr = fmaf(dx, s.r[0], fmaf(dy, s.r[1], dz * s.r[2]));
@@ -392,54 +424,79 @@ __device__ inline GroupVerdict group_test(float cx, float cy, float cz, float ra
   const float h2 = fmaf(lf, lf, lr * lr);
   const float D2 = fmaf(lu, lu, h2);
   const float r = rad * 1.0001f + 1e-6f;
-  // the vertical line through the origin misses the sphere: no triangle of
-  // the group can surround it
-  v.need_pole = !(h2 > r * r * 1.0001f);
-  if (D2 <= 4.0f * r * r) return v;  // sphere within 30 deg of the origin: keep
-  const float D = sqrtf(D2);
-  if (D - r > s.dmax * (1.0f + 1e-5f) + 1e-6f) { v.culled = true; return v; }
-  v.need_range = !(D + r < s.dmax * (1.0f - 1e-5f) && D - r > s.dmin * (1.0f + 1e-5f));
-  const float invD = 1.0f / D;
-  const float sa = r * invD;                    // sin(alpha), alpha <= 30 deg
-  const float ca = sqrtf(fmaxf(1.0f - sa * sa, 0.0f));
-  const float hc = sqrtf(h2);
-  const float sc = lu * invD, cc = hc * invD;   // sin, cos of the centre's elevation
-  float s_hi = sc >= ca ? 1.0f : fmaf(sc, ca, cc * sa);
-  float s_lo = -sc >= ca ? -1.0f : fmaf(sc, ca, -cc * sa);
-  s_lo -= 1e-5f + ETA_SIN;
-  s_hi += 1e-5f + ETA_SIN;
-  const uint32_t j = chan_search(s, s_lo, false);
-  if (j >= s.gamma || s.sin_tab[j] > s_hi) { v.culled = true; return v; }
-  if (!s.wrap && hc > 2.0f * r) {
-    // asin(x) <= 1.0472 x for x = r / hc < 1/2
-    const float beta = 1.0472f * (r / hc) + 1e-4f + s.az_noise;
+  const float r2 = r * r;
+  const bool near = D2 <= 4.0f * r2;  // the origin is within 2r: keep
+  const float invD = __builtin_amdgcn_rsqf(D2);
+  const float D = D2 * invD;
+  const bool beyond = D - r > s.dmax * (1.0f + 1e-5f) + 1e-6f;
+  const bool inside = (uint32_t)(D + r < s.dmax * (1.0f - 1e-5f)) &
+                      (uint32_t)(D - r > s.dmin * (1.0f + 1e-5f));
+  const float sa = r * invD;
+  const float m = fmaf(sa * sa * (1.0f / 3.0f), sa, sa) + (2e-5f + s.elev_tol);
+  // elevation of c (h >= 0: in [-pi/2, pi/2], |error| <= 5e-7)
+  const float hc = __builtin_amdgcn_sqrtf(h2);
+  const float el = atan2_bounded(lu, hc);
+  const float j_lo = ceilf((el - m - s.elev0) * s.inv_delev);
+  const float j_hi = floorf((el + m - s.elev0) * s.inv_delev);
+  const bool band = fmaxf(j_lo, 0.0f) <= fminf(j_hi, (float)(s.gamma - 1u));
+  uint32_t out_fov = 0u;
+  if (AZ) {
+    const float beta = 1.0472f * r * __builtin_amdgcn_rcpf(hc) + 1e-4f + s.az_noise;
     const float az = atan2_bounded(lr, lf);
-    const float half = 0.5f * (float)(s.chi - 1) / s.inv_dtheta;
-    const float mid = s.theta_start + half;
-    float d = az - mid;
+    const float half = 0.5f * (float)(s.chi - 1u) * __builtin_amdgcn_rcpf(s.inv_dtheta);
+    float d = az - (s.theta_start + half);
     d -= TWO_PI_F * floorf((d + PI_F) * (1.0f / TWO_PI_F));
-    if (fabsf(d) > half + beta + 1e-4f) v.culled = true;
+    out_fov = (uint32_t)(s.wrap == 0u) & (uint32_t)(hc > 2.0f * r) &
+              (uint32_t)(fabsf(d) > half * 1.0001f + beta + 1e-4f);
   }
+  // (bitwise: a short-circuit would add branches)
+  const uint32_t far = (uint32_t)!near;
+  GroupVerdict v;
+  v.culled = (far & ((uint32_t)beyond | (uint32_t)!band | out_fov)) != 0u;
+  v.need_range = ((uint32_t)near | (uint32_t)!inside) != 0u;
+  v.need_pole = !(h2 > r2 * 1.0001f);
   return v;
 }
 
-__device__ inline float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return v;
+// Wave-wide minimum / maximum of floats by DPP row shifts and broadcasts (no
+// LDS round trips), read from the last lane: a wave-uniform value.  The
+// reduction is a maximum of unsigned keys with the order of the floats (the
+// complement for a minimum), for which 0, what a lane whose DPP source is
+// absent reads, is neutral; no NaN quieting is needed either.
+__device__ inline uint32_t float_ukey(float x) {
+  const uint32_t b = __float_as_uint(x);
+  return b ^ ((uint32_t)((int)b >> 31) | 0x80000000u);
 }
-__device__ inline float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
+__device__ inline float ukey_float(uint32_t k) {
+  return __uint_as_float(k ^ (((k >> 31) - 1u) | 0x80000000u));
 }
+__device__ inline uint32_t wave_max_key(uint32_t v) {
+#define GRCA_DPP_STEP(CTRL, ROWS) \
+  v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, ROWS, 0xf, true));
+  GRCA_DPP_STEP(0x111, 0xf)  // row_shr:1
+  GRCA_DPP_STEP(0x112, 0xf)  // row_shr:2
+  GRCA_DPP_STEP(0x114, 0xf)  // row_shr:4
+  GRCA_DPP_STEP(0x118, 0xf)  // row_shr:8
+  GRCA_DPP_STEP(0x142, 0xa)  // row_bcast:15
+  GRCA_DPP_STEP(0x143, 0xc)  // row_bcast:31
+#undef GRCA_DPP_STEP
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ inline float wave_max_dpp(float x) { return ukey_float(wave_max_key(float_ukey(x))); }
+__device__ inline float wave_min_dpp(float x) { return ukey_float(~wave_max_key(~float_ukey(x))); }
 
-__device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
-  // Blocks are handed to the 8 XCDs round robin; give each XCD a contiguous
-  // run of triangles so that shared vertices stay in one XCD's L2.
-  const uint32_t q = nb / 8u, rem = nb % 8u;
-  const uint32_t x = b % 8u, local = b / 8u;
-  return x * q + (x < rem ? x : rem) + local;
+// Block b's place in tile order.  Blocks are handed to the 8 XCDs round
+// robin and each XCD takes its blocks in order; here every XCD gets runs of
+// CHUNK consecutive blocks (neighbouring triangles share vertices in the
+// XCD's L2), the runs dealt to the XCDs in turn, so that all XCDs move
+// through the scene together and finish together whatever the distribution
+// of work in it.  Blocks past the last full round of runs keep their index.
+constexpr uint32_t XCD_CHUNK = 16;
+__device__ inline uint32_t xcd_chunked(uint32_t b, uint32_t nb) {
+  const uint32_t full = nb / (8u * XCD_CHUNK) * (8u * XCD_CHUNK);
+  if (b >= full) return b;
+  const uint32_t x = b % 8u, k = b / 8u;
+  return ((k / XCD_CHUNK) * 8u + x) * XCD_CHUNK + k % XCD_CHUNK;
 }
 
 // Candidate pairs of a work item (rectangle or row).
@@ -447,46 +504,23 @@ __device__ inline uint32_t item_candidates(const Item& it) {
   return (it.chan >> 16) * (it.rays >> 16);
 }
 
-// Append the `n` records of an LDS stage to an item shard: ONE 64-bit atomic
-// reserves both the slots and the candidate range (slots in the low word,
-// candidates in the high word, so the two stay in the same order); each
-// record is stored with its first candidate index, the stage's running
-// candidate prefix `pre[i]` plus the reserved base.  Within a shard the
-// candidate starts therefore increase with the slot, which is what lets the
-// intersection kernel hand out equal ranges of candidates.
-__device__ inline void flush_stage(const Item* stage, const uint32_t* pre, uint32_t n,
-                                   uint32_t cands, Shard& ctr, Item* q_items, uint32_t* q_cs,
-                                   uint32_t scap, uint32_t* overflow) {
-  const uint32_t lane = lane_id();
-  unsigned long long old = 0ull;
-  if (lane == 0) {
-    old = atomicAdd(&ctr.nc, (unsigned long long)n | ((unsigned long long)cands << 32));
-    // candidate index space of the shard (2^31, so tickets cannot wrap) exhausted
-    if ((uint32_t)(old >> 32) > CAND_LIMIT - cands) atomicOr(overflow, 4u);
-  }
-  old = first_lane(old);
-  const uint32_t base = (uint32_t)old, cbase = (uint32_t)(old >> 32);
-  bool ovf = false;
-  for (uint32_t i = lane; i < n; i += 64) {
-    const uint32_t slot = base + i;
-    if (slot < scap) {
-      q_items[slot] = stage[i];
-      q_cs[slot] = cbase + pre[i];
-    } else {
-      ovf = true;
-    }
-  }
-  if (__ballot(ovf) != 0ull && lane == 0) atomicOr(overflow, 1u);
-}
-
-// Bounds pass, one 64-triangle tile per wave (one triangle per lane).  For
-// every sensor observing the tile's scene the wave computes the candidate
-// span of each (triangle, sensor) pair.  Small-class records are compacted
-// into the wave's own LDS stage (no block barrier) and appended to the
-// wave's item shard when the stage fills and at the end; large-class records
-// go to the wave's large-record shard with one atomic per wave and sensor.
-// The plain variant is held to 64 VGPRs (8 waves per SIMD; no spills): the
-// pass is VALU-bound with memory waits that more resident waves hide.
+// Bounds pass, one 128-triangle tile per wave: lane l holds triangles l
+// and 64 + l of the tile (its two 64-triangle halves), so that every memory
+// round trip of the wave serves two triangles.  Two phases over the sensors
+// observing the tile's scene:
+//  1. one bounding-sphere test per half (lane k tests sensor k of each run of
+//     64 sensors) skips a sensor for that half; otherwise each lane tests its
+//     triangles' own bounding spheres against the sensor (elevation band and
+//     range only) and the surviving (triangle, sensor) pairs are queued in
+//     the wave's LDS ring;
+//  2. whenever 64 pairs are queued, and at the end, every lane takes one
+//     pair, reads the triangle's vertices from LDS and computes the pair's
+//     candidate span, with the sensor read per lane.
+// Most pairs that pass the half's test fail their triangle's own test (small
+// triangles between two channels), so the span, the costly part, runs on
+// full waves of likely survivors rather than on every lane of every sensor.
+// The records of a span batch go to the tile's item shard (small class) and
+// large-record shard (large class) with one atomic each.
 template <int WPB, bool INLINE>
 __global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
     const DevScene* __restrict__ scenes, uint32_t nscenes, uint32_t total_tiles,
@@ -494,80 +528,194 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
     Item* __restrict__ items, uint32_t* __restrict__ item_cs, uint32_t item_scap,
     Item* __restrict__ large, uint32_t large_scap, Counters* __restrict__ cnt,
     uint32_t group_cull, uint32_t inline_max, unsigned long long* __restrict__ keys) {
-  constexpr uint32_t STAGE = 256;  // records; one sensor step adds at most 128
-  __shared__ Item s_items[WPB][STAGE];
-  __shared__ uint32_t s_pre[WPB][STAGE];  // candidates staged before each record
+  constexpr uint32_t RING = 128;  // queued pairs: at most 63 wait when 64 arrive
+  // ring entry: triangle (0..127) | need_range << 7 | need_pole << 8 | sensor << 9
+  __shared__ uint32_t s_ring[WPB][RING];
+  __shared__ float s_vtx[WPB][9][BOUNDS_TILE];  // the tile's vertices (x0 y0 z0 x1 .. z2), by triangle
   const uint32_t w = wave_id();
   const uint32_t lane = lane_id();
-  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x) * WPB + w;
-  if (tile >= total_tiles) return;  // wave-uniform
-  const uint32_t shard = tile % NSHARD;
-  Item* const stage = s_items[w];
-  uint32_t* const pre = s_pre[w];
-  uint32_t staged = 0, staged_c = 0;  // records and their candidates in the stage
+  uint32_t* const ring = s_ring[w];
+  float (*const vtx)[BOUNDS_TILE] = s_vtx[w];
   const bool pack_scan = small_c * small_r <= 1023u;
+  const uint32_t tile = xcd_chunked(blockIdx.x, gridDim.x) * WPB + w;
+  if (tile >= total_tiles) return;  // wave-uniform
+  // records go to the tile's shard: neighbouring tiles, which hold similar
+  // work, spread over all shards
+  const uint32_t shard = tile % NSHARD;
 
   uint32_t sc = 0;
   while (sc + 1 < nscenes && tile >= scenes[sc + 1].tile_start) ++sc;
   const DevScene& S = scenes[sc];
-  const uint32_t tri = (tile - S.tile_start) * 64u + lane;
-  const bool active = tri < S.ntri;
-  float vx[3] = {0, 0, 0}, vy[3] = {0, 0, 0}, vz[3] = {0, 0, 0};
-  if (active) {
-    const uint32_t i0 = S.idx[3ull * tri], i1 = S.idx[3ull * tri + 1], i2 = S.idx[3ull * tri + 2];
-    vx[0] = S.x[i0]; vy[0] = S.y[i0]; vz[0] = S.z[i0];
-    vx[1] = S.x[i1]; vy[1] = S.y[i1]; vz[1] = S.z[i1];
-    vx[2] = S.x[i2]; vy[2] = S.y[i2]; vz[2] = S.z[i2];
-  }
-  // bounding sphere of the tile's triangles (AABB centre, max vertex distance)
-  float gcx = 0.0f, gcy = 0.0f, gcz = 0.0f, grad = 0.0f;
-  const bool any_active = __ballot(active) != 0ull;
-  if (group_cull && any_active) {
-    const float big = 3.0e38f;
-    const float mnx = wave_min(active ? fminf(vx[0], fminf(vx[1], vx[2])) : big);
-    const float mny = wave_min(active ? fminf(vy[0], fminf(vy[1], vy[2])) : big);
-    const float mnz = wave_min(active ? fminf(vz[0], fminf(vz[1], vz[2])) : big);
-    const float mxx = wave_max(active ? fmaxf(vx[0], fmaxf(vx[1], vx[2])) : -big);
-    const float mxy = wave_max(active ? fmaxf(vy[0], fmaxf(vy[1], vy[2])) : -big);
-    const float mxz = wave_max(active ? fmaxf(vz[0], fmaxf(vz[1], vz[2])) : -big);
-    gcx = 0.5f * (mnx + mxx);
-    gcy = 0.5f * (mny + mxy);
-    gcz = 0.5f * (mnz + mxz);
-    float r2 = 0.0f;
-    if (active) {
+  // the scene's fields as wave-uniform values: the loop below branches on them
+  const uint32_t s_begin = first_lane(S.sensor_begin), s_end = first_lane(S.sensor_end);
+  const uint32_t tri0 = first_lane((tile - S.tile_start) * BOUNDS_TILE);
+  const uint32_t ntri = first_lane(S.ntri);
+  // both halves' loads are issued before any is waited for
+  float v[2][9];
+  bool active[2];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const float ex = vx[k] - gcx, ey = vy[k] - gcy, ez = vz[k] - gcz;
-        r2 = fmaxf(r2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
-      }
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t t = tri0 + 64u * h + lane;
+    active[h] = t < ntri;
+    uint32_t i0 = 0, i1 = 0, i2 = 0;
+    if (active[h]) {
+      i0 = S.idx[3ull * t]; i1 = S.idx[3ull * t + 1]; i2 = S.idx[3ull * t + 2];
     }
-    grad = sqrtf(wave_max(r2));
+#pragma unroll
+    for (int c = 0; c < 9; ++c) v[h][c] = 0.0f;
+    if (active[h]) {
+      v[h][0] = S.x[i0]; v[h][1] = S.y[i0]; v[h][2] = S.z[i0];
+      v[h][3] = S.x[i1]; v[h][4] = S.y[i1]; v[h][5] = S.z[i1];
+      v[h][6] = S.x[i2]; v[h][7] = S.y[i2]; v[h][8] = S.z[i2];
+    }
+  }
+  // bounding spheres (AABB centre, largest vertex distance) of the lane's
+  // triangles and of each half; the span phase reads vertices from LDS
+  float tc[2][4];                     // centre x, y, z and radius, per half
+  float gs[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // the halves' spheres (wave-uniform)
+  bool any_active[2];
+  uint32_t n_active[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float mn[3], mx[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      mn[c] = fminf(v[h][c], fminf(v[h][3 + c], v[h][6 + c]));
+      mx[c] = fmaxf(v[h][c], fmaxf(v[h][3 + c], v[h][6 + c]));
+      tc[h][c] = 0.5f * (mn[c] + mx[c]);
+    }
+    float r2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float ex = v[h][3 * k] - tc[h][0], ey = v[h][3 * k + 1] - tc[h][1],
+                  ez = v[h][3 * k + 2] - tc[h][2];
+      r2 = fmaxf(r2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+    }
+    tc[h][3] = sqrtf(r2);
+    const unsigned long long am = __ballot(active[h]);
+    any_active[h] = am != 0ull;
+    n_active[h] = first_lane((uint32_t)__popcll(am));
+    if (group_cull && any_active[h]) {
+      const float big = 3.0e38f;
+      float g[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        g[c] = 0.5f * (wave_min_dpp(active[h] ? mn[c] : big) + wave_max_dpp(active[h] ? mx[c] : -big));
+      float gr2 = 0.0f;
+      if (active[h]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const float ex = v[h][3 * k] - g[0], ey = v[h][3 * k + 1] - g[1],
+                      ez = v[h][3 * k + 2] - g[2];
+          gr2 = fmaxf(gr2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+        }
+      }
+      // wave-uniform: kept in scalar registers
+      gs[h][0] = first_lane(g[0]);
+      gs[h][1] = first_lane(g[1]);
+      gs[h][2] = first_lane(g[2]);
+      gs[h][3] = first_lane(sqrtf(wave_max_dpp(gr2)));
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) vtx[c][64 * h + lane] = v[h][c];
   }
   unsigned long long rtic = 0ull;  // candidates tested inline by this lane
-  unsigned long long g_cull = 0ull, g_range = ~0ull, g_pole = ~0ull;
-  const uint32_t n_active = (uint32_t)__popcll(__ballot(active));
+  unsigned long long g_cull[2] = {0ull, 0ull}, g_range[2] = {~0ull, ~0ull},
+                     g_pole[2] = {~0ull, ~0ull};
+  uint32_t tested = 0;     // triangle sphere tests of this wave (wave-uniform statistic)
   uint32_t evaluated = 0;  // spans computed by this wave (wave-uniform statistic)
-  for (uint32_t n = S.sensor_begin; n < S.sensor_end; ++n) {
-    const uint32_t ln = (n - S.sensor_begin) & 63u;
-    if (ln == 0) {
-      // group verdicts for the next 64 sensors: lane k tests sensor n + k
-      g_cull = any_active ? 0ull : ~0ull;
-      g_range = g_pole = ~0ull;
-      if (group_cull && any_active) {
-        const uint32_t ns = n + lane;
-        GroupVerdict gv{false, true, true};
-        if (ns < S.sensor_end) gv = group_test(gcx, gcy, gcz, grad, sens[ns]);
-        g_cull = __ballot(gv.culled);
-        g_range = __ballot(gv.need_range);
-        g_pole = __ballot(gv.need_pole);
+  uint32_t head = 0, tail = 0;  // pairs taken from / queued into the ring
+  // Phase 1 runs in steps (sensor n, half h); the step of half 0 tests both
+  // halves (their table loads in flight together) and keeps half 1's verdict
+  // for the next step, so that a step queues at most 64 pairs.
+  uint32_t n = s_begin, h = 0;
+  bool keep1 = false;
+  uint32_t flags1 = 0;
+  for (;;) {
+    if (n < s_end) {
+      // ---- phase 1
+      const uint32_t ln = (n - s_begin) & 31u;
+      if (h == 0) {
+        if (ln == 0) {
+          // both halves' verdicts for the next 32 sensors in one pass: lane k
+          // tests half k / 32 against sensor n + k % 32
+          const uint32_t q = lane >> 5, ns = n + (lane & 31u);
+          const bool any = q ? any_active[1] : any_active[0];
+          bool cul = !any, nr = true, np = true;
+          if (group_cull && any && ns < s_end) {
+            const float cx = q ? gs[1][0] : gs[0][0], cy = q ? gs[1][1] : gs[0][1];
+            const float cz = q ? gs[1][2] : gs[0][2], cr = q ? gs[1][3] : gs[0][3];
+            const GroupVerdict gv = sphere_test<true>(cx, cy, cz, cr, sens[ns]);
+            cul = gv.culled;
+            nr = gv.need_range;
+            np = gv.need_pole;
+          }
+          const unsigned long long bc = first_lane(__ballot(cul));
+          const unsigned long long br = first_lane(__ballot(nr));
+          const unsigned long long bp = first_lane(__ballot(np));
+          g_cull[0] = bc & 0xFFFFFFFFull; g_cull[1] = bc >> 32;
+          g_range[0] = br & 0xFFFFFFFFull; g_range[1] = br >> 32;
+          g_pole[0] = bp & 0xFFFFFFFFull; g_pole[1] = bp >> 32;
+        }
+        const bool t0 = !((g_cull[0] >> ln) & 1ull), t1 = !((g_cull[1] >> ln) & 1ull);
+        if (t0 || t1) {  // wave-uniform
+          // every lane runs both tests (no branch: the sensor's fields are read once)
+          const DevSensor& s = sens[n];
+          const GroupVerdict v0 = sphere_test<false>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s);
+          const GroupVerdict v1 = sphere_test<false>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s);
+          tested += (t0 ? n_active[0] : 0u) + (t1 ? n_active[1] : 0u);
+          const bool keep0 = t0 && active[0] && !v0.culled;
+          keep1 = t1 && active[1] && !v1.culled;
+          const uint32_t flags0 = (uint32_t)(v0.need_range && ((g_range[0] >> ln) & 1ull)) |
+                                  ((uint32_t)(v0.need_pole && ((g_pole[0] >> ln) & 1ull)) << 1);
+          flags1 = (uint32_t)(v1.need_range && ((g_range[1] >> ln) & 1ull)) |
+                   ((uint32_t)(v1.need_pole && ((g_pole[1] >> ln) & 1ull)) << 1);
+          const unsigned long long m = __ballot(keep0);
+          if (keep0)
+            ring[(tail + (uint32_t)__popcll(m & __lanemask_lt())) % RING] =
+                lane | (flags0 << 7) | (n << 9);
+          tail = first_lane(tail + (uint32_t)__popcll(m));
+        } else {
+          keep1 = false;
+        }
+        h = 1;
+      } else {
+        const unsigned long long m = __ballot(keep1);
+        if (keep1)
+          ring[(tail + (uint32_t)__popcll(m & __lanemask_lt())) % RING] =
+              (64u + lane) | (flags1 << 7) | (n << 9);
+        tail = first_lane(tail + (uint32_t)__popcll(m));
+        h = 0;
+        ++n;
       }
     }
-    if ((g_cull >> ln) & 1ull) continue;  // wave-uniform
-    evaluated += n_active;
-    const DevSensor& s = sens[n];
+    const bool drain = n >= s_end;
+    const uint32_t avail = tail - head;
+    if (avail < 64u && !(drain && avail > 0u)) {
+      if (drain) break;
+      continue;
+    }
+    // ---- phase 2: spans of up to 64 queued pairs, one per lane
+    const uint32_t cnt_b = avail < 64u ? avail : 64u;
+    wave_sync();
+    const bool live = lane < cnt_b;
+    const uint32_t e = ring[(head + (live ? lane : 0u)) % RING];
+    head = first_lane(head + cnt_b);
+    evaluated += cnt_b;
+    const uint32_t src = e & 127u;
+    const uint32_t pn = live ? (e >> 9) : s_begin;
+    float px[3], py[3], pz[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      px[k] = vtx[3 * k][src];
+      py[k] = vtx[3 * k + 1][src];
+      pz[k] = vtx[3 * k + 2][src];
+    }
+    const uint32_t ptri = tri0 + src;
+    const DevSensor& s = sens[pn];
     Span sp;
-    const bool ok = active && span_of(vx, vy, vz, s, small_c, small_r, (g_range >> ln) & 1ull,
-                                      (g_pole >> ln) & 1ull, sp);
+    const bool ok = live && span_of(px, py, pz, s, small_c, small_r, (e >> 7) & 1u,
+                                    (e >> 8) & 1u, sp);
     const uint32_t chan = ok ? (sp.c_from | (sp.c_count << 16)) : 0u;
     const bool is_large = ok && sp.large;
     bool rect0 = ok && !sp.large;
@@ -578,7 +726,8 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
     if (INLINE && __ballot(tiny) != 0ull) {
       if (tiny) {
         Statics st;
-        if (make_statics(vx[0], vy[0], vz[0], vx[1], vy[1], vz[1], vx[2], vy[2], vz[2], s, st)) {
+        if (make_statics(px[0], py[0], pz[0], px[1], py[1], pz[1], px[2], py[2], pz[2], s, st)) {
+          const uint32_t otri = S.orig[ptri];
           for (uint32_t c = 0; c < sp.c_count; ++c) {
             const uint32_t ch = sp.c_from + c;
             const float2 cp = s.chan[ch];
@@ -589,7 +738,7 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
               if (s.mask && !s.mask[gl]) continue;
               const float2 ca = s.az[ray];
               const unsigned long long key =
-                  ray_test(st, cp.x, cp.y, ca.x, ca.y, s.dmin, s.dmax, S.orig[tri]);
+                  ray_test(st, cp.x, cp.y, ca.x, ca.y, s.dmin, s.dmax, otri);
               if (key != KEY_INIT) key_min(keys, s.key_offset + gl, key);
             }
           }
@@ -598,23 +747,18 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
       }
       rect0 = rect0 && !tiny;
     }
-    const Item lg{tri, chan, 0u, n};
+    const Item lg{ptri, chan, 0u, pn};
     wave_push(is_large, lg, large + (size_t)shard * large_scap, large_scap,
               reinterpret_cast<uint32_t*>(&cnt->large[shard].nc), &cnt->overflow, 2u, nullptr);
-    // wave compaction of the small-class records into the LDS stage
+    // the batch's small-class records: rect0 records first, then rect1, all
+    // appended to the wave's item shard with one 64-bit atomic that reserves
+    // the slots (low word) and the candidate range (high word) together;
+    // each record carries its first candidate index, so that within a shard
+    // the candidate starts increase with the slot
     const unsigned long long m0 = __ballot(rect0), m1 = __ballot(rect1);
-    const uint32_t c0 = (uint32_t)__popcll(m0), c1 = (uint32_t)__popcll(m1);
+    const uint32_t c0 = first_lane((uint32_t)__popcll(m0));
+    const uint32_t c1 = first_lane((uint32_t)__popcll(m1));
     if (c0 == 0u) continue;
-    if (staged + c0 + c1 > STAGE) {
-      wave_sync();
-      flush_stage(stage, pre, staged, staged_c, cnt->items[shard],
-                  items + (size_t)shard * item_scap, item_cs + (size_t)shard * item_scap,
-                  item_scap, &cnt->overflow);
-      wave_sync();
-      staged = 0;
-      staged_c = 0;
-    }
-    // candidate prefix of the new records: the rect0 records first, then rect1
     const uint32_t k0 = rect0 ? sp.c_count * sp.r0_count : 0u;
     const uint32_t k1 = rect1 ? sp.c_count * sp.r1_count : 0u;
     uint32_t i0, i1, t0, t1;
@@ -628,27 +772,42 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
       t0 = __shfl(i0, 63, 64);
       t1 = __shfl(i1, 63, 64);
     }
+    Shard& sh = cnt->items[shard];
+    unsigned long long old = 0ull;
+    if (lane == 0) {
+      const uint32_t cands = t0 + t1;
+      old = atomicAdd(&sh.nc, (unsigned long long)(c0 + c1) | ((unsigned long long)cands << 32));
+      // candidate index space of the shard (2^31, so tickets cannot wrap) exhausted
+      if ((uint32_t)(old >> 32) > CAND_LIMIT - cands) atomicOr(&cnt->overflow, 4u);
+    }
+    old = first_lane(old);
+    const uint32_t base = (uint32_t)old, cbase = (uint32_t)(old >> 32);
+    Item* const q_items = items + (size_t)shard * item_scap;
+    uint32_t* const q_cs = item_cs + (size_t)shard * item_scap;
     const unsigned long long lt = __lanemask_lt();
+    bool ovf = false;
     if (rect0) {
-      const uint32_t slot = staged + (uint32_t)__popcll(m0 & lt);
-      stage[slot] = Item{tri, chan, sp.r0_start | (sp.r0_count << 16), n};
-      pre[slot] = staged_c + i0 - k0;
+      const uint32_t slot = base + (uint32_t)__popcll(m0 & lt);
+      if (slot < item_scap) {
+        q_items[slot] = Item{ptri, chan, sp.r0_start | (sp.r0_count << 16), pn};
+        q_cs[slot] = cbase + i0 - k0;
+      } else {
+        ovf = true;
+      }
     }
     if (rect1) {
-      const uint32_t slot = staged + c0 + (uint32_t)__popcll(m1 & lt);
-      stage[slot] = Item{tri, chan, sp.r1_start | (sp.r1_count << 16), n};
-      pre[slot] = staged_c + t0 + i1 - k1;
+      const uint32_t slot = base + c0 + (uint32_t)__popcll(m1 & lt);
+      if (slot < item_scap) {
+        q_items[slot] = Item{ptri, chan, sp.r1_start | (sp.r1_count << 16), pn};
+        q_cs[slot] = cbase + t0 + i1 - k1;
+      } else {
+        ovf = true;
+      }
     }
-    staged += c0 + c1;
-    staged_c += t0 + t1;
-  }
-  if (staged > 0u) {
-    wave_sync();
-    flush_stage(stage, pre, staged, staged_c, cnt->items[shard],
-                items + (size_t)shard * item_scap, item_cs + (size_t)shard * item_scap,
-                item_scap, &cnt->overflow);
+    if (__ballot(ovf) != 0ull && lane == 0) atomicOr(&cnt->overflow, 1u);
   }
   if (lane == 0 && evaluated) atomicAdd(&cnt->items[shard].pairs, (unsigned long long)evaluated);
+  if (lane == 0 && tested) atomicAdd(&cnt->items[shard].tests, (unsigned long long)tested);
   if (INLINE) {
     unsigned long long r = rtic;
 #pragma unroll
@@ -1188,6 +1347,7 @@ __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint
     uint32_t ni = (uint32_t)cnt->items[l].nc, nl = (uint32_t)cnt->large[l].nc;
     uint32_t nr = cnt->items[l].rows;
     unsigned long long rt = cnt->items[l].rtic, pr = cnt->items[l].pairs;
+    unsigned long long te = cnt->items[l].tests;
     uint32_t mi = ni, ml = nl;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -1196,6 +1356,7 @@ __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint
       nr += __shfl_xor(nr, o, 64);
       rt += __shfl_xor(rt, o, 64);
       pr += __shfl_xor(pr, o, 64);
+      te += __shfl_xor(te, o, 64);
       mi = max(mi, (uint32_t)__shfl_xor(mi, o, 64));
       ml = max(ml, (uint32_t)__shfl_xor(ml, o, 64));
     }
@@ -1203,6 +1364,7 @@ __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint
       Summary& S = cnt->sum;
       S.n_items = ni; S.n_large = nl; S.n_rows = nr; S.overflow = cnt->overflow;
       S.max_items_shard = mi; S.max_large_shard = ml; S.rtic = rt; S.pairs = pr;
+      S.tests = te;
     }
   }
   if (g >= n) return;
@@ -1327,14 +1489,15 @@ hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t tota
   case B: {                                                                                   \
     constexpr uint32_t W = B / 64;                                                            \
     const uint32_t nb = cdiv(total_tiles, W);                                                 \
-    if (inline_max)                                                                           \
+    if (inline_max) {                                                                         \
       hipLaunchKernelGGL((bounds_kernel<W, true>), dim3(nb), dim3(B), 0, st, scenes, nscenes,  \
                          total_tiles, sens, small_c, small_r, items, item_cs, item_scap, large, \
                          large_scap, cnt, group_cull, inline_max, keys);                       \
-    else                                                                                      \
+    } else {                                                                                  \
       hipLaunchKernelGGL((bounds_kernel<W, false>), dim3(nb), dim3(B), 0, st, scenes, nscenes, \
                          total_tiles, sens, small_c, small_r, items, item_cs, item_scap, large, \
                          large_scap, cnt, group_cull, 0u, keys);                               \
+    }                                                                                         \
     break;                                                                                    \
   }
   switch (block) {

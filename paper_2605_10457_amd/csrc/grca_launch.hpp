@@ -26,7 +26,7 @@ struct DeformParam {
 
 hipError_t launch_init(unsigned long long* keys, uint32_t n, Counters* cnt, hipStream_t st);
 // Queues (items, statics, large records) are NSHARD regions of `*_scap`
-// entries each; `total_tiles` counts 64-triangle tiles over the cast's scenes.
+// entries each; `total_tiles` counts bounds tiles (BOUNDS_TILE triangles) over the cast's scenes.
 // `item_cs` holds each item's first candidate index within its shard.
 hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t total_tiles,
                          uint32_t block, const DevSensor* sens, uint32_t small_c, uint32_t small_r,

@@ -68,7 +68,7 @@ class Stats(ctypes.Structure):
                 ("rect_items", ctypes.c_uint64), ("large_records", ctypes.c_uint64),
                 ("row_items", ctypes.c_uint64), ("rtic", ctypes.c_uint64),
                 ("recasts", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("pairs_evaluated", ctypes.c_uint64)]
+                ("pairs_evaluated", ctypes.c_uint64), ("sphere_tests", ctypes.c_uint64)]
 
 
 class Options(ctypes.Structure):
