@@ -37,11 +37,19 @@ HBM_PEAK_GBS = 8000.0
 # 157.3 TFLOP/s counts the packed (2-wide) FMA.
 FP32_PEAK_TFLOPS = 78.6
 FLOPS_PER_RTIC = 22               # ray test: 2 mul (direction) + 4 dot products x 5 flops
-# Candidate span of one (triangle, origin) pair on the common path (no range
-# or pole test, azimuth offsets by the series bound): transform 54, |p|^2 15,
-# sines 6, edge bulge 27, margins 2, channel bins 4, atan2 of vertex 0 20,
-# offsets of vertices 1-2 28, full-turn test 1, azimuth margin 6, ray-index
-# range 12 (add/sub/mul/rsq/rcp = 1, fma = 2; compares, min/max not counted).
+# Bounds pass, counting add/sub/mul/rsq/rcp/sqrt = 1, fma = 2 (compares,
+# min/max, floor/ceil and selects not counted):
+# * bounding-sphere test of one (triangle, origin) pair: offset 3, local
+#   frame 15, |.|^2 5, radius 3, near 1, distance 2, range 7, angular radius
+#   7, sqrt 1, atan2 20, channel-grid indices 6, pole 1;
+# * the same test of a 64-triangle half of a tile against one origin, plus
+#   its azimuth test: 38 more;
+# * candidate span of one pair on the common path (no range or pole test,
+#   azimuth offsets by the series bound): transform 54, |p|^2 15, sines 6,
+#   edge bulge 27, margins 2, channel bins 4, atan2 of vertex 0 20, offsets of
+#   vertices 1-2 28, full-turn test 1, azimuth margin 6, ray-index range 12.
+FLOPS_PER_SPHERE = 71
+FLOPS_PER_HALF_TEST = 109
 FLOPS_PER_SPAN = 175
 
 
@@ -302,14 +310,18 @@ def main():
                 "traffic": load_traffic("isect_kernel"),
                 "work": f"{FLOPS_PER_RTIC} FP32 flops x {stats['rtic']} RTIC per launch"}
     elif dom == "bounds":
-        # VALU-bound: FP32 flops of the spans the pass computed
-        flops = FLOPS_PER_SPAN * stats["pairs_evaluated"]
+        # VALU-bound: FP32 flops of the tests and spans the pass computed
+        half_tests = -(-int(sc.num_triangles) // 64) * n_sens
+        flops = (FLOPS_PER_HALF_TEST * half_tests + FLOPS_PER_SPHERE * stats["sphere_tests"] +
+                 FLOPS_PER_SPAN * stats["pairs_evaluated"])
         achieved = flops / (stage_ms["bounds"] * 1e-3) / 1e12
         roof = {"kernel": "bounds_kernel", "bound": "alu", "achieved": achieved,
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                 "traffic": load_traffic("bounds_kernel"),
-                "work": f"{FLOPS_PER_SPAN} FP32 flops x {stats['pairs_evaluated']} "
-                        f"(triangle, origin) spans per launch"}
+                "work": f"{FLOPS_PER_HALF_TEST} FP32 flops x {half_tests} tile-half tests + "
+                        f"{FLOPS_PER_SPHERE} x {stats['sphere_tests']} triangle sphere tests + "
+                        f"{FLOPS_PER_SPAN} x {stats['pairs_evaluated']} (triangle, origin) spans "
+                        f"per launch"}
     else:
         nbytes = 20 * stats["large_records"] + 20 * stats["row_items"]
         achieved = nbytes / (stage_ms[dom] * 1e-3) / 1e9
@@ -373,7 +385,7 @@ def main():
         "host_wall_ms_per_frame": wall_batched * 1e3 / args.steps,
         "stage_ms": stage_ms,
         "rtic_per_frame": stats["rtic"], "rtic_per_s": rtic_s,
-        "work": {k: stats[k] for k in ("pairs_tested", "pairs_evaluated", "rect_items",
+        "work": {k: stats[k] for k in ("pairs_tested", "sphere_tests", "pairs_evaluated", "rect_items",
                                        "large_records", "row_items")},
         "range_sweep": sweep,
         "roofline": roof,

@@ -70,14 +70,21 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Inclusive prefix sum over the wave by DPP: row shifts within each row of
+// 16 lanes (a lane with no source reads 0), then the row totals broadcast
+// to the following rows.  No LDS round trips.
 __device__ inline uint32_t wave_incl_scan(uint32_t v) {
-  const uint32_t lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t t = __shfl_up(v, o, 64);
-    if (lane >= (uint32_t)o) v += t;
-  }
+  v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x111, 0xf, 0xf, true);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x112, 0xf, 0xf, true);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x114, 0xf, 0xf, true);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x118, 0xf, 0xf, true);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return v;
+}
+// The value of lane 63, as a wave-uniform value.
+__device__ inline uint32_t last_lane(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // Append one record per lane with `want` set, one atomic per wave.
@@ -93,7 +100,7 @@ __device__ inline void wave_push(bool want, const Item& rec, Item* q, uint32_t c
     base = atomicAdd(counter, n);
     if (stat) atomicAdd(stat, n);
   }
-  base = __shfl(base, leader, 64);
+  base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
   if (want) {
     const uint32_t rank = (uint32_t)__popcll(mask & __lanemask_lt());
     const uint32_t slot = base + rank;
@@ -764,13 +771,13 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
     uint32_t i0, i1, t0, t1;
     if (pack_scan) {  // both counts <= 1023: one scan of (k0 | k1 << 16)
       const uint32_t pk = wave_incl_scan(k0 | (k1 << 16));
-      const uint32_t tt = __shfl(pk, 63, 64);
+      const uint32_t tt = last_lane(pk);
       i0 = pk & 0xFFFFu; i1 = pk >> 16; t0 = tt & 0xFFFFu; t1 = tt >> 16;
     } else {
       i0 = wave_incl_scan(k0);
       i1 = wave_incl_scan(k1);
-      t0 = __shfl(i0, 63, 64);
-      t1 = __shfl(i1, 63, 64);
+      t0 = last_lane(i0);
+      t1 = last_lane(i1);
     }
     Shard& sh = cnt->items[shard];
     unsigned long long old = 0ull;
@@ -1021,14 +1028,15 @@ __global__ __launch_bounds__(WPB * 64) void expand_kernel(
         }
         const uint32_t incl = wave_incl_scan(nitems);
         const uint32_t cincl = wave_incl_scan(ncand);
-        const uint32_t total = __shfl(incl, 63, 64);
-        const uint32_t ctotal = __shfl(cincl, 63, 64);
+        const uint32_t total = last_lane(incl);
+        const uint32_t ctotal = last_lane(cincl);
         if (total == 0) continue;
         unsigned long long old = 0ull;
         if (lane == 63)
           old = atomicAdd(&cnt->items[out_shard].nc,
                           (unsigned long long)total | ((unsigned long long)ctotal << 32));
-        old = __shfl(old, 63, 64);
+        old = (unsigned long long)__builtin_amdgcn_readlane((int)(uint32_t)old, 63) |
+              ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(old >> 32), 63) << 32);
         rows += total;
         uint32_t slot = (uint32_t)old + incl - nitems;
         uint32_t cs = (uint32_t)(old >> 32) + cincl - ncand;
@@ -1224,7 +1232,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
         const uint32_t incl = wave_incl_scan(count);
         const uint32_t excl = incl - count;  // batch position of this item's first candidate
         if (count) in_s[w][lane].bias = (int32_t)skip - (int32_t)excl;
-        const uint32_t total = __shfl(incl, 63, 64);
+        const uint32_t total = last_lane(incl);
         rtic += total;
         // Owner of batch position p: the last item with a candidate whose first
         // position is <= p.  Per window of 64 positions, each item starting in
