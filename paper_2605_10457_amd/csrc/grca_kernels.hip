@@ -528,8 +528,16 @@ __device__ inline uint32_t item_candidates(const Item& it) {
 // full waves of likely survivors rather than on every lane of every sensor.
 // The records of a span batch go to the tile's item shard (small class) and
 // large-record shard (large class) with one atomic each.
+// Resident waves per SIMD the plain bounds pass is compiled for: 7 leaves it
+// 72 VGPRs, enough for the span phase without spills (at 8 waves, 64 VGPRs,
+// the spills cost more than the extra wave gains).
+constexpr int BOUNDS_WAVES_PER_SIMD = 7;
+
 template <int WPB, bool INLINE>
-__global__ __launch_bounds__(WPB * 64, INLINE ? 1 : 8) void bounds_kernel(
+__global__ __launch_bounds__(WPB * 64, INLINE ? 1
+                                              : (4 * BOUNDS_WAVES_PER_SIMD / WPB > 0
+                                                     ? 4 * BOUNDS_WAVES_PER_SIMD / WPB
+                                                     : 1)) void bounds_kernel(
     const DevScene* __restrict__ scenes, uint32_t nscenes, uint32_t total_tiles,
     const DevSensor* __restrict__ sens, uint32_t small_c, uint32_t small_r,
     Item* __restrict__ items, uint32_t* __restrict__ item_cs, uint32_t item_scap,
