@@ -494,11 +494,13 @@ __device__ inline float wave_min_dpp(float x) { return ukey_float(~wave_max_key(
 
 // Block b's place in tile order.  Blocks are handed to the 8 XCDs round
 // robin and each XCD takes its blocks in order; here every XCD gets runs of
-// CHUNK consecutive blocks (neighbouring triangles share vertices in the
+// XCD_CHUNK consecutive blocks (neighbouring triangles share vertices in the
 // XCD's L2), the runs dealt to the XCDs in turn, so that all XCDs move
 // through the scene together and finish together whatever the distribution
-// of work in it.  Blocks past the last full round of runs keep their index.
-constexpr uint32_t XCD_CHUNK = 16;
+// of work in it.  Longer runs fetch fewer vertex lines twice (from two
+// XCDs); 64 blocks (256 tiles) cost no time over 16.  Blocks past the last
+// full round of runs keep their index.
+constexpr uint32_t XCD_CHUNK = 64;
 __device__ inline uint32_t xcd_chunked(uint32_t b, uint32_t nb) {
   const uint32_t full = nb / (8u * XCD_CHUNK) * (8u * XCD_CHUNK);
   if (b >= full) return b;
@@ -606,7 +608,9 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
                   ez = v[h][3 * k + 2] - tc[h][2];
       r2 = fmaxf(r2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
     }
-    tc[h][3] = sqrtf(r2);
+    // hardware square root (1 ulp; a denormal r2 may give 0): the sphere
+    // tests widen every radius by 1e-4 relative and 1e-6 m
+    tc[h][3] = __builtin_amdgcn_sqrtf(r2);
     const unsigned long long am = __ballot(active[h]);
     any_active[h] = am != 0ull;
     n_active[h] = first_lane((uint32_t)__popcll(am));
@@ -629,7 +633,7 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
       gs[h][0] = first_lane(g[0]);
       gs[h][1] = first_lane(g[1]);
       gs[h][2] = first_lane(g[2]);
-      gs[h][3] = first_lane(sqrtf(wave_max_dpp(gr2)));
+      gs[h][3] = first_lane(__builtin_amdgcn_sqrtf(wave_max_dpp(gr2)));
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) vtx[c][64 * h + lane] = v[h][c];
@@ -1291,9 +1295,14 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
           if (sn.mask && !sn.mask[gl]) continue;
           const float2 cp = sn.chan[ch];
           const float2 ca = sn.az[ray];
+          // the ray's key as this wave can see it (never below the true
+          // minimum: keys only decrease), read with the table entries; a hit
+          // that cannot improve on it issues no atomic
+          const uint32_t kidx = sn.key_offset + gl;
+          const unsigned long long seen = keys[kidx];
           const unsigned long long key = ray_test(st, cp.x, cp.y, ca.x, ca.y, sn.dmin, sn.dmax,
                                                   inf.tri);
-          if (key != KEY_INIT) key_min(keys, sn.key_offset + gl, key);
+          if (key < seen) key_min(keys, kidx, key);
         }
         wave_sync();
         if (last) break;
