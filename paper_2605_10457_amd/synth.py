@@ -495,6 +495,32 @@ def config4(seed_extra: int = 0, range_max: float = 1000.0, scale: float = 1.0) 
     return Workload("config4", sc, sens, 128)
 
 
+def colocated_rig(origins, heads: int = 4, channels: int = 128, rays: int = 4096,
+                  range_max: float = 1000.0):
+    """Rigs of co-located heads: at each origin, `heads` sensors with yaws
+    2*pi*j/heads, each covering 360/heads degrees, on the same full-vertical
+    channel grid (several oriented LiDARs sharing one origin)."""
+    out = []
+    for o in origins:
+        a0 = math.atan2(float(o[1]), float(o[0]))
+        for j in range(heads):
+            yaw = a0 + 2 * math.pi * j / heads
+            out.append(sensor(o, yaw, elevations_full_sphere(channels), rays, 360.0 / heads,
+                              range_max=range_max))
+    return out
+
+
+def config4_colocated(seed_extra: int = 0, range_max: float = 1000.0,
+                      scale: float = 1.0) -> Workload:
+    """Config 4's scene seen by 2 rigs of 4 co-located 90-degree heads of 128x4096
+    rays (the same 4.19M rays per frame), at the ring origins of config 4's
+    sensors 0 and 4."""
+    base = config4(seed_extra, range_max, scale)
+    origins = [base.sensors[0]["origin"], base.sensors[4]["origin"]]
+    sens = colocated_rig(origins, range_max=range_max)
+    return Workload("config4_colocated", base.scene, sens, base.oracle_rays_per_sensor)
+
+
 def client_workload(client: int, seed_extra: int = 0, tri_scale: float = 1.0) -> Workload:
     """One serving client: its own scene of 0.5-4M triangles (30-50% dynamic)
     built with config 3's recipe scaled, and 1-4 sensors drawn from

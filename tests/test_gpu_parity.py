@@ -248,3 +248,32 @@ def test_azimuth_noise_and_ray_mask(ctx):
     assert np.array_equal(t2, tm)
     with pytest.raises(grca.GrcaError):
         ctx.sensor_config(6, dict(s, azimuth_offset=np.full(512, 2 * step, np.float32)), 0)
+
+
+def test_colocated_heads(ctx):
+    _say("co-located heads: 2 rigs of 4 x 90-degree heads (one head with a shorter range), "
+         "one cast vs all-pairs per head and the oracle")
+    wl = synth.config1()
+    v, f = wl.scene.vertices, wl.scene.indices
+    ctx.scene_update(0, v, f)
+    rig = synth.colocated_rig([np.array([0.0, 0.0, 1.8], np.float32),
+                               np.array([10.0, -5.0, 2.2], np.float32)],
+                              heads=4, channels=32, rays=512)
+    rig[5]["range_max"] = np.float32(30.0)
+    ids = list(range(20, 28))
+    for i, s in zip(ids, rig):
+        ctx.sensor_config(i, s, 0)
+    n1 = 32 * 512
+    d, t = _cast(ctx, ids, 8 * n1)
+    for k, i in enumerate(ids):
+        d2, t2 = _cast(ctx, [i], n1, grca.GRCA_CAST_ALL_PAIRS)
+        sl = slice(k * n1, (k + 1) * n1)
+        assert np.array_equal(t[sl], t2), f"head {k}: culled != all-pairs"
+        assert np.array_equal(d[sl].view(np.uint32), d2.view(np.uint32))
+    for k in (0, 5):
+        orc = O.cast(rig[k], v, f, rays=np.arange(0, n1, 7))
+        sel = orc["rays"]
+        rep = parity.check(rig[k], v, f, orc, d[k * n1:(k + 1) * n1][sel],
+                           t[k * n1:(k + 1) * n1][sel])
+        parity.assert_parity(rep, f"colocated head {k}")
+    assert np.count_nonzero(t != grca.GRCA_MISS_TRI) > 1000
