@@ -38,18 +38,20 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 78.6
 FLOPS_PER_RTIC = 22               # ray test: 2 mul (direction) + 4 dot products x 5 flops
 # Bounds pass, counting add/sub/mul/rsq/rcp/sqrt = 1, fma = 2 (compares,
-# min/max, floor/ceil and selects not counted):
+# min/max, floor/ceil and selects not counted; work per sensor or per
+# triangle alone, such as range thresholds and radii, not counted per pair):
 # * bounding-sphere test of one (triangle, origin) pair: offset 3, local
-#   frame 15, |.|^2 5, radius 3, near 1, distance 2, range 7, angular radius
-#   7, sqrt 1, atan2 20, channel-grid indices 6, pole 1;
-# * the same test of a 64-triangle half of a tile against one origin, plus
-#   its azimuth test: 38 more;
+#   frame 15, |.|^2 5, distance 2, range 2, angular radius 6, sqrt 1,
+#   elevation atan2 19, channel-grid indices 6;
+# * the same test of a 128-triangle tile against one origin, plus its
+#   azimuth test (angular half-width 5, atan2 20, offset from the field of
+#   view's centre 7, margin 1): 92;
 # * candidate span of one pair on the common path (no range or pole test,
 #   azimuth offsets by the series bound): transform 54, |p|^2 15, sines 6,
 #   edge bulge 27, margins 2, channel bins 4, atan2 of vertex 0 20, offsets of
 #   vertices 1-2 28, full-turn test 1, azimuth margin 6, ray-index range 12.
-FLOPS_PER_SPHERE = 71
-FLOPS_PER_HALF_TEST = 109
+FLOPS_PER_SPHERE = 59
+FLOPS_PER_TILE_TEST = 92
 FLOPS_PER_SPAN = 175
 
 
@@ -317,14 +319,15 @@ def main():
                 "work": f"{FLOPS_PER_RTIC} FP32 flops x {stats['rtic']} RTIC per launch"}
     elif dom == "bounds":
         # VALU-bound: FP32 flops of the tests and spans the pass computed
-        half_tests = -(-int(sc.num_triangles) // 64) * n_sens
-        flops = (FLOPS_PER_HALF_TEST * half_tests + FLOPS_PER_SPHERE * stats["sphere_tests"] +
+        tile_tests = (-(-int(sc.num_triangles) // 128) * n_sens
+                      if opts.get("group_cull", 1) else 0)
+        flops = (FLOPS_PER_TILE_TEST * tile_tests + FLOPS_PER_SPHERE * stats["sphere_tests"] +
                  FLOPS_PER_SPAN * stats["pairs_evaluated"])
         achieved = flops / (stage_ms["bounds"] * 1e-3) / 1e12
         roof = {"kernel": "bounds_kernel", "bound": "alu", "achieved": achieved,
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                 "traffic": load_traffic("bounds_kernel"),
-                "work": f"{FLOPS_PER_HALF_TEST} FP32 flops x {half_tests} tile-half tests + "
+                "work": f"{FLOPS_PER_TILE_TEST} FP32 flops x {tile_tests} tile tests + "
                         f"{FLOPS_PER_SPHERE} x {stats['sphere_tests']} triangle sphere tests + "
                         f"{FLOPS_PER_SPAN} x {stats['pairs_evaluated']} (triangle, origin) spans "
                         f"per launch"}

@@ -92,7 +92,8 @@ const char* grca_last_error(const grca_context* ctx);
  *                rewrites positions only (num_vertices must equal the scene's).
  * Errors: INVALID_ARG for an index >= num_vertices, a non-finite coordinate
  * (host inputs are validated on the host; device inputs by a device pass
- * before the scene is replaced), num_triangles >= 2^31.  Synchronous with
+ * before the scene is replaced), num_triangles >= 2^28 or num_vertices >=
+ * 2^30 (kernels address both by 32-bit byte offsets).  Synchronous with
  * respect to `hip_stream` for host inputs. */
 grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id, const float* vertices_xyz,
                               uint32_t num_vertices, const uint32_t* indices,
@@ -228,7 +229,7 @@ typedef struct {
   uint32_t row_chunk;        /* max rays per per-channel work item (W), 1..65535       */
   uint32_t bounds_block;     /* threads per block of the bounds pass: 64..1024, x64    */
   uint32_t persist_waves_cu; /* resident waves per CU of the persistent kernels, 1..32 */
-  uint32_t group_cull;       /* 1: cull each wave's 64 triangles per sensor with one
+  uint32_t group_cull;       /* 1: cull each wave's 128 triangles per sensor with one
                                 bounding-sphere test first (the group-level cone test
                                 of section 8, "Future Work"); never changes results */
   uint32_t inline_max;       /* small-class rectangles of at most this many candidate

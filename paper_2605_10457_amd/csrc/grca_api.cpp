@@ -387,6 +387,11 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
     d.elev0 = S.elev0;
     d.inv_delev = S.inv_delev;
     d.elev_tol = S.elev_tol;
+    d.cull_dmax = d.dmax * (1.0f + 1e-5f) + 1e-6f;
+    d.in_dmax = d.dmax * (1.0f - 1e-5f);
+    d.in_dmin = d.dmin * (1.0f + 1e-5f);
+    d.elev_m = 2e-5f + d.elev_tol;
+    d.last_chan = (float)(d.gamma - 1u);
     d.az_noise = S.az_noise;
     d.cull_back = 0;
     if (flags & GRCA_CULL_BACKFACE) {
@@ -595,7 +600,9 @@ extern "C" grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id,
     const bool dev = flags & GRCA_MEM_DEVICE;
     const bool vonly = flags & GRCA_UPDATE_VERTICES_ONLY;
     if (num_vertices > 0 && !vertices_xyz) return fail(ctx, GRCA_ERR_INVALID_ARG, "vertices is NULL");
-    if (num_triangles >= (1u << 31)) return fail(ctx, GRCA_ERR_INVALID_ARG, "too many triangles");
+    // the bounds pass addresses indices and vertices by 32-bit byte offsets
+    if (num_triangles >= (1u << 28)) return fail(ctx, GRCA_ERR_INVALID_ARG, "too many triangles");
+    if (num_vertices >= (1u << 30)) return fail(ctx, GRCA_ERR_INVALID_ARG, "too many vertices");
     auto it = ctx->scenes.find(scene_id);
     if (vonly) {
       if (it == ctx->scenes.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown scene");

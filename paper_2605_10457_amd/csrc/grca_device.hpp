@@ -64,6 +64,11 @@ struct DevSensor {
   // the channel elevations as a uniform grid, for the first test of the
   // bounds pass: every channel j lies within elev_tol of elev0 + j / inv_delev
   float elev0, inv_delev, elev_tol;
+  // the sphere tests' per-sensor constants: range thresholds with their
+  // margins (cull beyond dmax (1 + 1e-5) + 1e-6; wholly inside
+  // (dmin (1 + 1e-5), dmax (1 - 1e-5))), the elevation margin 2e-5 +
+  // elev_tol and the last channel index gamma - 1
+  float cull_dmax, in_dmax, in_dmin, elev_m, last_chan;
 };
 
 // Triangles per tile of the bounds pass: one wave, two triangles per lane.

@@ -60,6 +60,16 @@ __device__ inline unsigned long long first_lane(unsigned long long v) {
 // Index of the calling wave within its block, as a wave-uniform (scalar)
 // value: everything derived from it (tile, scene, sensor loop) then stays in
 // scalar registers and scalar loads.
+// Global load at a 32-bit byte offset from a wave-uniform base: the address
+// is the scalar base plus the zero-extended offset, with no 64-bit vector
+// arithmetic.
+template <typename T>
+__device__ inline T gload(const T* base, uint32_t byte_off) {
+  typedef const T __attribute__((address_space(1))) GT;
+  typedef const char __attribute__((address_space(1))) GC;
+  return *(GT*)((GC*)base + byte_off);
+}
+
 __device__ inline uint32_t wave_id() {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 }
@@ -172,10 +182,7 @@ __device__ inline uint32_t chan_search(const DevSensor& s, float x, bool strict)
 // with P of degree 7, then the reflections of the octant.  The coefficients
 // were fitted to atan on [0, 1] by least squares reweighted toward the
 // minimax (Lawson) error; tests/test_atan_bound.py checks the bound.
-__device__ inline float atan2_bounded(float y, float x) {
-  const float ax = fabsf(x), ay = fabsf(y);
-  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
-  const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+__device__ inline float atan_unit(float t) {  // atan(t), t in [0, 1]
   const float u = t * t;
   float p = -0.00405456498f;
   p = fmaf(p, u, 0.0218629558f);
@@ -185,9 +192,26 @@ __device__ inline float atan2_bounded(float y, float x) {
   p = fmaf(p, u, 0.199465662f);
   p = fmaf(p, u, -0.333298594f);
   p = fmaf(p, u, 0.999999344f);
-  float r = p * t;
+  return p * t;
+}
+__device__ inline float atan2_bounded(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+  float r = atan_unit(t);
   if (ay > ax) r = 1.57079637f - r;
   if (x < 0.0f) r = 3.14159274f - r;
+  return y < 0.0f ? -r : r;
+}
+
+// atan2_bounded for x >= 0 (the right half-plane, e.g. an elevation from a
+// horizontal distance): the same steps without the reflection for x < 0 and
+// without the guard for x = y = 0, which gives NaN here.
+__device__ inline float atan2_right(float y, float x) {
+  const float ay = fabsf(y);
+  const float mx = fmaxf(x, ay), mn = fminf(x, ay);
+  float r = atan_unit(mn * __builtin_amdgcn_rcpf(mx));
+  if (ay > x) r = 1.57079637f - r;
   return y < 0.0f ? -r : r;
 }
 
@@ -393,7 +417,7 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
 }
 
 // Sphere culling (the "group" extension of the cone-triangle test): a group
-// of triangles, a 64-triangle half of a bounds tile or a single triangle, is bounded
+// of triangles, a 128-triangle bounds tile or a single triangle, is bounded
 // by a sphere (centre c, radius rad).  The verdict is `culled` when no ray of
 // sensor `s` can reach anything inside the sphere: it lies beyond range_max,
 // or the band of elevations it subtends holds no channel, or (AZ, on a
@@ -419,8 +443,8 @@ struct GroupVerdict {
 // widened by elev_tol (the table's largest distance from that grid); the
 // margins cover the FP32 error of c's angles and of the ray test.
 // need_range: the sphere straddles range_min or range_max; need_pole: it
-// touches the vertical axis through the origin.  Used for the halves of a
-// bounds tile (AZ) and for single triangles.
+// touches the vertical axis through the origin.  Used for bounds tiles (AZ)
+// and for single triangles.
 template <bool AZ>
 __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float rad,
                                            const DevSensor& s) {
@@ -435,17 +459,20 @@ __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float r
   const bool near = D2 <= 4.0f * r2;  // the origin is within 2r: keep
   const float invD = __builtin_amdgcn_rsqf(D2);
   const float D = D2 * invD;
-  const bool beyond = D - r > s.dmax * (1.0f + 1e-5f) + 1e-6f;
-  const bool inside = (uint32_t)(D + r < s.dmax * (1.0f - 1e-5f)) &
-                      (uint32_t)(D - r > s.dmin * (1.0f + 1e-5f));
+  const bool beyond = D - r > s.cull_dmax;
+  const bool inside = (uint32_t)(D + r < s.in_dmax) & (uint32_t)(D - r > s.in_dmin);
   const float sa = r * invD;
-  const float m = fmaf(sa * sa * (1.0f / 3.0f), sa, sa) + (2e-5f + s.elev_tol);
-  // elevation of c (h >= 0: in [-pi/2, pi/2], |error| <= 5e-7)
+  const float m = fmaf(sa * sa * (1.0f / 3.0f), sa, sa) + s.elev_m;
+  // elevation of c (in [-pi/2, pi/2], |error| <= 5e-7; NaN only at D = 0,
+  // where the sphere is near)
   const float hc = __builtin_amdgcn_sqrtf(h2);
-  const float el = atan2_bounded(lu, hc);
+  const float el = atan2_right(lu, hc);
   const float j_lo = ceilf((el - m - s.elev0) * s.inv_delev);
   const float j_hi = floorf((el + m - s.elev0) * s.inv_delev);
-  const bool band = fmaxf(j_lo, 0.0f) <= fminf(j_hi, (float)(s.gamma - 1u));
+  // some channel index j in [max(j_lo, 0), min(j_hi, gamma - 1)]; written
+  // with negated comparisons, so that a NaN keeps the sphere
+  const bool band = (uint32_t)!(j_lo > j_hi) & (uint32_t)!(j_lo > s.last_chan) &
+                    (uint32_t)!(j_hi < 0.0f);
   uint32_t out_fov = 0u;
   if (AZ) {
     const float beta = 1.0472f * r * __builtin_amdgcn_rcpf(hc) + 1e-4f + s.az_noise;
@@ -514,18 +541,17 @@ __device__ inline uint32_t item_candidates(const Item& it) {
 }
 
 // Bounds pass, one 128-triangle tile per wave: lane l holds triangles l
-// and 64 + l of the tile (its two 64-triangle halves), so that every memory
-// round trip of the wave serves two triangles.  Two phases over the sensors
-// observing the tile's scene:
-//  1. one bounding-sphere test per half (lane k tests sensor k of each run of
-//     64 sensors) skips a sensor for that half; otherwise each lane tests its
+// and 64 + l of the tile, so that every memory round trip of the wave serves
+// two triangles.  Two phases over the sensors observing the tile's scene:
+//  1. one bounding-sphere test of the whole tile (lane k tests sensor k of
+//     each run of 64 sensors) skips a sensor; otherwise each lane tests its
 //     triangles' own bounding spheres against the sensor (elevation band and
 //     range only) and the surviving (triangle, sensor) pairs are queued in
 //     the wave's LDS ring;
 //  2. whenever 64 pairs are queued, and at the end, every lane takes one
 //     pair, reads the triangle's vertices from LDS and computes the pair's
 //     candidate span, with the sensor read per lane.
-// Most pairs that pass the half's test fail their triangle's own test (small
+// Most pairs that pass the tile's test fail their triangle's own test (small
 // triangles between two channels), so the span, the costly part, runs on
 // full waves of likely survivors rather than on every lane of every sensor.
 // The records of a span batch go to the tile's item shard (small class) and
@@ -545,7 +571,9 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
     Item* __restrict__ items, uint32_t* __restrict__ item_cs, uint32_t item_scap,
     Item* __restrict__ large, uint32_t large_scap, Counters* __restrict__ cnt,
     uint32_t group_cull, uint32_t inline_max, unsigned long long* __restrict__ keys) {
-  constexpr uint32_t RING = 128;  // queued pairs: at most 63 wait when 64 arrive
+  // queued pairs: a sensor step queues at most 128 and runs only while
+  // fewer than 64 wait, so at most 191 are held
+  constexpr uint32_t RING = 256;
   // ring entry: triangle (0..127) | need_range << 7 | need_pole << 8 | sensor << 9
   __shared__ uint32_t s_ring[WPB][RING];
   __shared__ float s_vtx[WPB][9][BOUNDS_TILE];  // the tile's vertices (x0 y0 z0 x1 .. z2), by triangle
@@ -567,31 +595,33 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
   const uint32_t s_begin = first_lane(S.sensor_begin), s_end = first_lane(S.sensor_end);
   const uint32_t tri0 = first_lane((tile - S.tile_start) * BOUNDS_TILE);
   const uint32_t ntri = first_lane(S.ntri);
-  // both halves' loads are issued before any is waited for
+  // the lane's two triangles; lanes past the scene's last triangle load the
+  // tile's first one (no branch) and are masked.  Loads take the arrays'
+  // scalar bases and 32-bit byte offsets (the library keeps every scene
+  // under 2^28 triangles and 2^30 vertices).
   float v[2][9];
   bool active[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const uint32_t t = tri0 + 64u * h + lane;
     active[h] = t < ntri;
-    uint32_t i0 = 0, i1 = 0, i2 = 0;
-    if (active[h]) {
-      i0 = S.idx[3ull * t]; i1 = S.idx[3ull * t + 1]; i2 = S.idx[3ull * t + 2];
-    }
+    const uint32_t tt = active[h] ? t : tri0;
+    uint32_t id[3];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) v[h][c] = 0.0f;
-    if (active[h]) {
-      v[h][0] = S.x[i0]; v[h][1] = S.y[i0]; v[h][2] = S.z[i0];
-      v[h][3] = S.x[i1]; v[h][4] = S.y[i1]; v[h][5] = S.z[i1];
-      v[h][6] = S.x[i2]; v[h][7] = S.y[i2]; v[h][8] = S.z[i2];
+    for (int k = 0; k < 3; ++k) id[k] = gload(S.idx, (3u * tt + (uint32_t)k) * 4u);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      v[h][3 * k] = gload(S.x, id[k] * 4u);
+      v[h][3 * k + 1] = gload(S.y, id[k] * 4u);
+      v[h][3 * k + 2] = gload(S.z, id[k] * 4u);
     }
   }
   // bounding spheres (AABB centre, largest vertex distance) of the lane's
-  // triangles and of each half; the span phase reads vertices from LDS
-  float tc[2][4];                     // centre x, y, z and radius, per half
-  float gs[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // the halves' spheres (wave-uniform)
-  bool any_active[2];
-  uint32_t n_active[2];
+  // triangles and of the tile; the span phase reads vertices from LDS
+  float tc[2][4];  // centre x, y, z and radius, per triangle
+  float lo[3], hi[3];  // the lane's AABB over its active triangles
+#pragma unroll
+  for (int c = 0; c < 3; ++c) { lo[c] = 3.0e38f; hi[c] = -3.0e38f; }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     float mn[3], mx[3];
@@ -600,6 +630,7 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
       mn[c] = fminf(v[h][c], fminf(v[h][3 + c], v[h][6 + c]));
       mx[c] = fmaxf(v[h][c], fmaxf(v[h][3 + c], v[h][6 + c]));
       tc[h][c] = 0.5f * (mn[c] + mx[c]);
+      if (active[h]) { lo[c] = fminf(lo[c], mn[c]); hi[c] = fmaxf(hi[c], mx[c]); }
     }
     float r2 = 0.0f;
 #pragma unroll
@@ -611,102 +642,82 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
     // hardware square root (1 ulp; a denormal r2 may give 0): the sphere
     // tests widen every radius by 1e-4 relative and 1e-6 m
     tc[h][3] = __builtin_amdgcn_sqrtf(r2);
-    const unsigned long long am = __ballot(active[h]);
-    any_active[h] = am != 0ull;
-    n_active[h] = first_lane((uint32_t)__popcll(am));
-    if (group_cull && any_active[h]) {
-      const float big = 3.0e38f;
-      float g[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        g[c] = 0.5f * (wave_min_dpp(active[h] ? mn[c] : big) + wave_max_dpp(active[h] ? mx[c] : -big));
-      float gr2 = 0.0f;
-      if (active[h]) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const float ex = v[h][3 * k] - g[0], ey = v[h][3 * k + 1] - g[1],
-                      ez = v[h][3 * k + 2] - g[2];
-          gr2 = fmaxf(gr2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
-        }
-      }
-      // wave-uniform: kept in scalar registers
-      gs[h][0] = first_lane(g[0]);
-      gs[h][1] = first_lane(g[1]);
-      gs[h][2] = first_lane(g[2]);
-      gs[h][3] = first_lane(__builtin_amdgcn_sqrtf(wave_max_dpp(gr2)));
-    }
 #pragma unroll
     for (int c = 0; c < 9; ++c) vtx[c][64 * h + lane] = v[h][c];
   }
+  const uint32_t n_active = first_lane((uint32_t)(__popcll(__ballot(active[0])) +
+                                                  __popcll(__ballot(active[1]))));
+  // the tile's sphere (wave-uniform: scalar registers).  One sphere for both
+  // halves: the halves' own spheres would skip 1-2% fewer sensor steps for
+  // twice the reductions.
+  float gs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (group_cull) {
+    float g[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[c] = 0.5f * (wave_min_dpp(lo[c]) + wave_max_dpp(hi[c]));
+    float gr2 = 0.0f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float ex = v[h][3 * k] - g[0], ey = v[h][3 * k + 1] - g[1],
+                    ez = v[h][3 * k + 2] - g[2];
+        const float d2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+        if (active[h]) gr2 = fmaxf(gr2, d2);
+      }
+    }
+    gs[0] = first_lane(g[0]);
+    gs[1] = first_lane(g[1]);
+    gs[2] = first_lane(g[2]);
+    gs[3] = first_lane(__builtin_amdgcn_sqrtf(wave_max_dpp(gr2)));
+  }
   unsigned long long rtic = 0ull;  // candidates tested inline by this lane
-  unsigned long long g_cull[2] = {0ull, 0ull}, g_range[2] = {~0ull, ~0ull},
-                     g_pole[2] = {~0ull, ~0ull};
+  unsigned long long g_cull = 0ull, g_range = ~0ull, g_pole = ~0ull;
   uint32_t tested = 0;     // triangle sphere tests of this wave (wave-uniform statistic)
   uint32_t evaluated = 0;  // spans computed by this wave (wave-uniform statistic)
   uint32_t head = 0, tail = 0;  // pairs taken from / queued into the ring
-  // Phase 1 runs in steps (sensor n, half h); the step of half 0 tests both
-  // halves (their table loads in flight together) and keeps half 1's verdict
-  // for the next step, so that a step queues at most 64 pairs.
-  uint32_t n = s_begin, h = 0;
-  bool keep1 = false;
-  uint32_t flags1 = 0;
+  uint32_t n = s_begin;
   for (;;) {
-    if (n < s_end) {
-      // ---- phase 1
-      const uint32_t ln = (n - s_begin) & 31u;
-      if (h == 0) {
-        if (ln == 0) {
-          // both halves' verdicts for the next 32 sensors in one pass: lane k
-          // tests half k / 32 against sensor n + k % 32
-          const uint32_t q = lane >> 5, ns = n + (lane & 31u);
-          const bool any = q ? any_active[1] : any_active[0];
-          bool cul = !any, nr = true, np = true;
-          if (group_cull && any && ns < s_end) {
-            const float cx = q ? gs[1][0] : gs[0][0], cy = q ? gs[1][1] : gs[0][1];
-            const float cz = q ? gs[1][2] : gs[0][2], cr = q ? gs[1][3] : gs[0][3];
-            const GroupVerdict gv = sphere_test<true>(cx, cy, cz, cr, sens[ns]);
-            cul = gv.culled;
-            nr = gv.need_range;
-            np = gv.need_pole;
-          }
-          const unsigned long long bc = first_lane(__ballot(cul));
-          const unsigned long long br = first_lane(__ballot(nr));
-          const unsigned long long bp = first_lane(__ballot(np));
-          g_cull[0] = bc & 0xFFFFFFFFull; g_cull[1] = bc >> 32;
-          g_range[0] = br & 0xFFFFFFFFull; g_range[1] = br >> 32;
-          g_pole[0] = bp & 0xFFFFFFFFull; g_pole[1] = bp >> 32;
+    if (n < s_end && tail - head < 64u) {
+      // ---- phase 1: sensor n
+      const uint32_t ln = (n - s_begin) & 63u;
+      if (ln == 0) {
+        // the tile's verdicts for the next 64 sensors in one pass: lane k
+        // tests sensor n + k
+        const uint32_t ns = n + lane;
+        bool cul = false, nr = true, np = true;
+        if (group_cull && ns < s_end) {
+          const GroupVerdict gv = sphere_test<true>(gs[0], gs[1], gs[2], gs[3], sens[ns]);
+          cul = gv.culled;
+          nr = gv.need_range;
+          np = gv.need_pole;
         }
-        const bool t0 = !((g_cull[0] >> ln) & 1ull), t1 = !((g_cull[1] >> ln) & 1ull);
-        if (t0 || t1) {  // wave-uniform
-          // every lane runs both tests (no branch: the sensor's fields are read once)
-          const DevSensor& s = sens[n];
-          const GroupVerdict v0 = sphere_test<false>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s);
-          const GroupVerdict v1 = sphere_test<false>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s);
-          tested += (t0 ? n_active[0] : 0u) + (t1 ? n_active[1] : 0u);
-          const bool keep0 = t0 && active[0] && !v0.culled;
-          keep1 = t1 && active[1] && !v1.culled;
-          const uint32_t flags0 = (uint32_t)(v0.need_range && ((g_range[0] >> ln) & 1ull)) |
-                                  ((uint32_t)(v0.need_pole && ((g_pole[0] >> ln) & 1ull)) << 1);
-          flags1 = (uint32_t)(v1.need_range && ((g_range[1] >> ln) & 1ull)) |
-                   ((uint32_t)(v1.need_pole && ((g_pole[1] >> ln) & 1ull)) << 1);
-          const unsigned long long m = __ballot(keep0);
-          if (keep0)
-            ring[(tail + (uint32_t)__popcll(m & __lanemask_lt())) % RING] =
-                lane | (flags0 << 7) | (n << 9);
-          tail = first_lane(tail + (uint32_t)__popcll(m));
-        } else {
-          keep1 = false;
-        }
-        h = 1;
-      } else {
-        const unsigned long long m = __ballot(keep1);
-        if (keep1)
-          ring[(tail + (uint32_t)__popcll(m & __lanemask_lt())) % RING] =
-              (64u + lane) | (flags1 << 7) | (n << 9);
-        tail = first_lane(tail + (uint32_t)__popcll(m));
-        h = 0;
-        ++n;
+        g_cull = first_lane(__ballot(cul));
+        g_range = first_lane(__ballot(nr));
+        g_pole = first_lane(__ballot(np));
       }
+      if (!((g_cull >> ln) & 1ull)) {  // wave-uniform
+        // both triangles of every lane (no branch: the sensor's fields are read once)
+        const DevSensor& s = sens[n];
+        const GroupVerdict v0 = sphere_test<false>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s);
+        const GroupVerdict v1 = sphere_test<false>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s);
+        tested += n_active;
+        const bool gr = (g_range >> ln) & 1ull, gp = (g_pole >> ln) & 1ull;
+        const bool keep0 = active[0] && !v0.culled;
+        const bool keep1 = active[1] && !v1.culled;
+        const uint32_t tag = n << 9;
+        const uint32_t e0 = lane | ((uint32_t)(v0.need_range && gr) << 7) |
+                            ((uint32_t)(v0.need_pole && gp) << 8) | tag;
+        const uint32_t e1 = (64u + lane) | ((uint32_t)(v1.need_range && gr) << 7) |
+                            ((uint32_t)(v1.need_pole && gp) << 8) | tag;
+        const unsigned long long m0 = __ballot(keep0), m1 = __ballot(keep1);
+        const unsigned long long lt = __lanemask_lt();
+        const uint32_t c0 = (uint32_t)__popcll(m0);
+        if (keep0) ring[(tail + (uint32_t)__popcll(m0 & lt)) % RING] = e0;
+        if (keep1) ring[(tail + c0 + (uint32_t)__popcll(m1 & lt)) % RING] = e1;
+        tail = first_lane(tail + c0 + (uint32_t)__popcll(m1));
+      }
+      ++n;
     }
     const bool drain = n >= s_end;
     const uint32_t avail = tail - head;

@@ -1,4 +1,4 @@
-"""CPU check of the bounds pass's FP32 atan2 (``atan2_bounded`` in
+"""CPU check of the bounds pass's FP32 atan2 (``atan2_bounded`` and ``atan_unit`` in
 grca_kernels.hip): its error bound of 5e-7 rad feeds the azimuth margin of the
 conservative candidate spans (section 3.3's angular bounding of a triangle).
 
@@ -15,13 +15,17 @@ SRC = os.path.join(ROOT, "paper_2605_10457_amd", "csrc", "grca_kernels.hip")
 BOUND = 5e-7
 
 
-def _coefficients():
+def _body(name):
     txt = open(SRC).read()
-    body = txt[txt.index("__device__ inline float atan2_bounded("):]
-    body = body[:body.index("\n}\n")]
-    first = re.search(r"float p = (-?[0-9.e-]+)f;", body).group(1)
-    rest = re.findall(r"p = fmaf\(p, u, (-?[0-9.e-]+)f\);", body)
-    consts = re.findall(r"r = (\d\.\d+)f - r;", body)
+    body = txt[txt.index("__device__ inline float %s(" % name):]
+    return body[:body.index("\n}\n")]
+
+
+def _coefficients():
+    poly = _body("atan_unit")
+    first = re.search(r"float p = (-?[0-9.e-]+)f;", poly).group(1)
+    rest = re.findall(r"p = fmaf\(p, u, (-?[0-9.e-]+)f\);", poly)
+    consts = re.findall(r"r = (\d\.\d+)f - r;", _body("atan2_bounded"))
     return [np.float32(first)] + [np.float32(c) for c in rest], [np.float32(c) for c in consts]
 
 
@@ -70,3 +74,15 @@ def test_atan2_error_bound():
         err = np.abs(got - ref)
         err = np.minimum(err, 2 * np.pi - err)  # +-pi are the same direction
         assert err.max() <= BOUND, (ulps, err.max())
+
+
+def test_right_half_plane_variant():
+    # atan2_right (elevations: x >= 0) takes atan2_bounded's steps minus the
+    # x < 0 reflection, so the bound above covers it; check that the source
+    # still says so: the shared polynomial, the same quarter-turn constant,
+    # no other reflection
+    body = _body("atan2_right")
+    quarter = re.findall(r"r = (\d\.\d+)f - r;", _body("atan2_bounded"))[0]
+    assert "atan_unit(" in body and "__builtin_amdgcn_rcpf(mx)" in body
+    assert re.findall(r"r = (\d\.\d+)f - r;", body) == [quarter]
+    assert "x < 0.0f" not in body
