@@ -70,6 +70,11 @@ __device__ inline T gload(const T* base, uint32_t byte_off) {
   return *(GT*)((GC*)base + byte_off);
 }
 
+__device__ inline float2 gload_f2(const float2* base, uint32_t byte_off) {
+  const unsigned long long v = gload(reinterpret_cast<const unsigned long long*>(base), byte_off);
+  return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
+}
+
 __device__ inline uint32_t wave_id() {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 }
@@ -1141,6 +1146,72 @@ struct CandSensor {
   float dmin, dmax;
 };
 
+// One candidate of the flattened loop, from its owner item (staged in LDS)
+// and batch position f: the statics, the ray's table entries and the ray's
+// key as this wave can see it, all reads issued together.
+struct Cand {
+  Statics st;
+  float2 cp, ca;
+  unsigned long long seen;  // never below the true minimum: keys only decrease
+  uint32_t kidx, tri;
+  float dmin, dmax;
+  bool on;  // the ray is active (mask)
+};
+// LDS_SENS: every sensor slot of the cast is below 64 and read from the
+// block's LDS copy; otherwise from the device descriptors.  (One source per
+// instance: a per-lane choice between the two would turn every read into a
+// flat access, which also waits behind the LDS counter.)
+template <bool LDS_SENS>
+__device__ inline Cand cand_read(int own, uint32_t f, const float4 (*st_w)[64],
+                                 const ItemInfo* in_w, const IsectSensor* sen,
+                                 const DevSensor* sens, const unsigned long long* keys,
+                                 bool any_mask) {
+  const ItemInfo inf = in_w[own];
+  const uint32_t sid = inf.rs >> 16;
+  CandSensor sn;
+  if (LDS_SENS) {
+    const IsectSensor& q = sen[sid];
+    sn = CandSensor{q.chan, q.az, q.mask, q.chi, q.key_offset, q.dmin, q.dmax};
+  } else {
+    const DevSensor& q = sens[sid];
+    sn = CandSensor{q.chan, q.az, q.mask, q.chi, q.key_offset, q.dmin, q.dmax};
+  }
+  // batch position -> (channel, ray) of the item's rectangle
+  const uint32_t r_count = inf.rs & 0xFFFFu;
+  const uint32_t local = (uint32_t)((int32_t)f + inf.bias);
+  uint32_t c = 0;
+  if (local >= r_count) {
+    c = (uint32_t)((float)local * inf.inv_rc);
+    if (c * r_count > local) --c;
+    else if ((c + 1) * r_count <= local) ++c;
+  }
+  const uint32_t r = local - c * r_count;
+  const uint32_t ch = (inf.cr & 0xFFFFu) + c;
+  uint32_t ray = (inf.cr >> 16) + r;
+  if (ray >= sn.chi) ray -= sn.chi;
+  const uint32_t gl = ch * sn.chi + ray;
+  Cand o;
+  o.on = true;
+  if (any_mask) o.on = !sn.mask || gload(sn.mask, gl);
+  o.cp = gload_f2(sn.chan, ch * 8u);
+  o.ca = gload_f2(sn.az, ray * 8u);
+  o.kidx = sn.key_offset + gl;
+  o.seen = keys[o.kidx];
+  const float4 a0 = st_w[0][own], a1 = st_w[1][own], a2 = st_w[2][own];
+  o.st = Statics{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
+                 a2.x, a2.y, a2.z, a2.w, inf.h, 0.0f, 0.0f, 0.0f};
+  o.tri = inf.tri;
+  o.dmin = sn.dmin;
+  o.dmax = sn.dmax;
+  return o;
+}
+// The ray test, and the atomic for a hit that can improve on the key read.
+__device__ inline void cand_finish(const Cand& o, unsigned long long* keys) {
+  const unsigned long long key =
+      ray_test(o.st, o.cp.x, o.cp.y, o.ca.x, o.ca.y, o.dmin, o.dmax, o.tri);
+  if (o.on && key < o.seen) key_min(keys, o.kidx, key);
+}
+
 // Inclusive prefix maximum over the wave (identity -1) with DPP row shifts
 // and row broadcasts: no LDS round trips.
 __device__ inline int wave_incl_max(int v) {
@@ -1178,7 +1249,7 @@ __device__ inline uint32_t find_owner(const uint32_t* __restrict__ cs, uint32_t 
 // FLATTENED list of their candidates, 64 pairs per step.  Every ticket costs
 // the same whatever the sizes of the items in it.  Invalid pairs (degenerate,
 // or back-facing under single-sided casting) contribute no candidates.
-template <int WPB>
+template <int WPB, bool LDS_SENS>
 __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     const DevScene* __restrict__ scenes, const DevSensor* __restrict__ sens,
     uint32_t nsens, const Item* __restrict__ items, const uint32_t* __restrict__ item_cs,
@@ -1186,13 +1257,15 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     unsigned long long* __restrict__ keys) {
   __shared__ float4 st_s[WPB][3][64];  // the staged items' normals n0, n1, n2, N
   __shared__ ItemInfo in_s[WPB][64];
-  __shared__ int mark_s[WPB][64];
+  __shared__ int mark_s[WPB][128];
   __shared__ IsectSensor sen_s[64];
   const uint32_t w = wave_id();
   const uint32_t lane = lane_id();
-  if (threadIdx.x < min(nsens, 64u))
-    sen_s[threadIdx.x] = isect_sensor(scenes, sens[threadIdx.x]);
-  __syncthreads();
+  if (LDS_SENS && threadIdx.x < nsens) sen_s[threadIdx.x] = isect_sensor(scenes, sens[threadIdx.x]);
+  // whether any sensor of the cast has an active-ray mask (block-uniform)
+  bool has_mask = false;
+  for (uint32_t k = threadIdx.x; k < nsens; k += blockDim.x) has_mask |= sens[k].mask != nullptr;
+  const bool any_mask = __syncthreads_or(has_mask) != 0;
   const ShardWalk sw = shard_walk(WPB);
   unsigned long long rtic = 0ull;  // wave-uniform
   for (uint32_t sh = sw.first; sh < NSHARD; sh += sw.step) {
@@ -1227,20 +1300,24 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
           const uint32_t hi = (uint32_t)min<uint64_t>(e, (uint64_t)b);
           if (hi > lo) {
             // the pair's statics, built here in FP64 from the gathered triangle
-            const IsectSensor sq = it.sensor < 64u ? sen_s[it.sensor]
-                                                   : isect_sensor(scenes, sens[it.sensor]);
+            const IsectSensor sq = LDS_SENS ? sen_s[it.sensor]
+                                            : isect_sensor(scenes, sens[it.sensor]);
+            // (global loads at 32-bit byte offsets: the pointers come from
+            // LDS, and flat accesses would also wait behind the LDS counter)
             const uint32_t t = it.tri;
-            const uint32_t v0 = sq.idx[3ull * t], v1 = sq.idx[3ull * t + 1],
-                           v2 = sq.idx[3ull * t + 2];
+            const uint32_t v0 = gload(sq.idx, 12u * t), v1 = gload(sq.idx, 12u * t + 4u),
+                           v2 = gload(sq.idx, 12u * t + 8u);
             Statics st;
-            if (make_statics(sq.x[v0], sq.y[v0], sq.z[v0], sq.x[v1], sq.y[v1], sq.z[v1],
-                             sq.x[v2], sq.y[v2], sq.z[v2], sq, st)) {
+            if (make_statics(gload(sq.x, 4u * v0), gload(sq.y, 4u * v0), gload(sq.z, 4u * v0),
+                             gload(sq.x, 4u * v1), gload(sq.y, 4u * v1), gload(sq.z, 4u * v1),
+                             gload(sq.x, 4u * v2), gload(sq.y, 4u * v2), gload(sq.z, 4u * v2),
+                             sq, st)) {
               count = hi - lo;
               st_s[w][0][lane] = make_float4(st.n0x, st.n0y, st.n0z, st.n1x);
               st_s[w][1][lane] = make_float4(st.n1y, st.n1z, st.n2x, st.n2y);
               st_s[w][2][lane] = make_float4(st.n2z, st.Nx, st.Ny, st.Nz);
               ItemInfo inf;
-              inf.tri = sq.orig[it.tri];  // keys carry the caller's triangle id
+              inf.tri = gload(sq.orig, 4u * it.tri);  // keys carry the caller's triangle id
               inf.cr = (it.chan & 0xFFFFu) | (it.rays << 16);
               inf.rs = rc | (it.sensor << 16);
               inf.bias = 0;
@@ -1258,62 +1335,33 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
         const uint32_t total = last_lane(incl);
         rtic += total;
         // Owner of batch position p: the last item with a candidate whose first
-        // position is <= p.  Per window of 64 positions, each item starting in
+        // position is <= p.  Per window of 128 positions, each item starting in
         // the window marks its slot, and a prefix maximum spreads the marks;
         // positions before the first mark keep the previous window's owner.
-        int carry = -1, cur = -1;
-        Statics st;
-        ItemInfo inf;
-        CandSensor sn;
-        for (uint32_t base = 0; base < total; base += 64) {
+        // Each lane takes two positions of the window, p and p + 64: both
+        // candidates' table and key reads are in flight together.
+        int carry = -1;
+        for (uint32_t base = 0; base < total; base += 128u) {
           mark_s[w][lane] = -1;
+          mark_s[w][64 + lane] = -1;
           wave_sync();
-          if (count && excl >= base && excl - base < 64u) mark_s[w][excl - base] = (int)lane;
+          if (count && excl >= base && excl - base < 128u) mark_s[w][excl - base] = (int)lane;
           wave_sync();
-          const int own = max(wave_incl_max(mark_s[w][lane]), carry);
-          carry = __builtin_amdgcn_readlane(own, 63);
+          const int own_a = max(wave_incl_max(mark_s[w][lane]), carry);
+          const int own_b =
+              max(wave_incl_max(mark_s[w][64 + lane]), __builtin_amdgcn_readlane(own_a, 63));
+          carry = __builtin_amdgcn_readlane(own_b, 63);
           wave_sync();
-          const uint32_t f = base + lane;
-          if (f >= total) continue;
-          if (own != cur) {
-            cur = own;
-            const float4 a0 = st_s[w][0][own], a1 = st_s[w][1][own], a2 = st_s[w][2][own];
-            inf = in_s[w][own];
-            st = Statics{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
-                         a2.x, a2.y, a2.z, a2.w, inf.h, 0.0f, 0.0f, 0.0f};
-            const uint32_t sid = inf.rs >> 16;
-            if (sid < 64u) {
-              const IsectSensor& q2 = sen_s[sid];
-              sn = CandSensor{q2.chan, q2.az, q2.mask, q2.chi, q2.key_offset, q2.dmin, q2.dmax};
-            } else {
-              const DevSensor& s2 = sens[sid];
-              sn = CandSensor{s2.chan, s2.az, s2.mask, s2.chi, s2.key_offset, s2.dmin, s2.dmax};
-            }
-          }
-          const uint32_t r_count = inf.rs & 0xFFFFu;
-          const uint32_t local = (uint32_t)((int32_t)f + inf.bias);
-          uint32_t c = 0;
-          if (local >= r_count) {
-            c = (uint32_t)((float)local * inf.inv_rc);
-            if (c * r_count > local) --c;
-            else if ((c + 1) * r_count <= local) ++c;
-          }
-          const uint32_t r = local - c * r_count;
-          const uint32_t ch = (inf.cr & 0xFFFFu) + c;
-          uint32_t ray = (inf.cr >> 16) + r;
-          if (ray >= sn.chi) ray -= sn.chi;
-          const uint32_t gl = ch * sn.chi + ray;
-          if (sn.mask && !sn.mask[gl]) continue;
-          const float2 cp = sn.chan[ch];
-          const float2 ca = sn.az[ray];
-          // the ray's key as this wave can see it (never below the true
-          // minimum: keys only decrease), read with the table entries; a hit
-          // that cannot improve on it issues no atomic
-          const uint32_t kidx = sn.key_offset + gl;
-          const unsigned long long seen = keys[kidx];
-          const unsigned long long key = ray_test(st, cp.x, cp.y, ca.x, ca.y, sn.dmin, sn.dmax,
-                                                  inf.tri);
-          if (key < seen) key_min(keys, kidx, key);
+          const uint32_t fa = base + lane, fb = fa + 64u;
+          if (fa >= total) continue;  // fb >= total too
+          const bool has_b = fb < total;
+          const Cand ca =
+              cand_read<LDS_SENS>(own_a, fa, st_s[w], in_s[w], sen_s, sens, keys, any_mask);
+          Cand cb;
+          if (has_b)
+            cb = cand_read<LDS_SENS>(own_b, fb, st_s[w], in_s[w], sen_s, sens, keys, any_mask);
+          cand_finish(ca, keys);
+          if (has_b) cand_finish(cb, keys);
         }
         wave_sync();
         if (last) break;
@@ -1561,8 +1609,12 @@ hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, uint32_t 
                         const Item* items, const uint32_t* item_cs, uint32_t item_scap,
                         uint32_t ticket_cands, Counters* cnt, unsigned long long* keys,
                         uint32_t nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(isect_kernel<4>, dim3(nblocks), dim3(256), 0, st, scenes, sens, nsens, items,
-                     item_cs, item_scap, ticket_cands, cnt, keys);
+  if (nsens <= 64)
+    hipLaunchKernelGGL((isect_kernel<4, true>), dim3(nblocks), dim3(256), 0, st, scenes, sens,
+                       nsens, items, item_cs, item_scap, ticket_cands, cnt, keys);
+  else
+    hipLaunchKernelGGL((isect_kernel<4, false>), dim3(nblocks), dim3(256), 0, st, scenes, sens,
+                       nsens, items, item_cs, item_scap, ticket_cands, cnt, keys);
   return hipGetLastError();
 }
 
