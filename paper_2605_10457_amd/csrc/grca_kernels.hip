@@ -1147,14 +1147,14 @@ struct CandSensor {
 };
 
 // One candidate of the flattened loop, from its owner item (staged in LDS)
-// and batch position f: the statics, the ray's table entries and the ray's
-// key as this wave can see it, all reads issued together.
+// and batch position f: the ray's table entries and the ray's key as this
+// wave can see it (never below the true minimum: keys only decrease), all
+// reads issued together.  The owner's statics are read from LDS when the
+// candidate is tested, so that a lane can keep several candidates in flight.
 struct Cand {
-  Statics st;
   float2 cp, ca;
-  unsigned long long seen;  // never below the true minimum: keys only decrease
-  uint32_t kidx, tri;
-  float dmin, dmax;
+  unsigned long long seen;
+  uint32_t kidx;
   bool on;  // the ray is active (mask)
 };
 // LDS_SENS: every sensor slot of the cast is below 64 and read from the
@@ -1162,20 +1162,21 @@ struct Cand {
 // instance: a per-lane choice between the two would turn every read into a
 // flat access, which also waits behind the LDS counter.)
 template <bool LDS_SENS>
-__device__ inline Cand cand_read(int own, uint32_t f, const float4 (*st_w)[64],
-                                 const ItemInfo* in_w, const IsectSensor* sen,
-                                 const DevSensor* sens, const unsigned long long* keys,
-                                 bool any_mask) {
-  const ItemInfo inf = in_w[own];
-  const uint32_t sid = inf.rs >> 16;
-  CandSensor sn;
+__device__ inline CandSensor cand_sensor(uint32_t sid, const IsectSensor* sen,
+                                         const DevSensor* sens) {
   if (LDS_SENS) {
     const IsectSensor& q = sen[sid];
-    sn = CandSensor{q.chan, q.az, q.mask, q.chi, q.key_offset, q.dmin, q.dmax};
-  } else {
-    const DevSensor& q = sens[sid];
-    sn = CandSensor{q.chan, q.az, q.mask, q.chi, q.key_offset, q.dmin, q.dmax};
+    return CandSensor{q.chan, q.az, q.mask, q.chi, q.key_offset, q.dmin, q.dmax};
   }
+  const DevSensor& q = sens[sid];
+  return CandSensor{q.chan, q.az, q.mask, q.chi, q.key_offset, q.dmin, q.dmax};
+}
+template <bool LDS_SENS>
+__device__ inline Cand cand_read(int own, uint32_t f, const ItemInfo* in_w,
+                                 const IsectSensor* sen, const DevSensor* sens,
+                                 const unsigned long long* keys, bool any_mask) {
+  const ItemInfo inf = in_w[own];
+  const CandSensor sn = cand_sensor<LDS_SENS>(inf.rs >> 16, sen, sens);
   // batch position -> (channel, ray) of the item's rectangle
   const uint32_t r_count = inf.rs & 0xFFFFu;
   const uint32_t local = (uint32_t)((int32_t)f + inf.bias);
@@ -1197,18 +1198,22 @@ __device__ inline Cand cand_read(int own, uint32_t f, const float4 (*st_w)[64],
   o.ca = gload_f2(sn.az, ray * 8u);
   o.kidx = sn.key_offset + gl;
   o.seen = keys[o.kidx];
-  const float4 a0 = st_w[0][own], a1 = st_w[1][own], a2 = st_w[2][own];
-  o.st = Statics{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
-                 a2.x, a2.y, a2.z, a2.w, inf.h, 0.0f, 0.0f, 0.0f};
-  o.tri = inf.tri;
-  o.dmin = sn.dmin;
-  o.dmax = sn.dmax;
   return o;
 }
-// The ray test, and the atomic for a hit that can improve on the key read.
-__device__ inline void cand_finish(const Cand& o, unsigned long long* keys) {
-  const unsigned long long key =
-      ray_test(o.st, o.cp.x, o.cp.y, o.ca.x, o.ca.y, o.dmin, o.dmax, o.tri);
+// The ray test against the owner's statics, and the atomic for a hit that
+// can improve on the key read.
+template <bool LDS_SENS>
+__device__ inline void cand_finish(const Cand& o, int own, const float4 (*st_w)[64],
+                                   const ItemInfo* in_w, const IsectSensor* sen,
+                                   const DevSensor* sens, unsigned long long* keys) {
+  const ItemInfo& inf = in_w[own];
+  const float4 a0 = st_w[0][own], a1 = st_w[1][own], a2 = st_w[2][own];
+  const Statics st{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
+                   a2.x, a2.y, a2.z, a2.w, inf.h, 0.0f, 0.0f, 0.0f};
+  const uint32_t sid = inf.rs >> 16;
+  const float dmin = LDS_SENS ? sen[sid].dmin : sens[sid].dmin;
+  const float dmax = LDS_SENS ? sen[sid].dmax : sens[sid].dmax;
+  const unsigned long long key = ray_test(st, o.cp.x, o.cp.y, o.ca.x, o.ca.y, dmin, dmax, inf.tri);
   if (o.on && key < o.seen) key_min(keys, o.kidx, key);
 }
 
@@ -1249,6 +1254,10 @@ __device__ inline uint32_t find_owner(const uint32_t* __restrict__ cs, uint32_t 
 // FLATTENED list of their candidates, 64 pairs per step.  Every ticket costs
 // the same whatever the sizes of the items in it.  Invalid pairs (degenerate,
 // or back-facing under single-sided casting) contribute no candidates.
+// Candidates per lane per window of the intersection's flattened loop: 4
+// keeps it at 114 VGPRs (4 waves per SIMD) and measured 0.259 ms against
+// 0.263 ms for 2 and 0.282 ms for 6 (3 waves per SIMD) on the ring workload.
+constexpr int ISECT_SLOTS = 4;
 template <int WPB, bool LDS_SENS>
 __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     const DevScene* __restrict__ scenes, const DevSensor* __restrict__ sens,
@@ -1257,7 +1266,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     unsigned long long* __restrict__ keys) {
   __shared__ float4 st_s[WPB][3][64];  // the staged items' normals n0, n1, n2, N
   __shared__ ItemInfo in_s[WPB][64];
-  __shared__ int mark_s[WPB][128];
+  __shared__ int mark_s[WPB][64 * ISECT_SLOTS];
   __shared__ IsectSensor sen_s[64];
   const uint32_t w = wave_id();
   const uint32_t lane = lane_id();
@@ -1335,33 +1344,37 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
         const uint32_t total = last_lane(incl);
         rtic += total;
         // Owner of batch position p: the last item with a candidate whose first
-        // position is <= p.  Per window of 128 positions, each item starting in
-        // the window marks its slot, and a prefix maximum spreads the marks;
-        // positions before the first mark keep the previous window's owner.
-        // Each lane takes two positions of the window, p and p + 64: both
-        // candidates' table and key reads are in flight together.
+        // position is <= p.  Per window of 64 x ISECT_SLOTS positions, each
+        // item starting in the window marks its slot, and a prefix maximum
+        // spreads the marks; positions before the first mark keep the
+        // previous window's owner.  Each lane takes the positions p + 64 j:
+        // all its candidates' table and key reads are in flight together.
+        constexpr uint32_t WIN = 64u * ISECT_SLOTS;
         int carry = -1;
-        for (uint32_t base = 0; base < total; base += 128u) {
-          mark_s[w][lane] = -1;
-          mark_s[w][64 + lane] = -1;
+        for (uint32_t base = 0; base < total; base += WIN) {
+#pragma unroll
+          for (int j = 0; j < ISECT_SLOTS; ++j) mark_s[w][64 * j + lane] = -1;
           wave_sync();
-          if (count && excl >= base && excl - base < 128u) mark_s[w][excl - base] = (int)lane;
+          if (count && excl >= base && excl - base < WIN) mark_s[w][excl - base] = (int)lane;
           wave_sync();
-          const int own_a = max(wave_incl_max(mark_s[w][lane]), carry);
-          const int own_b =
-              max(wave_incl_max(mark_s[w][64 + lane]), __builtin_amdgcn_readlane(own_a, 63));
-          carry = __builtin_amdgcn_readlane(own_b, 63);
+          int own[ISECT_SLOTS];
+#pragma unroll
+          for (int j = 0; j < ISECT_SLOTS; ++j) {
+            own[j] = max(wave_incl_max(mark_s[w][64 * j + lane]), carry);
+            carry = __builtin_amdgcn_readlane(own[j], 63);
+          }
           wave_sync();
-          const uint32_t fa = base + lane, fb = fa + 64u;
-          if (fa >= total) continue;  // fb >= total too
-          const bool has_b = fb < total;
-          const Cand ca =
-              cand_read<LDS_SENS>(own_a, fa, st_s[w], in_s[w], sen_s, sens, keys, any_mask);
-          Cand cb;
-          if (has_b)
-            cb = cand_read<LDS_SENS>(own_b, fb, st_s[w], in_s[w], sen_s, sens, keys, any_mask);
-          cand_finish(ca, keys);
-          if (has_b) cand_finish(cb, keys);
+          if (base + lane >= total) continue;  // and every later position
+          Cand c[ISECT_SLOTS];
+#pragma unroll
+          for (int j = 0; j < ISECT_SLOTS; ++j)
+            if (j == 0 || base + 64u * j + lane < total)
+              c[j] = cand_read<LDS_SENS>(own[j], base + 64u * j + lane, in_s[w], sen_s, sens, keys,
+                                         any_mask);
+#pragma unroll
+          for (int j = 0; j < ISECT_SLOTS; ++j)
+            if (j == 0 || base + 64u * j + lane < total)
+              cand_finish<LDS_SENS>(c[j], own[j], st_s[w], in_s[w], sen_s, sens, keys);
         }
         wave_sync();
         if (last) break;
