@@ -392,6 +392,7 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
     d.in_dmin = d.dmin * (1.0f + 1e-5f);
     d.elev_m = 2e-5f + d.elev_tol;
     d.last_chan = (float)(d.gamma - 1u);
+    d.elev0_g = d.elev0 * d.inv_delev;
     d.az_noise = S.az_noise;
     d.cull_back = 0;
     if (flags & GRCA_CULL_BACKFACE) {

@@ -67,8 +67,8 @@ struct DevSensor {
   // the sphere tests' per-sensor constants: range thresholds with their
   // margins (cull beyond dmax (1 + 1e-5) + 1e-6; wholly inside
   // (dmin (1 + 1e-5), dmax (1 - 1e-5))), the elevation margin 2e-5 +
-  // elev_tol and the last channel index gamma - 1
-  float cull_dmax, in_dmax, in_dmin, elev_m, last_chan;
+  // elev_tol, the last channel index gamma - 1 and elev0 * inv_delev
+  float cull_dmax, in_dmax, in_dmin, elev_m, last_chan, elev0_g;
 };
 
 // Triangles per tile of the bounds pass: one wave, two triangles per lane.

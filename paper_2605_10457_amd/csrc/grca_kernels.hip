@@ -75,6 +75,12 @@ __device__ inline float2 gload_f2(const float2* base, uint32_t byte_off) {
   return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
 }
 
+// Number of lanes below this one whose bit is set in mask m (v_mbcnt).
+__device__ inline uint32_t rank_in(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ inline uint32_t wave_id() {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 }
@@ -117,7 +123,7 @@ __device__ inline void wave_push(bool want, const Item& rec, Item* q, uint32_t c
   }
   base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
   if (want) {
-    const uint32_t rank = (uint32_t)__popcll(mask & __lanemask_lt());
+    const uint32_t rank = rank_in(mask);
     const uint32_t slot = base + rank;
     if (slot < cap) {
       q[slot] = rec;
@@ -472,8 +478,12 @@ __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float r
   // where the sphere is near)
   const float hc = __builtin_amdgcn_sqrtf(h2);
   const float el = atan2_right(lu, hc);
-  const float j_lo = ceilf((el - m - s.elev0) * s.inv_delev);
-  const float j_hi = floorf((el + m - s.elev0) * s.inv_delev);
+  // grid coordinates of el -+ m: (el - elev0) / delev -+ m / delev (the
+  // roundings are a few ulps of a channel index, far inside the margin)
+  const float eg = fmaf(el, s.inv_delev, -s.elev0_g);
+  const float mg = m * s.inv_delev;
+  const float j_lo = ceilf(eg - mg);
+  const float j_hi = floorf(eg + mg);
   // some channel index j in [max(j_lo, 0), min(j_hi, gamma - 1)]; written
   // with negated comparisons, so that a NaN keeps the sphere
   const bool band = (uint32_t)!(j_lo > j_hi) & (uint32_t)!(j_lo > s.last_chan) &
@@ -716,19 +726,19 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
         const uint32_t e1 = (64u + lane) | ((uint32_t)(v1.need_range && gr) << 7) |
                             ((uint32_t)(v1.need_pole && gp) << 8) | tag;
         const unsigned long long m0 = __ballot(keep0), m1 = __ballot(keep1);
-        const unsigned long long lt = __lanemask_lt();
         const uint32_t c0 = (uint32_t)__popcll(m0);
-        if (keep0) ring[(tail + (uint32_t)__popcll(m0 & lt)) % RING] = e0;
-        if (keep1) ring[(tail + c0 + (uint32_t)__popcll(m1 & lt)) % RING] = e1;
+        if (keep0) ring[(tail + rank_in(m0)) % RING] = e0;
+        if (keep1) ring[(tail + c0 + rank_in(m1)) % RING] = e1;
         tail = first_lane(tail + c0 + (uint32_t)__popcll(m1));
       }
       ++n;
     }
-    const bool drain = n >= s_end;
+    // a batch runs when 64 pairs wait, or, once every sensor is tested, on
+    // whatever waits (scalar control: the values are wave-uniform)
     const uint32_t avail = tail - head;
-    if (avail < 64u && !(drain && avail > 0u)) {
-      if (drain) break;
-      continue;
+    if (avail < 64u) {
+      if (n < s_end) continue;
+      if (avail == 0u) break;
     }
     // ---- phase 2: spans of up to 64 queued pairs, one per lane
     const uint32_t cnt_b = avail < 64u ? avail : 64u;
@@ -819,10 +829,9 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
     const uint32_t base = (uint32_t)old, cbase = (uint32_t)(old >> 32);
     Item* const q_items = items + (size_t)shard * item_scap;
     uint32_t* const q_cs = item_cs + (size_t)shard * item_scap;
-    const unsigned long long lt = __lanemask_lt();
     bool ovf = false;
     if (rect0) {
-      const uint32_t slot = base + (uint32_t)__popcll(m0 & lt);
+      const uint32_t slot = base + rank_in(m0);
       if (slot < item_scap) {
         q_items[slot] = Item{ptri, chan, sp.r0_start | (sp.r0_count << 16), pn};
         q_cs[slot] = cbase + i0 - k0;
@@ -831,7 +840,7 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
       }
     }
     if (rect1) {
-      const uint32_t slot = base + c0 + (uint32_t)__popcll(m1 & lt);
+      const uint32_t slot = base + c0 + rank_in(m1);
       if (slot < item_scap) {
         q_items[slot] = Item{ptri, chan, sp.r1_start | (sp.r1_count << 16), pn};
         q_cs[slot] = cbase + t0 + i1 - k1;
