@@ -536,18 +536,18 @@ __device__ inline float wave_min_dpp(float x) { return ukey_float(~wave_max_key(
 
 // Block b's place in tile order.  Blocks are handed to the 8 XCDs round
 // robin and each XCD takes its blocks in order; here every XCD gets runs of
-// XCD_CHUNK consecutive blocks (neighbouring triangles share vertices in the
+// `run` consecutive blocks (neighbouring triangles share vertices in the
 // XCD's L2), the runs dealt to the XCDs in turn, so that all XCDs move
 // through the scene together and finish together whatever the distribution
 // of work in it.  Longer runs fetch fewer vertex lines twice (from two
-// XCDs); 64 blocks (256 tiles) cost no time over 16.  Blocks past the last
-// full round of runs keep their index.
-constexpr uint32_t XCD_CHUNK = 64;
-__device__ inline uint32_t xcd_chunked(uint32_t b, uint32_t nb) {
-  const uint32_t full = nb / (8u * XCD_CHUNK) * (8u * XCD_CHUNK);
+// XCDs); runs of 256 tiles cost no time over 64.  Blocks past the last full
+// round of runs keep their index.
+constexpr uint32_t XCD_RUN_TILES = 256;
+__device__ inline uint32_t xcd_chunked(uint32_t b, uint32_t nb, uint32_t run) {
+  const uint32_t full = nb / (8u * run) * (8u * run);
   if (b >= full) return b;
   const uint32_t x = b % 8u, k = b / 8u;
-  return ((k / XCD_CHUNK) * 8u + x) * XCD_CHUNK + k % XCD_CHUNK;
+  return ((k / run) * 8u + x) * run + k % run;
 }
 
 // Candidate pairs of a work item (rectangle or row).
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
   uint32_t* const ring = s_ring[w];
   float (*const vtx)[BOUNDS_TILE] = s_vtx[w];
   const bool pack_scan = small_c * small_r <= 1023u;
-  const uint32_t tile = xcd_chunked(blockIdx.x, gridDim.x) * WPB + w;
+  const uint32_t tile = xcd_chunked(blockIdx.x, gridDim.x, XCD_RUN_TILES / WPB) * WPB + w;
   if (tile >= total_tiles) return;  // wave-uniform
   // records go to the tile's shard: neighbouring tiles, which hold similar
   // work, spread over all shards
