@@ -277,3 +277,31 @@ def test_colocated_heads(ctx):
                            t[k * n1:(k + 1) * n1][sel])
         parity.assert_parity(rep, f"colocated head {k}")
     assert np.count_nonzero(t != grca.GRCA_MISS_TRI) > 1000
+
+
+def test_more_than_64_sensors_in_one_cast(ctx):
+    # 72 sensor slots in one cast: the intersection reads sensor fields from
+    # the device descriptors instead of its LDS copy (at most 64 slots)
+    _say("72 small sensors (18 rigs x 4 heads, 8x64 rays) in one cast vs all-pairs per "
+         "sensor, and vs the cast of the first 64")
+    wl = synth.config1()
+    v, f = wl.scene.vertices, wl.scene.indices
+    ctx.scene_update(0, v, f)
+    rng = np.random.default_rng(72)
+    origins = [np.array([rng.uniform(-15, 15), rng.uniform(-15, 15), rng.uniform(0.5, 3.0)],
+                        np.float32) for _ in range(18)]
+    rig = synth.colocated_rig(origins, heads=4, channels=8, rays=64, range_max=60.0)
+    ids = list(range(100, 172))
+    for i, s in zip(ids, rig):
+        ctx.sensor_config(i, s, 0)
+    n1 = 8 * 64
+    d, t = _cast(ctx, ids, 72 * n1)
+    d64, t64 = _cast(ctx, ids[:64], 64 * n1)
+    assert np.array_equal(t[:64 * n1], t64)
+    assert np.array_equal(d[:64 * n1].view(np.uint32), d64.view(np.uint32))
+    for k, i in enumerate(ids):
+        d2, t2 = _cast(ctx, [i], n1, grca.GRCA_CAST_ALL_PAIRS)
+        sl = slice(k * n1, (k + 1) * n1)
+        assert np.array_equal(t[sl], t2), f"sensor {k}: culled != all-pairs"
+        assert np.array_equal(d[sl].view(np.uint32), d2.view(np.uint32))
+    assert np.count_nonzero(t != grca.GRCA_MISS_TRI) > 5000
