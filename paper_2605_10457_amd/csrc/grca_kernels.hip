@@ -532,6 +532,20 @@ __device__ inline uint32_t wave_max_key(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 __device__ inline float wave_max_dpp(float x) { return ukey_float(wave_max_key(float_ukey(x))); }
+// Wave-wide sum by the same DPP steps (0, what an absent source reads, is
+// neutral), read from the last lane.
+__device__ inline float wave_sum_dpp(float x) {
+#define GRCA_DPP_ADD(CTRL, ROWS) \
+  x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, ROWS, 0xf, true));
+  GRCA_DPP_ADD(0x111, 0xf)  // row_shr:1
+  GRCA_DPP_ADD(0x112, 0xf)  // row_shr:2
+  GRCA_DPP_ADD(0x114, 0xf)  // row_shr:4
+  GRCA_DPP_ADD(0x118, 0xf)  // row_shr:8
+  GRCA_DPP_ADD(0x142, 0xa)  // row_bcast:15
+  GRCA_DPP_ADD(0x143, 0xc)  // row_bcast:31
+#undef GRCA_DPP_ADD
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
 __device__ inline float wave_min_dpp(float x) { return ukey_float(~wave_max_key(~float_ukey(x))); }
 
 // Block b's place in tile order.  Blocks are handed to the 8 XCDs round
@@ -634,9 +648,6 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
   // bounding spheres (AABB centre, largest vertex distance) of the lane's
   // triangles and of the tile; the span phase reads vertices from LDS
   float tc[2][4];  // centre x, y, z and radius, per triangle
-  float lo[3], hi[3];  // the lane's AABB over its active triangles
-#pragma unroll
-  for (int c = 0; c < 3; ++c) { lo[c] = 3.0e38f; hi[c] = -3.0e38f; }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     float mn[3], mx[3];
@@ -645,7 +656,6 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
       mn[c] = fminf(v[h][c], fminf(v[h][3 + c], v[h][6 + c]));
       mx[c] = fmaxf(v[h][c], fmaxf(v[h][3 + c], v[h][6 + c]));
       tc[h][c] = 0.5f * (mn[c] + mx[c]);
-      if (active[h]) { lo[c] = fminf(lo[c], mn[c]); hi[c] = fmaxf(hi[c], mx[c]); }
     }
     float r2 = 0.0f;
 #pragma unroll
@@ -664,12 +674,19 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
                                                   __popcll(__ballot(active[1]))));
   // the tile's sphere (wave-uniform: scalar registers).  One sphere for both
   // halves: the halves' own spheres would skip 1-2% fewer sensor steps for
-  // twice the reductions.
+  // twice the reductions; the centre of the box of the vertices gives a
+  // slightly tighter test for 6 reductions instead of 3, which costs more
+  // than it saves.
   float gs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   if (group_cull) {
+    // centre: the mean of the triangles' centres (3 sums instead of the 6
+    // extrema of a box); radius: the largest vertex distance
     float g[3];
+    const float inv_n = 1.0f / (float)n_active;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) g[c] = 0.5f * (wave_min_dpp(lo[c]) + wave_max_dpp(hi[c]));
+    for (int c = 0; c < 3; ++c)
+      g[c] = first_lane(wave_sum_dpp((active[0] ? tc[0][c] : 0.0f) + (active[1] ? tc[1][c] : 0.0f)) *
+                        inv_n);
     float gr2 = 0.0f;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -681,9 +698,9 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
         if (active[h]) gr2 = fmaxf(gr2, d2);
       }
     }
-    gs[0] = first_lane(g[0]);
-    gs[1] = first_lane(g[1]);
-    gs[2] = first_lane(g[2]);
+    gs[0] = g[0];
+    gs[1] = g[1];
+    gs[2] = g[2];
     gs[3] = first_lane(__builtin_amdgcn_sqrtf(wave_max_dpp(gr2)));
   }
   unsigned long long rtic = 0ull;  // candidates tested inline by this lane
