@@ -225,7 +225,9 @@ __device__ inline unsigned long long ray_test(const Statics& st, float cphi, flo
   const float w2 = fmaf(st.n2x, dx, fmaf(st.n2y, dy, st.n2z * dz));
   const float c = fmaf(st.Nx, dx, fmaf(st.Ny, dy, st.Nz * dz));
   if (w0 >= 0.0f && w1 >= 0.0f && w2 >= 0.0f && c > 0.0f) {
-    const float t = st.h / c;
+    // hardware reciprocal (1 ulp) and one rounded product: t within 2 ulps
+    // of h / c, the same at every call site
+    const float t = st.h * __builtin_amdgcn_rcpf(c);
     if (t >= dmin && t <= dmax) {
       // f_sort(t) for t > 0 sets the sign bit; the miss key stays larger.
       const uint32_t u = __float_as_uint(t);

@@ -1172,6 +1172,24 @@ struct CandSensor {
   float dmin, dmax;
 };
 
+// Item i of a wave's staged ItemInfo array in LDS, read through an LDS
+// pointer so that the address is 32-bit arithmetic (a generic pointer would
+// make it a 64-bit multiply-add).
+__device__ inline ItemInfo lds_item(const ItemInfo* base, uint32_t i) {
+  typedef const uint32_t __attribute__((address_space(3))) LU;
+  typedef const char __attribute__((address_space(3))) LC;
+  static_assert(sizeof(ItemInfo) == 24, "six words");
+  LU* p = (LU*)((LC*)base + __umul24(24u, i));
+  ItemInfo o;
+  o.tri = p[0];
+  o.cr = p[1];
+  o.rs = p[2];
+  o.bias = (int32_t)p[3];
+  o.inv_rc = __uint_as_float(p[4]);
+  o.h = __uint_as_float(p[5]);
+  return o;
+}
+
 // One candidate of the flattened loop, from its owner item (staged in LDS)
 // and batch position f: the ray's table entries and the ray's key as this
 // wave can see it (never below the true minimum: keys only decrease), all
@@ -1201,22 +1219,26 @@ template <bool LDS_SENS>
 __device__ inline Cand cand_read(int own, uint32_t f, const ItemInfo* in_w,
                                  const IsectSensor* sen, const DevSensor* sens,
                                  const unsigned long long* keys, bool any_mask) {
-  const ItemInfo inf = in_w[own];
+  const ItemInfo inf = lds_item(in_w, (uint32_t)own);
   const CandSensor sn = cand_sensor<LDS_SENS>(inf.rs >> 16, sen, sens);
-  // batch position -> (channel, ray) of the item's rectangle
+  // batch position -> (channel, ray) of the item's rectangle.  local is
+  // below 255 x 65535 < 2^24 (the span-class limits), so it is exact in
+  // FP32 and local x rcp(r_count) is within 1 of the quotient for r_count
+  // >= 3 (exact for 1 and 2); one correction step makes it exact.  Every
+  // product below stays under 2^25: 24-bit multiplies.
   const uint32_t r_count = inf.rs & 0xFFFFu;
   const uint32_t local = (uint32_t)((int32_t)f + inf.bias);
   uint32_t c = 0;
   if (local >= r_count) {
     c = (uint32_t)((float)local * inf.inv_rc);
-    if (c * r_count > local) --c;
-    else if ((c + 1) * r_count <= local) ++c;
+    if (__umul24(c, r_count) > local) --c;
+    else if (__umul24(c + 1, r_count) <= local) ++c;
   }
-  const uint32_t r = local - c * r_count;
+  const uint32_t r = local - __umul24(c, r_count);
   const uint32_t ch = (inf.cr & 0xFFFFu) + c;
   uint32_t ray = (inf.cr >> 16) + r;
   if (ray >= sn.chi) ray -= sn.chi;
-  const uint32_t gl = ch * sn.chi + ray;
+  const uint32_t gl = __umul24(ch, sn.chi) + ray;
   Cand o;
   o.on = true;
   if (any_mask) o.on = !sn.mask || gload(sn.mask, gl);
@@ -1232,8 +1254,9 @@ template <bool LDS_SENS>
 __device__ inline void cand_finish(const Cand& o, int own, const float4 (*st_w)[64],
                                    const ItemInfo* in_w, const IsectSensor* sen,
                                    const DevSensor* sens, unsigned long long* keys) {
-  const ItemInfo& inf = in_w[own];
-  const float4 a0 = st_w[0][own], a1 = st_w[1][own], a2 = st_w[2][own];
+  const uint32_t ow = (uint32_t)own;
+  const ItemInfo inf = lds_item(in_w, ow);
+  const float4 a0 = st_w[0][ow], a1 = st_w[1][ow], a2 = st_w[2][ow];
   const Statics st{a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
                    a2.x, a2.y, a2.z, a2.w, inf.h, 0.0f, 0.0f, 0.0f};
   const uint32_t sid = inf.rs >> 16;
@@ -1356,7 +1379,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
               inf.cr = (it.chan & 0xFFFFu) | (it.rays << 16);
               inf.rs = rc | (it.sensor << 16);
               inf.bias = 0;
-              inf.inv_rc = 1.0f / (float)rc;
+              inf.inv_rc = __builtin_amdgcn_rcpf((float)rc);  // an estimate: corrected below
               inf.h = st.h;
               in_s[w][lane] = inf;
               skip = lo - c0;  // candidates of the item before this ticket
