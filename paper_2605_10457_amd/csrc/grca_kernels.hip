@@ -682,7 +682,7 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
     // centre: the mean of the triangles' centres (3 sums instead of the 6
     // extrema of a box); radius: the largest vertex distance
     float g[3];
-    const float inv_n = 1.0f / (float)n_active;
+    const float inv_n = __builtin_amdgcn_rcpf((float)n_active);  // any centre will do
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       g[c] = first_lane(wave_sum_dpp((active[0] ? tc[0][c] : 0.0f) + (active[1] ? tc[1][c] : 0.0f)) *
@@ -774,7 +774,9 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
       pz[k] = vtx[3 * k + 2][src];
     }
     const uint32_t ptri = tri0 + src;
-    const DevSensor& s = sens[pn];
+    // (at most 4096 sensor slots per cast: a 32-bit offset)
+    const DevSensor& s = *reinterpret_cast<const DevSensor*>(
+        reinterpret_cast<const char*>(sens) + __umul24(pn, (uint32_t)sizeof(DevSensor)));
     Span sp;
     const bool ok = live && span_of(px, py, pz, s, small_c, small_r, (e >> 7) & 1u,
                                     (e >> 8) & 1u, sp);
@@ -821,8 +823,9 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
     const uint32_t c0 = first_lane((uint32_t)__popcll(m0));
     const uint32_t c1 = first_lane((uint32_t)__popcll(m1));
     if (c0 == 0u) continue;
-    const uint32_t k0 = rect0 ? sp.c_count * sp.r0_count : 0u;
-    const uint32_t k1 = rect1 ? sp.c_count * sp.r1_count : 0u;
+    // (counts below 2^16: 24-bit multiplies)
+    const uint32_t k0 = rect0 ? __umul24(sp.c_count, sp.r0_count) : 0u;
+    const uint32_t k1 = rect1 ? __umul24(sp.c_count, sp.r1_count) : 0u;
     uint32_t i0, i1, t0, t1;
     if (pack_scan) {  // both counts <= 1023: one scan of (k0 | k1 << 16)
       const uint32_t pk = wave_incl_scan(k0 | (k1 << 16));
