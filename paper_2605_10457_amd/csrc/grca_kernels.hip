@@ -1486,6 +1486,7 @@ __global__ __launch_bounds__(256) void allpairs_kernel(const DevSensor* __restri
 }
 
 // ------------------------------------------------------------------ resolve
+template <bool VEC>
 __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint32_t n,
                                float* __restrict__ dist, uint32_t* __restrict__ tri,
                                Counters* __restrict__ cnt) {
@@ -1516,13 +1517,40 @@ __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint
       S.tests = te;
     }
   }
-  if (g >= n) return;
-  const unsigned long long k = keys[g];
-  const uint32_t hi = (uint32_t)(k >> 32);
-  // inverse of f_sort: m = ((u >> 31) - 1) | 2^31
-  const uint32_t m = ((hi >> 31) - 1u) | 0x80000000u;
-  if (dist) dist[g] = __uint_as_float(hi ^ m);
-  if (tri) tri[g] = (uint32_t)k;
+  // rays 4g .. 4g + 3: 16-byte loads and stores when the outputs allow them
+  const uint32_t r0 = 4u * g;
+  if (r0 >= n) return;
+  const bool vec = VEC && r0 + 3u < n;
+  unsigned long long k[4];
+  if (vec) {
+    const ulonglong2* p = reinterpret_cast<const ulonglong2*>(keys + r0);
+    const ulonglong2 a = p[0], b = p[1];
+    k[0] = a.x; k[1] = a.y; k[2] = b.x; k[3] = b.y;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) k[j] = r0 + j < n ? keys[r0 + j] : KEY_INIT;
+  }
+  float d[4];
+  uint32_t t[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t hi = (uint32_t)(k[j] >> 32);
+    // inverse of f_sort: m = ((u >> 31) - 1) | 2^31
+    const uint32_t m = ((hi >> 31) - 1u) | 0x80000000u;
+    d[j] = __uint_as_float(hi ^ m);
+    t[j] = (uint32_t)k[j];
+  }
+  if (vec) {
+    if (dist) *reinterpret_cast<float4*>(dist + r0) = make_float4(d[0], d[1], d[2], d[3]);
+    if (tri) *reinterpret_cast<uint4*>(tri + r0) = make_uint4(t[0], t[1], t[2], t[3]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (r0 + j >= n) break;
+      if (dist) dist[r0 + j] = d[j];
+      if (tri) tri[r0 + j] = t[j];
+    }
+  }
 }
 
 // ------------------------------------------------------------------ pose
@@ -1697,8 +1725,15 @@ hipError_t launch_allpairs(const DevScene* scenes, const DevSensor* sens, uint32
 
 hipError_t launch_resolve(const unsigned long long* keys, uint32_t n, float* dist, uint32_t* tri,
                           Counters* cnt, hipStream_t st) {
-  hipLaunchKernelGGL(resolve_kernel, dim3(cdiv(n > 0 ? n : 1, 256)), dim3(256), 0, st, keys, n,
-                     dist, tri, cnt);
+  // 16-byte stores need 16-byte aligned outputs (caller buffers may be offset)
+  const bool vec = (reinterpret_cast<uintptr_t>(dist) % 16u == 0) &&
+                   (reinterpret_cast<uintptr_t>(tri) % 16u == 0);
+  const uint32_t nb = cdiv(std::max(cdiv(n, 4u), 64u), 256u);
+  if (vec)
+    hipLaunchKernelGGL(resolve_kernel<true>, dim3(nb), dim3(256), 0, st, keys, n, dist, tri, cnt);
+  else
+    hipLaunchKernelGGL(resolve_kernel<false>, dim3(nb), dim3(256), 0, st, keys, n, dist, tri,
+                       cnt);
   return hipGetLastError();
 }
 
