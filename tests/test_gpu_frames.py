@@ -281,3 +281,28 @@ def test_range_limited_parity(torch, dmax):
         assert np.array_equal(t4, t[4 * 128 * 4096:5 * 128 * 4096])
     finally:
         ctx.close()
+
+
+def test_device_outputs_at_offsets(torch):
+    # the output conversion stores four rays with 16-byte stores when both
+    # output pointers are 16-byte aligned, one by one otherwise
+    _say("cast into device outputs at 4-byte and 16-byte offsets vs host outputs")
+    a = synth.config1()
+    ctx = grca.Context(0)
+    try:
+        ctx.scene_update(0, a.scene.vertices, a.scene.indices)
+        ctx.sensor_config(0, a.sensors[0], 0)
+        n = 32 * 512
+        ref_d, ref_t = ctx.cast_host([0], n)
+        for off in (1, 4):
+            d = torch.full((n + off,), -1.0, dtype=torch.float32, device="cuda")
+            t = torch.zeros((n + off,), dtype=torch.int32, device="cuda")
+            ctx.cast([0], out_distance=d[off:], out_tri=t[off:])
+            ctx.synchronize()
+            got_d = d.cpu().numpy()
+            got_t = t.cpu().numpy().view(np.uint32)
+            assert np.all(got_d[:off] == -1.0) and np.all(got_t[:off] == 0)
+            assert np.array_equal(got_t[off:], ref_t), off
+            assert np.array_equal(got_d[off:].view(np.uint32), ref_d.view(np.uint32)), off
+    finally:
+        ctx.close()
