@@ -610,7 +610,6 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
   const uint32_t lane = lane_id();
   uint32_t* const ring = s_ring[w];
   float (*const vtx)[BOUNDS_TILE] = s_vtx[w];
-  const bool pack_scan = small_c * small_r <= 1023u;
   const uint32_t tile = xcd_chunked(blockIdx.x, gridDim.x, XCD_RUN_TILES / WPB) * WPB + w;
   if (tile >= total_tiles) return;  // wave-uniform
   // records go to the tile's shard: neighbouring tiles, which hold similar
@@ -814,11 +813,12 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
     const Item lg{ptri, chan, 0u, pn};
     wave_push(is_large, lg, large + (size_t)shard * large_scap, large_scap,
               reinterpret_cast<uint32_t*>(&cnt->large[shard].nc), &cnt->overflow, 2u, nullptr);
-    // the batch's small-class records: rect0 records first, then rect1, all
+    // the batch's small-class records, each lane's rect0 then its rect1, all
     // appended to the wave's item shard with one 64-bit atomic that reserves
     // the slots (low word) and the candidate range (high word) together;
     // each record carries its first candidate index, so that within a shard
-    // the candidate starts increase with the slot
+    // the candidate starts increase with the slot.  One scan of the lane's
+    // candidate total (below 2^26 per lane, so the wave's total fits 32 bits).
     const unsigned long long m0 = __ballot(rect0), m1 = __ballot(rect1);
     const uint32_t c0 = first_lane((uint32_t)__popcll(m0));
     const uint32_t c1 = first_lane((uint32_t)__popcll(m1));
@@ -826,21 +826,11 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
     // (counts below 2^16: 24-bit multiplies)
     const uint32_t k0 = rect0 ? __umul24(sp.c_count, sp.r0_count) : 0u;
     const uint32_t k1 = rect1 ? __umul24(sp.c_count, sp.r1_count) : 0u;
-    uint32_t i0, i1, t0, t1;
-    if (pack_scan) {  // both counts <= 1023: one scan of (k0 | k1 << 16)
-      const uint32_t pk = wave_incl_scan(k0 | (k1 << 16));
-      const uint32_t tt = last_lane(pk);
-      i0 = pk & 0xFFFFu; i1 = pk >> 16; t0 = tt & 0xFFFFu; t1 = tt >> 16;
-    } else {
-      i0 = wave_incl_scan(k0);
-      i1 = wave_incl_scan(k1);
-      t0 = last_lane(i0);
-      t1 = last_lane(i1);
-    }
+    const uint32_t incl = wave_incl_scan(k0 + k1);
+    const uint32_t cands = last_lane(incl);
     Shard& sh = cnt->items[shard];
     unsigned long long old = 0ull;
     if (lane == 0) {
-      const uint32_t cands = t0 + t1;
       old = atomicAdd(&sh.nc, (unsigned long long)(c0 + c1) | ((unsigned long long)cands << 32));
       // candidate index space of the shard (2^31, so tickets cannot wrap) exhausted
       if ((uint32_t)(old >> 32) > CAND_LIMIT - cands) atomicOr(&cnt->overflow, 4u);
@@ -849,21 +839,22 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
     const uint32_t base = (uint32_t)old, cbase = (uint32_t)(old >> 32);
     Item* const q_items = items + (size_t)shard * item_scap;
     uint32_t* const q_cs = item_cs + (size_t)shard * item_scap;
+    // records of the lanes below (a rect1 implies the lane's rect0)
+    const uint32_t slot0 = base + rank_in(m0) + rank_in(m1);
+    const uint32_t cs0 = cbase + incl - (k0 + k1);
     bool ovf = false;
     if (rect0) {
-      const uint32_t slot = base + rank_in(m0);
-      if (slot < item_scap) {
-        q_items[slot] = Item{ptri, chan, sp.r0_start | (sp.r0_count << 16), pn};
-        q_cs[slot] = cbase + i0 - k0;
+      if (slot0 < item_scap) {
+        q_items[slot0] = Item{ptri, chan, sp.r0_start | (sp.r0_count << 16), pn};
+        q_cs[slot0] = cs0;
       } else {
         ovf = true;
       }
     }
     if (rect1) {
-      const uint32_t slot = base + c0 + rank_in(m1);
-      if (slot < item_scap) {
-        q_items[slot] = Item{ptri, chan, sp.r1_start | (sp.r1_count << 16), pn};
-        q_cs[slot] = cbase + t0 + i1 - k1;
+      if (slot0 + 1u < item_scap) {
+        q_items[slot0 + 1u] = Item{ptri, chan, sp.r1_start | (sp.r1_count << 16), pn};
+        q_cs[slot0 + 1u] = cs0 + k0;
       } else {
         ovf = true;
       }
