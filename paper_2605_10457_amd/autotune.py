@@ -89,9 +89,10 @@ def signature(workload) -> str:
     return f"{workload.name}_{workload.scene.num_triangles}_{shape}"
 
 
-def save(result: dict, arch: str, sig: str) -> str:
+def save(result: dict, arch: str, name: str, sig: str) -> str:
+    """Write the result for workload `name` (the file load() reads back)."""
     os.makedirs(TUNING_DIR, exist_ok=True)
-    path = os.path.join(TUNING_DIR, f"{arch}_{sig.split('_')[0]}.json")
+    path = os.path.join(TUNING_DIR, f"{arch}_{name}.json")
     out = dict(result, arch=arch, signature=sig)
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
@@ -115,7 +116,8 @@ def main():
     from . import synth
 
     ap = argparse.ArgumentParser(description="tune the caster on a workload and save the result")
-    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--config", default="4",
+                    help="1-4, or 'colocated' (config 4's scene seen by 2 rigs of 4 heads)")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--rounds", type=int, default=2)
@@ -125,8 +127,9 @@ def main():
         print(f"[tune] {m}", file=sys.stderr, flush=True)
 
     t0 = time.time()
-    wl = {1: synth.config1, 2: synth.config2, 3: synth.config3,
-          4: lambda: synth.config4(scale=args.scale)}[args.config]()
+    wl = {"1": synth.config1, "2": synth.config2, "3": synth.config3,
+          "4": lambda: synth.config4(scale=args.scale),
+          "colocated": lambda: synth.config4_colocated(scale=args.scale)}[args.config]()
     log(f"{wl.name}: {wl.scene.num_triangles} tris in {time.time() - t0:.1f}s")
     ctx = grca.Context(0)
     ctx.set_options(item_capacity=96 << 20, large_capacity=8 << 20)
@@ -134,7 +137,7 @@ def main():
     n = sum(len(s["elevation"]) * s["rays_per_channel"] for s in wl.sensors)
     res = tune(ctx, ids, n, reps=args.reps, max_rounds=args.rounds, log=log)
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-    path = save(res, arch, signature(wl))
+    path = save(res, arch, wl.name, signature(wl))
     log(f"best {res['options']} {res['ms']:.3f} ms -> {path}")
     print(json.dumps({"options": res["options"], "ms": res["ms"], "path": path}))
     ctx.close()
