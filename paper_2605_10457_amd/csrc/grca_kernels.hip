@@ -75,6 +75,14 @@ __device__ inline float2 gload_f2(const float2* base, uint32_t byte_off) {
   return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
 }
 
+// Lane l's value of a double (wave-uniform result).
+__device__ inline double lane_f64(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Number of lanes below this one whose bit is set in mask m (v_mbcnt).
 __device__ inline uint32_t rank_in(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -1041,11 +1049,19 @@ __global__ __launch_bounds__(WPB * 64) void expand_kernel(
       if (!make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
                         S.z[i2], s, st, nrm))
         continue;
+      // the three edge planes' angles, lane k computing edge k (one atan2
+      // and one sqrt in the instruction stream instead of three each; the
+      // values are the same), then read from lanes 0-2
+      const uint32_t ke = lane < 3u ? lane : 0u;
+      const double ex = ke == 0u ? nrm[0][0] : (ke == 1u ? nrm[1][0] : nrm[2][0]);
+      const double ey = ke == 0u ? nrm[0][1] : (ke == 1u ? nrm[1][1] : nrm[2][1]);
+      const double be = atan2(ey, ex);
+      const double he = sqrt(ex * ex + ey * ey);
       double beta[3], hxy[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        beta[k] = atan2(nrm[k][1], nrm[k][0]);
-        hxy[k] = sqrt(nrm[k][0] * nrm[k][0] + nrm[k][1] * nrm[k][1]);
+        beta[k] = lane_f64(be, k);
+        hxy[k] = lane_f64(he, k);
       }
       const uint32_t c_from = L.chan & 0xFFFFu, c_count = L.chan >> 16;
       for (uint32_t base = 0; base < c_count; base += 64) {
