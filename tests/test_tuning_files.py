@@ -4,7 +4,6 @@ signature, and the shipped files load for the workloads they were tuned on."""
 import json
 import os
 
-
 from paper_2605_10457_amd import autotune
 
 
