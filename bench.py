@@ -365,8 +365,7 @@ def main():
             sel = offs[s_i] + rays.astype(np.int64)
             rep = parity.check(s, v_or, sc.indices, orc, d_np[sel], t_np[sel])
             bad += rep["counts"]["clean_mismatch"] + rep["counts"]["flagged_unacceptable"]
-            for k2, v2 in rep["counts"].items():
-                counts[k2] = counts.get(k2, 0) + v2
+            parity.merge(counts, rep["counts"])
         cpu = {"value": tot_rays / t_cpu, "unit": "rays/s", "cores": int(threads), "kind": "oracle",
                "sample": f"{args.cpu_rays} seeded rays per sensor x {n_sens} sensors of the last "
                          f"timed frame, FP64 brute force over all {sc.num_triangles} triangles",

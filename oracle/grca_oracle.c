@@ -45,13 +45,26 @@
 
 /* ---- flags --------------------------------------------------------------- */
 #define ORC_GRAZING            1u  /* ray within GRAZE_RAD of a relevant triangle's boundary */
-#define ORC_NEAR_TIE           2u  /* best and second-best triangles within TIE_REL in t     */
-#define ORC_RANGE_EDGE         4u  /* a hit within TIE_REL of range_min or range_max          */
+#define ORC_NEAR_TIE           2u  /* best and second-best triangles within the band in t    */
+#define ORC_RANGE_EDGE         4u  /* a hit within the band of range_min or range_max that is
+                                      not behind the closest in-range hit                   */
 #define ORC_GRAZING_INCIDENCE  8u  /* |d . n| of the hit triangle below INCIDENCE_COS         */
 
 #define GRAZE_RAD     1e-6
 #define TIE_REL       1e-5
 #define INCIDENCE_COS 0.05
+
+/* Relative half-width of the band within which a single-precision evaluation
+ * of a hit distance may legitimately differ from this FP64 one: TIE_REL, the
+ * distance tolerance of the parity criterion, widened in proportion to
+ * 1/|cos| below INCIDENCE_COS, because t = h / (d . n) amplifies the absolute
+ * error of the direction by 1/|cos incidence|.  Two distances whose bands
+ * overlap may come out in either order; a distance whose band contains a
+ * range limit may fall on either side of it. */
+static double dist_band(double cos_abs) {
+  if (cos_abs >= INCIDENCE_COS) return TIE_REL;
+  return TIE_REL * INCIDENCE_COS / (cos_abs > 1e-300 ? cos_abs : 1e-300);
+}
 
 typedef struct {
   float origin[3];
@@ -194,8 +207,10 @@ static void cast_one(const cast_job* J, uint64_t i) {
   const double dmin = (double)s->range_min, dmax = (double)s->range_max;
   const int single = (int)(s->flags & 1u);
 
-  /* pass 1: closest hit = lexicographic min of (t, k); second best on another triangle */
-  double t1 = INFINITY, t2 = INFINITY;
+  /* pass 1: closest hit = lexicographic min of (t, k); second best on another
+   * triangle; the nearest face hit whose distance band holds a range limit */
+  double t1 = INFINITY, t2 = INFINITY, b1 = TIE_REL, b2 = TIE_REL;
+  double te = INFINITY, be = TIE_REL;
   uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu;
   uint32_t flags = 0;
   for (uint64_t k = 0; k < J->ntri; ++k) {
@@ -204,18 +219,27 @@ static void cast_one(const cast_job* J, uint64_t i) {
     load_vertex(J->xyz, J->idx[3 * k + 1], b);
     load_vertex(J->xyz, J->idx[3 * k + 2], c);
     if (!mt_fp64(o, d, a, b, c, single, &t, &det)) continue;
-    if (fabs(t - dmin) <= TIE_REL * dmin || fabs(t - dmax) <= TIE_REL * dmax)
-      flags |= ORC_RANGE_EDGE;
+    /* |cos incidence| = |det| / |e1 x e2| for a unit d (det = -d . (e1 x e2)) */
+    double e1[3], e2[3], N[3];
+    sub3(b, a, e1); sub3(c, a, e2); cross3(e1, e2, N);
+    const double band = dist_band(fabs(det) / norm3(N));
+    if ((fabs(t - dmin) <= band * dmin || fabs(t - dmax) <= band * dmax) && t < te) {
+      te = t; be = band;
+    }
     if (!(t >= dmin && t <= dmax)) continue;
     const uint32_t kk = (uint32_t)k;
     if (t < t1 || (t == t1 && kk < k1)) {
-      t2 = t1; k2 = k1;
-      t1 = t; k1 = kk;
+      t2 = t1; k2 = k1; b2 = b1;
+      t1 = t; k1 = kk; b1 = band;
     } else if (t < t2 || (t == t2 && kk < k2)) {
-      t2 = t; k2 = kk;
+      t2 = t; k2 = kk; b2 = band;
     }
   }
-  if (k2 != 0xFFFFFFFFu && t2 - t1 <= TIE_REL * t1) flags |= ORC_NEAR_TIE;
+  if (k2 != 0xFFFFFFFFu && t2 - t1 <= fmax(b1, b2) * t1) flags |= ORC_NEAR_TIE;
+  /* a range-edge hit matters only if it is not behind the closest in-range
+   * hit (beyond their bands): a hidden one cannot change the answer */
+  if (te < INFINITY && (k1 == 0xFFFFFFFFu || te <= t1 * (1.0 + fmax(b1, be))))
+    flags |= ORC_RANGE_EDGE;
 
   /* pass 2: grazing -- a triangle whose angular boundary passes within
    * GRAZE_RAD of the ray and which is not hidden behind the best hit. */

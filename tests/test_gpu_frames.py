@@ -56,8 +56,7 @@ def _sample_parity(sensors, v, f, d, t, per_sensor, seed, label):
         sel = off + rays.astype(np.int64)
         rep = parity.check(s, v, f, orc, d[sel], t[sel])
         parity.assert_parity(rep, label)
-        for k, x in rep["counts"].items():
-            tot[k] = tot.get(k, 0) + x
+        parity.merge(tot, rep["counts"])
         off += n
     print(label, tot, flush=True)
     return tot

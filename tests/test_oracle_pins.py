@@ -367,3 +367,154 @@ def test_ray_mask_switches_rays_off():
     on = mask.astype(bool)
     assert np.array_equal(a["tri"][on], b["tri"][on])
     assert np.all(b["tri"][~on] == O.MISS) and np.all(np.isinf(b["t"][~on]))
+
+
+def test_pose_deform_time_term_closed_form():
+    """v_rest + A sin(omega t + phase) n at instants where the argument is an
+    exact quarter turn, with omega != 1, so that omega t itself is pinned:
+    omega t + phase = pi/2 gives +A n, 3 pi/2 gives -A n, pi gives v_rest."""
+    rng = np.random.default_rng(16)
+    rest = rng.uniform(-10, 10, (40, 3)).astype(np.float32)
+    nrm = rng.normal(0, 1, (40, 3))
+    nrm = (nrm / np.linalg.norm(nrm, axis=1, keepdims=True)).astype(np.float32)
+    A = 0.25
+    plus = (rest.astype(np.float64) + A * nrm.astype(np.float64)).astype(np.float32)
+    minus = (rest.astype(np.float64) - A * nrm.astype(np.float64)).astype(np.float32)
+    zero = np.zeros(40, np.float32)
+    # omega = 2 rad/s: 2 * (pi/4) is pi/2 exactly in FP64, so sin is exactly 1
+    assert np.array_equal(O.pose_deform(rest, nrm, zero, A, 2.0, math.pi / 4), plus)
+    assert np.array_equal(O.pose_deform(rest, nrm, zero, A, 2.0, 3 * math.pi / 4), minus)
+    assert np.array_equal(O.pose_deform(rest, nrm, zero, A, 4.0, math.pi / 4), rest)
+    # with a phase of 0.5 rad (exact in FP32): omega t + 0.5 = pi/2 and 3 pi/2
+    # (sin is flat there, so the FP64 rounding of the sum does not show)
+    ph = np.full(40, np.float32(0.5))
+    assert np.array_equal(O.pose_deform(rest, nrm, ph, A, 2.0, (math.pi / 2 - 0.5) / 2), plus)
+    assert np.array_equal(O.pose_deform(rest, nrm, ph, A, 2.0, (3 * math.pi / 2 - 0.5) / 2),
+                          minus)
+    # the time scale matters: at t = pi/4, omega = 1 would give sin = 0.707, not 1
+    assert not np.array_equal(O.pose_deform(rest, nrm, zero, A, 1.0, math.pi / 4), plus)
+
+
+# ---------------------------------------------------------------- oracle_pair outputs
+def _wall_sensor(elev, rays=360):
+    # yaw 0: f = +x, r = -y, u = +z; ray R has theta = (R - rays/2) * 2 pi / rays
+    return synth.sensor((0.0, 0.0, 0.0), 0.0, np.asarray(elev, np.float32), rays, 360.0,
+                        0.05, 1000.0)
+
+
+def _angles(s, g):
+    chi = s["rays_per_channel"]
+    th = (g % chi - chi // 2) * (float(s["fov"]) / chi)
+    ph = float(s["elevation"][g // chi])
+    return th, ph
+
+
+def test_pair_plane_distance_and_incidence_on_axis_wall():
+    """Wall in the plane x = X: the plane distance along the ray is
+    X / (cos theta cos phi) and the signed incidence cosine is
+    +-cos theta cos phi, the sign following the winding."""
+    X = 7.5
+    s = _wall_sensor(np.radians([-20.0, -3.0, 0.0, 11.0]))
+    ccw = np.array([[X, -40, -40], [X, 40, -40], [X, 0, 40]], np.float32)   # normal +x
+    cw = ccw[[0, 2, 1]]                                                     # normal -x
+    f = np.array([[0, 1, 2]], np.uint32)
+    checked = 0
+    for g in [2 * 360 + 180, 2 * 360 + 185, 0 * 360 + 170, 3 * 360 + 200, 1 * 360 + 150]:
+        th, ph = _angles(s, g)
+        expect_t = X / (math.cos(th) * math.cos(ph))
+        expect_c = math.cos(th) * math.cos(ph)
+        a = O.pair(s, ccw, f, g, 0)
+        b = O.pair(s, cw, f, g, 0)
+        assert a["plane_t"] == pytest.approx(expect_t, rel=1e-13)
+        assert b["plane_t"] == pytest.approx(expect_t, rel=1e-13)
+        assert a["cos_inc"] == pytest.approx(expect_c, rel=1e-13)
+        assert b["cos_inc"] == pytest.approx(-expect_c, rel=1e-13)
+        assert a["hit"] and b["hit"] and a["t"] == pytest.approx(expect_t, rel=1e-13)
+        assert not a["degenerate"]
+        checked += 1
+    assert checked == 5
+
+
+@pytest.mark.parametrize("y0", [0.01, -0.01, 0.3])
+def test_pair_margin_vertical_edge(y0):
+    """Edge x = X, y = Y0 (vertical), interior toward -y: the signed sine of
+    the angle from ray (theta, phi) to the plane through the emitter and that
+    edge is cos(phi) sin(theta + atan2(Y0, X)), positive inside."""
+    X = 5.0
+    s = _wall_sensor(np.radians([-4.0, 0.0, 2.5]))
+    tri = np.array([[X, y0, -60], [X, y0, 60], [X, y0 - 60, 0]], np.float32)
+    f = np.array([[0, 1, 2]], np.uint32)
+    yy = float(np.float32(y0))
+    alpha = math.atan2(yy, X)
+    for g in [1 * 360 + 180, 1 * 360 + 179, 0 * 360 + 181, 2 * 360 + 178, 2 * 360 + 183]:
+        th, ph = _angles(s, g)
+        expect = math.cos(ph) * math.sin(th + alpha)
+        p = O.pair(s, tri, f, g, 0)
+        assert p["margin"] == pytest.approx(expect, rel=1e-10, abs=1e-15), (g, p, expect)
+        assert p["hit"] == (expect >= 0)
+
+
+@pytest.mark.parametrize("z0", [0.02, -0.05])
+def test_pair_margin_horizontal_edge(z0):
+    """Edge x = X, z = Z0 (horizontal), interior below: the margin is
+    (Z0 cos theta cos phi - X sin phi) / sqrt(X^2 + Z0^2)."""
+    X = 6.0
+    s = _wall_sensor(np.radians([-1.0, 0.0, 0.4]))
+    tri = np.array([[X, -60, z0], [X, 60, z0], [X, 0, z0 - 60]], np.float32)
+    f = np.array([[0, 1, 2]], np.uint32)
+    zz = float(np.float32(z0))
+    for g in [0 * 360 + 180, 1 * 360 + 180, 2 * 360 + 180, 2 * 360 + 176, 0 * 360 + 190]:
+        th, ph = _angles(s, g)
+        expect = (zz * math.cos(th) * math.cos(ph) - X * math.sin(ph)) / math.hypot(X, zz)
+        p = O.pair(s, tri, f, g, 0)
+        assert p["margin"] == pytest.approx(expect, rel=1e-10, abs=1e-15), (g, p, expect)
+
+
+def test_pair_degenerate_cases():
+    s = _wall_sensor(np.radians([0.0]))
+    f = np.array([[0, 1, 2]], np.uint32)
+    # emitter in the triangle's plane (z = 0)
+    inplane = np.array([[1, -1, 0], [2, 1, 0], [3, 0, 0]], np.float32)
+    assert O.pair(s, inplane, f, 180, 0)["degenerate"]
+    # zero area (collinear vertices)
+    line = np.array([[5, -1, 0], [5, 0, 0], [5, 1, 0]], np.float32)
+    p = O.pair(s, line, f, 180, 0)
+    assert p["degenerate"] and not p["hit"]
+    # repeated index
+    v = np.array([[5, -1, -1], [5, 1, -1]], np.float32)
+    p = O.pair(s, v, np.array([[0, 1, 1]], np.uint32), 180, 0)
+    assert p["degenerate"] and not p["hit"]
+
+
+# ---------------------------------------------------------------- range-edge flag relevance
+def _ray_x(rmax=10.0):
+    s = _sensor(origin=(0, 0, 0), elev=np.array([0.0], np.float32), rays=4, fov=360.0,
+                rmin=0.05, rmax=rmax)
+    return s, np.array([2], np.uint32)   # ray 2 points along +x
+
+
+def _walls(*xs, half=1.0):
+    v = []
+    for x in xs:
+        v += [[x, -half, -half], [x, half, -half], [x, 0, half]]
+    return np.array(v, np.float32), np.arange(3 * len(xs), dtype=np.uint32).reshape(-1, 3)
+
+
+def test_range_edge_flag_only_when_not_hidden():
+    s, r = _ray_x(10.0)
+    # clean hit at 5 m, a triangle exactly at range_max behind it: hidden, no flag
+    v, f = _walls(5.0, 10.0)
+    out = O.cast(s, v, f, rays=r)
+    assert out["tri"][0] == 0 and out["flags"][0] == 0
+    # the range-max triangle alone: flagged
+    v, f = _walls(10.0)
+    out = O.cast(s, v, f, rays=r)
+    assert out["tri"][0] == 0 and out["flags"][0] & O.RANGE_EDGE
+    # just beyond range_max (out of range in FP64) and nothing in front: flagged, miss
+    v, f = _walls(10.00003)
+    out = O.cast(s, v, f, rays=r)
+    assert out["tri"][0] == O.MISS and out["flags"][0] & O.RANGE_EDGE
+    # just beyond range_max, behind a clean hit: hidden
+    v, f = _walls(4.0, 10.00003)
+    out = O.cast(s, v, f, rays=r)
+    assert out["tri"][0] == 0 and out["flags"][0] == 0
