@@ -82,8 +82,18 @@ const char* grca_last_error(const grca_context* ctx);
 
 /* ---- scenes ---------------------------------------------------------------- */
 
+/* Calls that change a scene or a sensor (grca_scene_update, _release,
+ * _set_rigid, _set_deform, _pose, grca_sensor_config of an existing id,
+ * grca_sensor_release) first wait for every cast and frame launch in flight
+ * that reads it, on any workspace or stream, and complete any recast those
+ * need with the state they were issued against.  Casts that do not read it
+ * keep running. */
+
 /* Create or replace scene `scene_id` (any 32-bit id; one context holds many
- * scenes, e.g. one per serving client).
+ * scenes, e.g. one per serving client): the triangle set of the problem
+ * statement (section 1.1), in the world frame in which section 3.1 places the
+ * emitters, as vertex and index buffers (the per-triangle vertex data the
+ * appendix's early pass reads once per frame).
  *  vertices_xyz: num_vertices * 3 FP32, xyz-interleaved.  Stored on the device
  *                as structure-of-arrays x[], y[], z[].
  *  indices:      num_triangles * 3 uint32; triangle k uses vertices
@@ -207,7 +217,8 @@ typedef struct {
   uint64_t row_items;     /* per-channel work items expanded from large records      */
   uint64_t rtic;          /* ray-triangle intersection checks executed               */
   uint32_t recasts;       /* overflow-driven recasts                                 */
-  uint32_t reserved;
+  uint32_t overflowed;    /* casts (for a frame: launches since it was created) whose
+                             work queues overflowed; each was recast or reported      */
   uint64_t pairs_evaluated; /* of pairs_tested: those whose span the bounds pass
                                computed (kept by the tile's and by the triangle's own
                                bounding-sphere test)                                 */
@@ -256,12 +267,24 @@ grca_status grca_frame_create(grca_context* ctx, uint32_t scene_id, const uint32
                               uint32_t num_sensors, float* out_distance_dev,
                               uint32_t* out_tri_dev, grca_frame** out);
 /* Launch one frame: copy the instance matrices (host, may be NULL) and time
- * into the frame's pose block, then replay the graph on hip_stream. */
+ * into the frame's pose block, then replay the graph on hip_stream.  Launches
+ * may be issued back to back without synchronising; each one overwrites the
+ * frame's outputs.  If the frame's scene or one of its sensors was
+ * reallocated since the last launch (grca_scene_update with a new topology,
+ * grca_scene_set_rigid / _set_deform, grca_sensor_config of one of its
+ * sensors), the graph is re-captured first; NOT_FOUND if one was released,
+ * INVALID_ARG if a sensor now observes another scene. */
 grca_status grca_frame_launch(grca_frame* frame, const float* instance_matrices, double time_s,
                               void* hip_stream);
-/* Check the frame's last launch for a queue overflow (waits for it); on
- * overflow the frame's buffers are grown, the graph is re-captured and the
- * frame is re-run. */
+/* Wait for the frame's launches and check every launch since the last
+ * synchronize for a work-queue overflow (the overflow record accumulates on
+ * the device across launches).  On overflow the frame's queues are grown and
+ * the graph is re-captured; if the last launch overflowed it is run again, so
+ * the outputs are complete on return.  Returns CAPACITY (after growing) when
+ * an EARLIER launch overflowed: its outputs, already overwritten or copied
+ * out by the caller, were incomplete (the deferred list's capacity is "never
+ * reached" in appendix "BAT list allocation"; here it is never exceeded
+ * silently). */
 grca_status grca_frame_synchronize(grca_frame* frame, void* hip_stream);
 void grca_frame_destroy(grca_frame* frame);
 /* One frame exactly as grca_frame_launch runs it (same kernels, buffers and
@@ -287,6 +310,8 @@ grca_status grca_cast_ws(grca_context* ctx, grca_workspace* ws, const uint32_t* 
                          void* hip_stream);
 /* As grca_synchronize for one workspace: waits for its cast and recasts on overflow. */
 grca_status grca_workspace_synchronize(grca_context* ctx, grca_workspace* ws, void* hip_stream);
+/* As grca_last_stats for the most recent cast on workspace `ws` (waits for it). */
+grca_status grca_workspace_stats(grca_context* ctx, grca_workspace* ws, grca_stats* out);
 
 #ifdef __cplusplus
 }

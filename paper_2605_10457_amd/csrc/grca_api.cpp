@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -130,6 +131,7 @@ struct CastRecord {
   hipStream_t st = nullptr;
   uint64_t rays = 0, pairs = 0;
   uint32_t recasts = 0;
+  uint32_t overflowed = 0;  // casts of this record whose queues overflowed
 };
 
 struct grca_workspace {
@@ -175,6 +177,8 @@ struct grca_frame {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t tev[7] = {};  // stage events of grca_frame_profile
+  bool stale = false;      // a scene or sensor it reads was reallocated: re-capture
+  uint32_t lost = 0;       // overflowed launches not recast, not yet reported
 };
 
 struct grca_context {
@@ -185,6 +189,8 @@ struct grca_context {
   grca_options opt{};
   grca_workspace* def_ws = nullptr;
   grca_workspace* last_ws = nullptr;
+  std::set<grca_workspace*> workspaces;  // the default one and the caller's
+  std::set<grca_frame*> frames;
   std::string err;
 };
 
@@ -285,6 +291,7 @@ grca_status ws_reserve(grca_context* ctx, grca_workspace* ws, uint64_t rays, uin
 grca_status ws_init(grca_context* ctx, grca_workspace* ws) {
   ws->ctx = ctx;
   HIPCHK(dmalloc(&ws->cnt, 1));
+  HIPCHK(hipMemset(ws->cnt, 0, sizeof(Counters)));  // the sticky record starts clear
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&ws->cnt_host), RING * sizeof(Summary)));
   std::memset(ws->cnt_host, 0, RING * sizeof(Summary));
   for (int i = 0; i < RING; ++i) HIPCHK(hipEventCreateWithFlags(&ws->ev[i], hipEventDisableTiming));
@@ -314,6 +321,45 @@ struct Plan {
   uint64_t rays = 0;
   uint64_t pairs = 0;
 };
+
+// A sensor's device record, without the per-cast fields (output offset,
+// scene slot, single-sided flag).
+DevSensor sensor_record(const SensorData& S) {
+  DevSensor d{};
+  for (int c = 0; c < 3; ++c) {
+    d.o[c] = S.desc.origin[c]; d.f[c] = S.desc.forward[c];
+    d.r[c] = S.desc.right[c]; d.u[c] = S.desc.up[c];
+  }
+  d.dmin = S.desc.range_min;
+  d.dmax = S.desc.range_max;
+  d.gamma = S.desc.num_channels;
+  d.chi = S.desc.rays_per_channel;
+  d.wrap = S.wrap ? 1u : 0u;
+  d.lut_size = S.lut_size;
+  const double theta0 = -std::floor(d.chi / 2.0) * S.dtheta;
+  d.theta_start = (float)theta0;
+  d.inv_dtheta = (float)(1.0 / S.dtheta);
+  d.period_idx = (float)(kTwoPi / S.dtheta);
+  d.theta_start_d = theta0;
+  d.inv_dtheta_d = 1.0 / S.dtheta;
+  d.period_idx_d = kTwoPi / S.dtheta;
+  d.chan = S.chan; d.chan_d = S.chan_d; d.sin_tab = S.sin_tab; d.bins = S.lut; d.az = S.az;
+  d.mask = S.mask;
+  d.elev0 = S.elev0;
+  d.inv_delev = S.inv_delev;
+  d.elev_tol = S.elev_tol;
+  d.cull_dmax = d.dmax * (1.0f + 1e-5f) + 1e-6f;
+  d.in_dmax = d.dmax * (1.0f - 1e-5f);
+  d.in_dmin = d.dmin * (1.0f + 1e-5f);
+  d.elev_m = 2e-5f + d.elev_tol;
+  d.last_chan = (float)(d.gamma - 1u);
+  d.elev0_g = d.elev0 * d.inv_delev;
+  d.az_noise = S.az_noise;
+  d.key_offset = 0;
+  d.scene = 0;
+  d.cull_back = 0;
+  return d;
+}
 
 grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32_t block,
                       Plan& P, uint32_t flags = 0) {
@@ -362,38 +408,9 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
     DevScene& cur = P.scenes.back();
     cur.sensor_end = k + 1;
     P.pairs += cur.ntri;
-    DevSensor d{};
-    for (int c = 0; c < 3; ++c) {
-      d.o[c] = S.desc.origin[c]; d.f[c] = S.desc.forward[c];
-      d.r[c] = S.desc.right[c]; d.u[c] = S.desc.up[c];
-    }
-    d.dmin = S.desc.range_min;
-    d.dmax = S.desc.range_max;
-    d.gamma = S.desc.num_channels;
-    d.chi = S.desc.rays_per_channel;
+    DevSensor d = sensor_record(S);
     d.key_offset = (uint32_t)offs[i];
-    d.wrap = S.wrap ? 1u : 0u;
     d.scene = (uint32_t)(P.scenes.size() - 1);
-    d.lut_size = S.lut_size;
-    const double theta0 = -std::floor(d.chi / 2.0) * S.dtheta;
-    d.theta_start = (float)theta0;
-    d.inv_dtheta = (float)(1.0 / S.dtheta);
-    d.period_idx = (float)(kTwoPi / S.dtheta);
-    d.theta_start_d = theta0;
-    d.inv_dtheta_d = 1.0 / S.dtheta;
-    d.period_idx_d = kTwoPi / S.dtheta;
-    d.chan = S.chan; d.chan_d = S.chan_d; d.sin_tab = S.sin_tab; d.bins = S.lut; d.az = S.az;
-    d.mask = S.mask;
-    d.elev0 = S.elev0;
-    d.inv_delev = S.inv_delev;
-    d.elev_tol = S.elev_tol;
-    d.cull_dmax = d.dmax * (1.0f + 1e-5f) + 1e-6f;
-    d.in_dmax = d.dmax * (1.0f - 1e-5f);
-    d.in_dmin = d.dmin * (1.0f + 1e-5f);
-    d.elev_m = 2e-5f + d.elev_tol;
-    d.last_chan = (float)(d.gamma - 1u);
-    d.elev0_g = d.elev0 * d.inv_delev;
-    d.az_noise = S.az_noise;
     d.cull_back = 0;
     if (flags & GRCA_CULL_BACKFACE) {
       const float* f = S.desc.forward;
@@ -493,6 +510,7 @@ grca_status ws_drain(grca_context* ctx, grca_workspace* ws) {
     CastRecord& R = ws->rec[slot];
     if (!R.live) continue;
     int attempt = 0;
+    if (ws->cnt_host[slot].overflow) R.overflowed = 1;
     while (ws->cnt_host[slot].overflow) {
       if (++attempt > 6) {
         R.live = false;
@@ -524,6 +542,13 @@ grca_status check_vec(const float* v, const char* name, const grca_context* ctx)
     if (!std::isfinite(v[k])) return fail(ctx, GRCA_ERR_INVALID_ARG, std::string(name) + " not finite");
   return GRCA_OK;
 }
+
+// Before a scene or sensor changes: finish every cast and frame launch still
+// in flight that reads it (recasting overflowed ones with the state they were
+// issued against), and, with `stale`, mark the frames that read it for
+// re-capture (their graphs hold its device pointers).  scene_id / sensor_id
+// of -1 match nothing.  Defined with the frames below.
+grca_status settle_users(grca_context* ctx, int64_t scene_id, int64_t sensor_id, bool stale);
 
 }  // namespace
 
@@ -564,6 +589,7 @@ extern "C" grca_status grca_create(int hip_device, grca_context** out) {
     delete ctx;
     return GRCA_ERR_DEVICE;
   }
+  ctx->workspaces.insert(ctx->def_ws);
   *out = ctx;
   return GRCA_OK;
 }
@@ -633,6 +659,11 @@ extern "C" grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id,
       dfree(bad);
       if (hbad & 1u) return fail(ctx, GRCA_ERR_INVALID_ARG, "non-finite vertex coordinate");
       if (hbad & 2u) return fail(ctx, GRCA_ERR_INVALID_ARG, "index out of range");
+    }
+    if (it != ctx->scenes.end()) {
+      // a topology update reallocates the scene; a vertex-only update keeps its buffers
+      grca_status rs = settle_users(ctx, scene_id, -1, !vonly);
+      if (rs != GRCA_OK) return rs;
     }
     SceneData fresh;
     SceneData& sc = (it == ctx->scenes.end()) ? fresh : it->second;
@@ -727,6 +758,8 @@ extern "C" grca_status grca_scene_release(grca_context* ctx, uint32_t scene_id) 
     auto it = ctx->scenes.find(scene_id);
     if (it == ctx->scenes.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown scene");
     HIPCHK(hipSetDevice(ctx->device));
+    grca_status rs = settle_users(ctx, scene_id, -1, true);
+    if (rs != GRCA_OK) return rs;
     HIPCHK(hipDeviceSynchronize());
     free_scene(it->second);
     ctx->scenes.erase(it);
@@ -796,6 +829,8 @@ extern "C" grca_status grca_scene_set_rigid(grca_context* ctx, uint32_t scene_id
     SceneData& sc = it->second;
     grca_status rc = check_ranges(ctx, sc, num_instances, vertex_start, vertex_count);
     if (rc != GRCA_OK) return rc;
+    rc = settle_users(ctx, scene_id, -1, true);
+    if (rc != GRCA_OK) return rc;
     hipStream_t st = as_stream(hip_stream);
     HIPCHK(hipStreamSynchronize(st));
     dfree(sc.rr_x); dfree(sc.rr_y); dfree(sc.rr_z); dfree(sc.rigid_blocks);
@@ -853,6 +888,8 @@ extern "C" grca_status grca_scene_set_deform(grca_context* ctx, uint32_t scene_i
       if (!std::isfinite(normals_xyz[i])) return fail(ctx, GRCA_ERR_INVALID_ARG, "non-finite normal");
     for (uint64_t i = 0; i < total; ++i)
       if (!std::isfinite(phases[i])) return fail(ctx, GRCA_ERR_INVALID_ARG, "non-finite phase");
+    rc = settle_users(ctx, scene_id, -1, true);
+    if (rc != GRCA_OK) return rc;
     hipStream_t st = as_stream(hip_stream);
     HIPCHK(hipStreamSynchronize(st));
     dfree(sc.dr_x); dfree(sc.dr_y); dfree(sc.dr_z);
@@ -940,7 +977,9 @@ extern "C" grca_status grca_scene_pose(grca_context* ctx, uint32_t scene_id,
     if (!std::isfinite(time_s)) return fail(ctx, GRCA_ERR_INVALID_ARG, "time not finite");
     SceneData& sc = it->second;
     hipStream_t st = as_stream(hip_stream);
-    grca_status rc = stage_pose(ctx, sc, instance_matrices, time_s, flags & GRCA_MEM_DEVICE, st);
+    grca_status rc = settle_users(ctx, scene_id, -1, false);
+    if (rc != GRCA_OK) return rc;
+    rc = stage_pose(ctx, sc, instance_matrices, time_s, flags & GRCA_MEM_DEVICE, st);
     if (rc != GRCA_OK) return rc;
     return enqueue_pose_kernels(ctx, sc, st);
   })
@@ -1058,6 +1097,11 @@ extern "C" grca_status grca_sensor_config(grca_context* ctx, uint32_t sensor_id,
     }
     auto it = ctx->sensors.find(sensor_id);
     if (it != ctx->sensors.end()) {
+      const grca_status rs = settle_users(ctx, -1, sensor_id, true);
+      if (rs != GRCA_OK) {
+        cleanup();
+        return rs;
+      }
       HIPCHK(hipDeviceSynchronize());
       free_sensor(it->second);
       it->second = sd;
@@ -1074,6 +1118,8 @@ extern "C" grca_status grca_sensor_release(grca_context* ctx, uint32_t sensor_id
     auto it = ctx->sensors.find(sensor_id);
     if (it == ctx->sensors.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown sensor");
     HIPCHK(hipSetDevice(ctx->device));
+    grca_status rs = settle_users(ctx, -1, sensor_id, true);
+    if (rs != GRCA_OK) return rs;
     HIPCHK(hipDeviceSynchronize());
     free_sensor(it->second);
     ctx->sensors.erase(it);
@@ -1125,6 +1171,7 @@ grca_status cast_on(grca_context* ctx, grca_workspace* ws, const uint32_t* ids, 
   R.rays = P.rays;
   R.pairs = P.pairs;
   R.recasts = 0;
+  R.overflowed = 0;
   rc = enqueue_kernels(ctx, ws, slot, P, dist, tri, flags, st);
   if (rc != GRCA_OK) return rc;
   R.live = true;
@@ -1165,31 +1212,41 @@ extern "C" grca_status grca_synchronize(grca_context* ctx, void* hip_stream) {
   })
 }
 
+namespace {
+grca_status stats_of(grca_context* ctx, grca_workspace* ws, grca_stats* out) {
+  std::memset(out, 0, sizeof(*out));
+  if (!ws || ws->last_slot < 0) return GRCA_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  const int slot = ws->last_slot;
+  const bool was_live = ws->rec[slot].live;
+  grca_status rc = ws_drain(ctx, ws);
+  if (rc != GRCA_OK) return rc;
+  if (!was_live) HIPCHK(hipEventSynchronize(ws->ev[slot]));
+  const Summary& c = ws->cnt_host[slot];
+  const CastRecord& R = ws->rec[slot];
+  out->rays = R.rays;
+  out->pairs_tested = R.pairs;
+  out->rect_items = c.n_items >= c.n_rows ? c.n_items - c.n_rows : 0;
+  out->large_records = c.n_large;
+  out->row_items = c.n_rows;
+  out->rtic = c.rtic;
+  out->recasts = R.recasts;
+  out->overflowed = R.overflowed;
+  out->pairs_evaluated = c.pairs;
+  out->sphere_tests = c.tests;
+  return GRCA_OK;
+}
+}  // namespace
+
 extern "C" grca_status grca_last_stats(grca_context* ctx, grca_stats* out) {
   if (!ctx || !out) return GRCA_ERR_INVALID_ARG;
-  GUARD({
-    std::memset(out, 0, sizeof(*out));
-    grca_workspace* ws = ctx->last_ws;
-    if (!ws || ws->last_slot < 0) return GRCA_OK;
-    HIPCHK(hipSetDevice(ctx->device));
-    const int slot = ws->last_slot;
-    const bool was_live = ws->rec[slot].live;
-    grca_status rc = ws_drain(ctx, ws);
-    if (rc != GRCA_OK) return rc;
-    if (!was_live) HIPCHK(hipEventSynchronize(ws->ev[slot]));
-    const Summary& c = ws->cnt_host[slot];
-    const CastRecord& R = ws->rec[slot];
-    out->rays = R.rays;
-    out->pairs_tested = R.pairs;
-    out->rect_items = c.n_items >= c.n_rows ? c.n_items - c.n_rows : 0;
-    out->large_records = c.n_large;
-    out->row_items = c.n_rows;
-    out->rtic = c.rtic;
-    out->recasts = R.recasts;
-    out->pairs_evaluated = c.pairs;
-    out->sphere_tests = c.tests;
-    return GRCA_OK;
-  })
+  GUARD({ return stats_of(ctx, ctx->last_ws, out); })
+}
+
+extern "C" grca_status grca_workspace_stats(grca_context* ctx, grca_workspace* ws,
+                                            grca_stats* out) {
+  if (!ctx || !ws || ws->ctx != ctx || !out) return GRCA_ERR_INVALID_ARG;
+  GUARD({ return stats_of(ctx, ws, out); })
 }
 
 // =============================================================== options
@@ -1246,6 +1303,7 @@ extern "C" grca_status grca_workspace_create(grca_context* ctx, uint64_t max_ray
       return rc;
     }
     ws->fixed = true;
+    ctx->workspaces.insert(ws);
     *out = ws;
     if (bytes_out) *bytes_out = ws->bytes;
     return GRCA_OK;
@@ -1256,6 +1314,7 @@ extern "C" void grca_workspace_destroy(grca_workspace* ws) {
   if (!ws) return;
   if (ws->ctx) {
     if (ws->ctx->last_ws == ws) ws->ctx->last_ws = nullptr;
+    ws->ctx->workspaces.erase(ws);
     (void)hipSetDevice(ws->ctx->device);
   }
   ws_free(ws);
@@ -1347,6 +1406,12 @@ void destroy_graphs(grca_frame* fr) {
 }
 
 grca_status frame_plan(grca_context* ctx, grca_frame* fr, Plan& P) {
+  for (uint32_t id : fr->ids) {
+    auto it = ctx->sensors.find(id);
+    if (it != ctx->sensors.end() && it->second.desc.scene_id != fr->scene_id)
+      return fail(ctx, GRCA_ERR_INVALID_ARG,
+                  "frame sensor " + std::to_string(id) + " no longer observes the frame's scene");
+  }
   return make_plan(ctx, fr->ids.data(), (uint32_t)fr->ids.size(), ctx->opt.bounds_block, P);
 }
 
@@ -1377,6 +1442,87 @@ grca_status capture_frame(grca_context* ctx, grca_frame* fr) {
   R.dist = fr->out_dist;
   R.tri = fr->out_tri;
   R.flags = GRCA_MEM_DEVICE;
+  return GRCA_OK;
+}
+// Wait for the frame's launches in flight and look at the sticky overflow
+// record they left.  Launches that overflowed dropped work: the queues are
+// grown and the graph re-captured; if the last launch overflowed it is run
+// again (its pose inputs are still in place), and earlier ones, whose outputs
+// have been overwritten, are counted in `lost` for grca_frame_synchronize.
+grca_status frame_settle(grca_context* ctx, grca_frame* fr, hipStream_t st) {
+  grca_workspace* ws = fr->ws;
+  CastRecord& R = ws->rec[0];
+  if (!R.live) return GRCA_OK;
+  for (int attempt = 0; attempt < 7; ++attempt) {
+    HIPCHK(hipEventSynchronize(ws->ev[0]));
+    const Summary c = ws->cnt_host[0];
+    if (!c.sticky.overflow) {
+      R.live = false;
+      return GRCA_OK;
+    }
+    fr->lost += c.sticky.casts - (c.overflow ? 1u : 0u);
+    R.overflowed += c.sticky.casts;
+    Summary want = c;
+    want.overflow = c.sticky.overflow;
+    want.max_items_shard = c.sticky.max_items_shard;
+    want.max_large_shard = c.sticky.max_large_shard;
+    uint64_t items = ws->item_cap, large = ws->large_cap;
+    grca_status rc = grown_caps(ctx, want, items, large);
+    if (rc != GRCA_OK) { R.live = false; return rc; }
+    dfree(ws->items); dfree(ws->item_cs); ws->item_cap = 0;
+    dfree(ws->large); ws->large_cap = 0;
+    rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
+    if (rc != GRCA_OK) { R.live = false; return rc; }
+    rc = capture_frame(ctx, fr);
+    if (rc != GRCA_OK) { R.live = false; return rc; }
+    fr->stale = false;
+    HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(&ws->cnt->sticky),
+                       (uint32_t)(sizeof(Sticky) / sizeof(uint32_t)), 0u, st));
+    if (!c.overflow) {  // the last launch was complete
+      HIPCHK(hipStreamSynchronize(st));
+      R.live = false;
+      return GRCA_OK;
+    }
+    R.recasts++;
+    HIPCHK(hipGraphLaunch(fr->exec, st));
+    HIPCHK(hipEventRecord(ws->ev[0], st));
+    R.st = st;
+  }
+  R.live = false;
+  return fail(ctx, GRCA_ERR_CAPACITY, "frame queue kept overflowing after regrowth");
+}
+
+// A frame whose inputs were reallocated is re-captured before it runs again.
+grca_status frame_refresh(grca_context* ctx, grca_frame* fr) {
+  if (!fr->stale) return GRCA_OK;
+  const grca_status rc = capture_frame(ctx, fr);
+  if (rc == GRCA_OK) fr->stale = false;
+  return rc;
+}
+
+grca_status settle_users(grca_context* ctx, int64_t scene_id, int64_t sensor_id, bool stale) {
+  auto reads = [&](const std::vector<uint32_t>& ids) {
+    for (uint32_t id : ids) {
+      if ((int64_t)id == sensor_id) return true;
+      if (scene_id < 0) continue;
+      auto it = ctx->sensors.find(id);
+      if (it != ctx->sensors.end() && (int64_t)it->second.desc.scene_id == scene_id) return true;
+    }
+    return false;
+  };
+  for (grca_workspace* ws : ctx->workspaces) {
+    bool busy = false;
+    for (int i = 0; i < RING && !busy; ++i) busy = ws->rec[i].live && reads(ws->rec[i].ids);
+    if (!busy) continue;
+    const grca_status rc = ws_drain(ctx, ws);
+    if (rc != GRCA_OK) return rc;
+  }
+  for (grca_frame* fr : ctx->frames) {
+    if ((int64_t)fr->scene_id != scene_id && !reads(fr->ids)) continue;
+    const grca_status rc = frame_settle(ctx, fr, fr->ws->rec[0].st);
+    if (rc != GRCA_OK) return rc;
+    if (stale) fr->stale = true;
+  }
   return GRCA_OK;
 }
 }  // namespace
@@ -1415,6 +1561,7 @@ extern "C" grca_status grca_frame_create(grca_context* ctx, uint32_t scene_id,
       grca_frame_destroy(fr);
       return rc;
     }
+    ctx->frames.insert(fr);
     *out = fr;
     return GRCA_OK;
   })
@@ -1431,8 +1578,10 @@ extern "C" grca_status grca_frame_launch(grca_frame* fr, const float* instance_m
     if (!std::isfinite(time_s)) return fail(ctx, GRCA_ERR_INVALID_ARG, "time not finite");
     hipStream_t st = as_stream(hip_stream);
     grca_workspace* ws = fr->ws;
+    grca_status rc = frame_refresh(ctx, fr);
+    if (rc != GRCA_OK) return rc;
     if (ws->rec[0].live && ws->rec[0].st != st) HIPCHK(hipStreamWaitEvent(st, ws->ev[0], 0));
-    grca_status rc = stage_pose(ctx, it->second, instance_matrices, time_s, false, st);
+    rc = stage_pose(ctx, it->second, instance_matrices, time_s, false, st);
     if (rc != GRCA_OK) return rc;
     HIPCHK(hipGraphLaunch(fr->exec, st));
     HIPCHK(hipEventRecord(ws->ev[0], st));
@@ -1449,35 +1598,25 @@ extern "C" grca_status grca_frame_synchronize(grca_frame* fr, void* hip_stream) 
   grca_context* ctx = fr->ctx;
   GUARD({
     HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t st = as_stream(hip_stream);
-    grca_workspace* ws = fr->ws;
-    for (int attempt = 0; attempt < 7; ++attempt) {
-      HIPCHK(hipEventSynchronize(ws->ev[0]));
-      const Summary c = ws->cnt_host[0];
-      if (!c.overflow) {
-        ws->rec[0].live = false;
-        return GRCA_OK;
-      }
-      uint64_t items = ws->item_cap, large = ws->large_cap;
-      grca_status rc = grown_caps(ctx, c, items, large);
-      if (rc != GRCA_OK) return rc;
-      dfree(ws->items); dfree(ws->item_cs); ws->item_cap = 0;
-      dfree(ws->large); ws->large_cap = 0;
-      rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
-      if (rc != GRCA_OK) return rc;
-      rc = capture_frame(ctx, fr);
-      if (rc != GRCA_OK) return rc;
-      ws->rec[0].recasts++;
-      HIPCHK(hipGraphLaunch(fr->exec, st));
-      HIPCHK(hipEventRecord(ws->ev[0], st));
+    const grca_status rc = frame_settle(ctx, fr, as_stream(hip_stream));
+    if (rc != GRCA_OK) return rc;
+    if (fr->lost) {
+      const uint32_t n = fr->lost;
+      fr->lost = 0;
+      return fail(ctx, GRCA_ERR_CAPACITY,
+                  std::to_string(n) + " earlier launch(es) of this frame overflowed their work "
+                  "queues and produced incomplete outputs; the queues have been grown");
     }
-    return fail(ctx, GRCA_ERR_CAPACITY, "frame queue kept overflowing after regrowth");
+    return GRCA_OK;
   })
 }
 
 extern "C" void grca_frame_destroy(grca_frame* fr) {
   if (!fr) return;
-  if (fr->ctx) (void)hipSetDevice(fr->ctx->device);
+  if (fr->ctx) {
+    (void)hipSetDevice(fr->ctx->device);
+    fr->ctx->frames.erase(fr);
+  }
   if (fr->ws) (void)ws_quiesce(fr->ctx, fr->ws);
   destroy_graphs(fr);
   for (int k = 0; k < 7; ++k)
@@ -1499,8 +1638,10 @@ extern "C" grca_status grca_frame_profile(grca_frame* fr, const float* instance_
     if (!std::isfinite(time_s)) return fail(ctx, GRCA_ERR_INVALID_ARG, "time not finite");
     hipStream_t st = as_stream(hip_stream);
     grca_workspace* ws = fr->ws;
+    grca_status rc = frame_refresh(ctx, fr);
+    if (rc != GRCA_OK) return rc;
     if (ws->rec[0].live && ws->rec[0].st != st) HIPCHK(hipStreamWaitEvent(st, ws->ev[0], 0));
-    grca_status rc = stage_pose(ctx, it->second, instance_matrices, time_s, false, st);
+    rc = stage_pose(ctx, it->second, instance_matrices, time_s, false, st);
     if (rc != GRCA_OK) return rc;
     Plan P;
     rc = frame_plan(ctx, fr, P);

@@ -108,6 +108,16 @@ struct alignas(256) Shard {
 };
 static_assert(sizeof(Shard) == 256, "one shard counter per 256-byte line");
 
+// Overflow record that outlives a cast: the init kernel leaves it alone, so
+// it accumulates over every cast run on the same counters (the launches of a
+// frame) until the host clears it.
+struct Sticky {
+  uint32_t overflow;         // OR of the overflow bits of those casts
+  uint32_t casts;            // how many of them overflowed
+  uint32_t max_items_shard;  // largest item-shard request among them
+  uint32_t max_large_shard;  // largest large-shard request among them
+};
+
 // Compact per-cast summary written at the end of a cast and copied to the host.
 struct Summary {
   uint32_t n_items;          // item slots requested over all shards
@@ -119,14 +129,16 @@ struct Summary {
   unsigned long long rtic;   // candidate pairs executed
   unsigned long long pairs;  // (triangle, origin) spans computed
   unsigned long long tests;  // (triangle, origin) bounding-sphere tests
+  Sticky sticky;             // the sticky record as this cast left it
 };
 
-// Device counters of one cast, cleared by the init kernel.
+// Device counters of one cast, cleared by the init kernel up to `sticky`.
 struct Counters {
   Shard items[NSHARD];
   Shard large[NSHARD];
   alignas(256) uint32_t overflow;
   alignas(256) Summary sum;
+  alignas(256) Sticky sticky;  // not cleared per cast (see Sticky)
 };
 
 // Per-(triangle, origin) statics of the ray test, all in the sensor's local

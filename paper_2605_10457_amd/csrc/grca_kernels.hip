@@ -148,7 +148,8 @@ __global__ void init_kernel(unsigned long long* __restrict__ keys, uint32_t n,
                             Counters* __restrict__ cnt) {
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g < n) keys[g] = KEY_INIT;
-  constexpr uint32_t WORDS = (uint32_t)(sizeof(Counters) / sizeof(uint32_t));
+  // everything but the sticky overflow record
+  constexpr uint32_t WORDS = (uint32_t)(__builtin_offsetof(Counters, sticky) / sizeof(uint32_t));
   if (g < WORDS) reinterpret_cast<uint32_t*>(cnt)[g] = 0u;
 }
 
@@ -1202,9 +1203,12 @@ __device__ inline ItemInfo lds_item(const ItemInfo* base, uint32_t i) {
 
 // One candidate of the flattened loop, from its owner item (staged in LDS)
 // and batch position f: the ray's table entries and the ray's key as this
-// wave can see it (never below the true minimum: keys only decrease), all
-// reads issued together.  The owner's statics are read from LDS when the
-// candidate is tested, so that a lane can keep several candidates in flight.
+// wave can see it, all reads issued together.  The key is read atomically
+// (relaxed), so it is some value the key held: never below the true minimum,
+// since keys only decrease.  A hit that is not below it cannot improve on the
+// final key and skips its atomic; the atomicMin stays the authority.  The
+// owner's statics are read from LDS when the candidate is tested, so that a
+// lane can keep several candidates in flight.
 struct Cand {
   float2 cp, ca;
   unsigned long long seen;
@@ -1255,7 +1259,9 @@ __device__ inline Cand cand_read(int own, uint32_t f, const ItemInfo* in_w,
   o.cp = gload_f2(sn.chan, ch * 8u);
   o.ca = gload_f2(sn.az, ray * 8u);
   o.kidx = sn.key_offset + gl;
-  o.seen = keys[o.kidx];
+  // a single-copy-atomic read: another wave's atomicMin may land at any time
+  o.seen = __hip_atomic_load(const_cast<unsigned long long*>(keys) + o.kidx, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
   return o;
 }
 // The ray test against the owner's statics, and the atomic for a hit that
@@ -1522,6 +1528,15 @@ __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint
       S.n_items = ni; S.n_large = nl; S.n_rows = nr; S.overflow = cnt->overflow;
       S.max_items_shard = mi; S.max_large_shard = ml; S.rtic = rt; S.pairs = pr;
       S.tests = te;
+      Sticky k = cnt->sticky;
+      if (cnt->overflow) {
+        k.overflow |= cnt->overflow;
+        k.casts += 1u;
+        k.max_items_shard = max(k.max_items_shard, mi);
+        k.max_large_shard = max(k.max_large_shard, ml);
+        cnt->sticky = k;
+      }
+      S.sticky = k;
     }
   }
   // rays 4g .. 4g + 3: 16-byte loads and stores when the outputs allow them

@@ -67,7 +67,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("rays", ctypes.c_uint64), ("pairs_tested", ctypes.c_uint64),
                 ("rect_items", ctypes.c_uint64), ("large_records", ctypes.c_uint64),
                 ("row_items", ctypes.c_uint64), ("rtic", ctypes.c_uint64),
-                ("recasts", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("recasts", ctypes.c_uint32), ("overflowed", ctypes.c_uint32),
                 ("pairs_evaluated", ctypes.c_uint64), ("sphere_tests", ctypes.c_uint64)]
 
 
@@ -121,6 +121,7 @@ def load() -> ctypes.CDLL:
         "grca_workspace_destroy": ([P], None),
         "grca_cast_ws": ([P, P, P, U32, P, P, P], ctypes.c_int),
         "grca_workspace_synchronize": ([P, P, P], ctypes.c_int),
+        "grca_workspace_stats": ([P, P, ctypes.POINTER(Stats)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -139,7 +140,7 @@ def exported_symbols() -> list[str]:
         "grca_frame_launch", "grca_frame_synchronize", "grca_frame_destroy",
         "grca_frame_profile",
         "grca_workspace_create", "grca_workspace_destroy", "grca_cast_ws",
-        "grca_workspace_synchronize",
+        "grca_workspace_synchronize", "grca_workspace_stats",
     ]
 
 
@@ -357,6 +358,12 @@ def grca_cast_ws(ctx, ws, sensor_ids, out_distance_dev, out_tri_dev, stream=None
 
 def grca_workspace_synchronize(ctx, ws, stream=None):
     _check(ctx, load().grca_workspace_synchronize(ctx, ws, _stream(stream)))
+
+
+def grca_workspace_stats(ctx, ws) -> dict:
+    s = Stats()
+    _check(ctx, load().grca_workspace_stats(ctx, ws, ctypes.byref(s)))
+    return {f: int(getattr(s, f)) for f, _ in Stats._fields_}
 
 
 # ---------------------------------------------------------------- object wrapper

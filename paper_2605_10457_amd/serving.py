@@ -13,9 +13,14 @@ multi-scene cast over all their sensors.  Requests that arrive while other
 batches are on the GPU join the next batch as soon as a slot and HBM budget
 free up; batches on different slots overlap on the device.
 
-Admission: a request's transient HBM is its rays x 16 B (key + outputs); a
-batch must fit its slot (max rays) and the global transient budget.  A client
-has at most one request in flight (its scene is re-posed per request).
+Admission: a request's transient HBM is its rays x 16 B (key + outputs) plus
+its share of the slot's work queues: 20 B per queued work item (16 B record +
+4 B candidate start) and 16 B per large-class record, estimated per client
+from a calibration cast of its rig (x 1.25 for pose-to-pose variation).  A
+batch must fit its slot's ray capacity and queue capacity (so that no cast
+overflows and regrows its queues mid-run) and the global transient budget.
+A client has at most one request in flight (its scene is re-posed per
+request).
 
 Latency is measured on the host clock from arrival to outputs ready.
 """
@@ -29,7 +34,10 @@ import numpy as np
 
 from . import grca, synth
 
-BYTES_PER_RAY = 16  # 8 B key + 4 B distance + 4 B triangle id
+BYTES_PER_RAY = 16    # 8 B key + 4 B distance + 4 B triangle id
+BYTES_PER_ITEM = 20   # queued work item: 16 B record + 4 B first-candidate index
+BYTES_PER_LARGE = 16  # large-class (triangle, origin) record
+QUEUE_MARGIN = 1.25   # calibration estimate -> admission estimate
 
 
 @dataclasses.dataclass
@@ -40,6 +48,12 @@ class Client:
     sensor_ids: list
     rays: int
     rate_hz: float
+    items: int = 0   # queued work items of one request (calibration estimate)
+    large: int = 0   # large-class records of one request (calibration estimate)
+
+    def transient_bytes(self) -> int:
+        return (self.rays * BYTES_PER_RAY + self.items * BYTES_PER_ITEM
+                + self.large * BYTES_PER_LARGE)
 
 
 @dataclasses.dataclass(order=True)
@@ -54,30 +68,35 @@ class Request:
     offset: int = dataclasses.field(default=0, compare=False)
 
 
-def plan_batch(queue, client_rays: dict, busy: set, slot_max_rays: int, budget_bytes: int,
-               in_use_bytes: int):
+def plan_batch(queue, need: dict, busy: set, slot_max_rays: int, slot_max_items: int,
+               budget_bytes: int, in_use_bytes: int):
     """Admission for one free slot: oldest requests first, at most one per
     client, skipping clients with a request in flight; a request joins the
-    batch while the batch fits the slot's ray capacity and the transient HBM
-    budget.  Requests that can never fit (larger than a slot or the whole
-    budget) are rejected.  Returns (batch, still_queued, rejected)."""
+    batch while the batch fits the slot's ray and queue capacities and the
+    transient HBM budget.  `need[cid]` = (rays, queue items, transient bytes)
+    of one request of client cid.  Requests that can never fit (larger than a
+    slot or the whole budget) are rejected.  Returns (batch, still_queued,
+    rejected)."""
     batch, keep, rejected = [], [], []
     taken = set()
-    rays = 0
+    rays = items = nbytes = 0
     for r in sorted(queue):
-        need = client_rays[r.cid]
-        if need > slot_max_rays or need * BYTES_PER_RAY > budget_bytes:
+        n_r, n_i, n_b = need[r.cid]
+        if n_r > slot_max_rays or n_i > slot_max_items or n_b > budget_bytes:
             rejected.append(r)
             continue
         if r.cid in busy or r.cid in taken:
             keep.append(r)
             continue
-        if rays + need > slot_max_rays or in_use_bytes + (rays + need) * BYTES_PER_RAY > budget_bytes:
+        if (rays + n_r > slot_max_rays or items + n_i > slot_max_items
+                or in_use_bytes + nbytes + n_b > budget_bytes):
             keep.append(r)
             continue
         batch.append(r)
         taken.add(r.cid)
-        rays += need
+        rays += n_r
+        items += n_i
+        nbytes += n_b
     return batch, keep, rejected
 
 
@@ -89,9 +108,11 @@ class Slot:
         self.dist = torch.empty(max_rays, dtype=torch.float32, device="cuda")
         self.tri = torch.empty(max_rays, dtype=torch.int32, device="cuda")
         self.max_rays = max_rays
+        self.max_items = item_cap
         self.event = None
         self.reqs: list[Request] = []
         self.rays = 0
+        self.nbytes = 0
 
 
 class Server:
@@ -112,10 +133,14 @@ class Server:
         self.admitted = 0
         self.rejected = 0
         self.max_batch = 0
+        self.overflowed = 0
+        self.need = {c.cid: (c.rays, int(math.ceil(c.items * QUEUE_MARGIN)),
+                             int(math.ceil(c.transient_bytes() * QUEUE_MARGIN)))
+                     for c in clients}
 
     # -------------------------------------------------------------- batching
     def _launch(self, slot: Slot, reqs: list[Request], now: float):
-        ids, off = [], 0
+        ids, off, nbytes = [], 0, 0
         for r in reqs:
             c = self.clients[r.cid]
             sc = c.workload.scene
@@ -127,6 +152,7 @@ class Server:
             r.batch = self.batches
             ids.extend(c.sensor_ids)
             off += c.rays
+            nbytes += self.need[r.cid][2]
             self.busy_clients.add(r.cid)
         grca.grca_cast_ws(self.ctx.h, slot.ws, ids, slot.dist, slot.tri, slot.stream)
         ev = self.torch.cuda.Event()
@@ -134,12 +160,14 @@ class Server:
         slot.event = ev
         slot.reqs = reqs
         slot.rays = off
-        self.in_use += off * BYTES_PER_RAY
+        slot.nbytes = nbytes
+        self.in_use += nbytes
         self.batches += 1
         self.max_batch = max(self.max_batch, len(reqs))
 
     def _complete(self, slot: Slot, now: float):
         grca.grca_workspace_synchronize(self.ctx.h, slot.ws, slot.stream)
+        self.overflowed += grca.grca_workspace_stats(self.ctx.h, slot.ws)["overflowed"]
         for r in slot.reqs:
             r.done = now
             self.busy_clients.discard(r.cid)
@@ -148,15 +176,15 @@ class Server:
                 d = slot.dist[r.offset:r.offset + c.rays].cpu().numpy().copy()
                 t = slot.tri[r.offset:r.offset + c.rays].cpu().numpy().view(np.uint32).copy()
                 self.outputs[r.rid] = (d, t)
-        self.in_use -= slot.rays * BYTES_PER_RAY
+        self.in_use -= slot.nbytes
         slot.event = None
         slot.reqs = []
         slot.rays = 0
+        slot.nbytes = 0
 
     def _admit(self, queue: list, slot: Slot) -> list:
-        batch, keep, rejected = plan_batch(queue, {c: x.rays for c, x in self.clients.items()},
-                                           self.busy_clients, slot.max_rays, self.budget,
-                                           self.in_use)
+        batch, keep, rejected = plan_batch(queue, self.need, self.busy_clients, slot.max_rays,
+                                           slot.max_items, self.budget, self.in_use)
         queue[:] = keep
         self.rejected += len(rejected)
         self.admitted += len(batch)
@@ -207,6 +235,7 @@ class Server:
                            "mean": float(lat.mean()) if lat.size else None},
             "rays_per_s": rays / wall, "wall_s": wall,
             "slot_bytes": [s.bytes for s in self.slots],
+            "casts_overflowed": self.overflowed,
         }
 
     def close(self):
@@ -228,10 +257,17 @@ def make_clients(ctx: grca.Context, n_clients: int = 16, tri_scale: float = 1.0,
         next_sensor += len(ids)
         rays = sum(len(s["elevation"]) * s["rays_per_channel"] for s in wl.sensors)
         rng = np.random.default_rng([synth.BASE_SEED + 5 + seed_extra, c, 99])
-        clients.append(Client(c, wl, 1000 + c, ids, rays, float(rng.uniform(10, 20))))
+        cl = Client(c, wl, 1000 + c, ids, rays, float(rng.uniform(10, 20)))
+        # calibration cast: the rig's queue demand at the resident pose
+        ctx.cast_host(ids, rays)
+        st = ctx.last_stats()
+        cl.items = int(st["rect_items"] + st["row_items"])
+        cl.large = int(st["large_records"])
+        clients.append(cl)
         if log:
             log(f"client {c}: {wl.scene.num_triangles} tris ({wl.scene.n_dynamic_tris} dyn), "
-                f"{len(ids)} sensors, {rays} rays, {clients[-1].rate_hz:.1f} Hz")
+                f"{len(ids)} sensors, {rays} rays, {cl.items} queue items, "
+                f"{cl.rate_hz:.1f} Hz")
     return clients
 
 

@@ -576,3 +576,43 @@ def small_random_scene(seed: int, n_tris: int = 64, spread: float = 6.0):
     v = np.concatenate(v).astype(np.float32)
     f = np.arange(v.shape[0], dtype=np.uint32).reshape(-1, 3)
     return v, f
+
+
+def degenerate_scene():
+    """Exact-degenerate inputs for parity tests, on a 10 x 10 m ground grid of
+    1 m cells with a vertex at the origin and no sub-cell offset:
+      * full-sphere sensors (nadir channel at -90 deg) exactly above a grid
+        vertex, above a cell diagonal and above a cell boundary edge;
+      * zero-area triangles: one repeated vertex three times, one with a
+        repeated index, one with collinear vertices;
+      * a vertical triangle whose plane contains the first sensor's origin;
+      * a small wall in front of the first sensor straddling its range_min
+        (0.5 m): the rays near its centre meet it closer than range_min;
+      * an exactly duplicated triangle (same vertices, two ids).
+    Returns (vertices, indices, sensors, (smaller id, larger id) of the duplicate)."""
+    b = _Builder()
+    gv, gf = grid(10, 10, 10.0, 10.0, -5.0, -5.0)
+    b.add(gv, gf)
+    extra = [
+        np.array([[2.0, 1.0, 0.8]] * 3),                              # one point
+        np.array([[2.5, -1.0, 0.5], [2.5, -1.5, 1.5], [2.5, -1.5, 1.5]]),  # repeated vertex
+        np.array([[-2.0, 2.0, 0.3], [-2.0, 3.0, 1.3], [-2.0, 2.5, 0.8]]),  # collinear
+        np.array([[2.0, 0.0, 0.5], [4.0, 0.0, 0.5], [3.0, 0.0, 3.0]]),   # plane y = 0 through o
+        np.array([[0.4, -0.6, 1.0], [0.4, 0.6, 1.0], [0.4, 0.0, 2.1]]),  # straddles range_min
+        np.array([[-3.0, -1.0, 0.2], [-3.0, 1.0, 0.2], [-3.0, 0.0, 2.5]]),  # duplicated wall
+    ]
+    for tri in extra:
+        b.add(tri, np.array([[0, 1, 2]], np.uint32))
+    v, f = b.build()
+    # repeated index: the same stored vertex used twice
+    f[b.nt - 5] = [f[b.nt - 5][0], f[b.nt - 5][1], f[b.nt - 5][1]]
+    dup_v = v[f[b.nt - 1]]
+    v = np.concatenate([v, dup_v]).astype(np.float32)
+    n0 = v.shape[0] - 3
+    f = np.concatenate([f, np.array([[n0, n0 + 1, n0 + 2]], np.uint32)]).astype(np.uint32)
+    dup = (f.shape[0] - 2, f.shape[0] - 1)
+    el = elevations_full_sphere(24)
+    sensors = [sensor([0.0, 0.0, 1.5], 0.0, el, 96, 360.0, range_min=0.5, range_max=30.0),
+               sensor([0.5, 0.5, 1.2], 0.7, el, 96, 360.0, range_max=30.0),
+               sensor([0.5, 0.0, 2.0], -1.1, el, 96, 180.0, range_max=30.0)]
+    return v, f, sensors, dup

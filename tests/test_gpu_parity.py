@@ -305,3 +305,15 @@ def test_more_than_64_sensors_in_one_cast(ctx):
         assert np.array_equal(t[sl], t2), f"sensor {k}: culled != all-pairs"
         assert np.array_equal(d[sl].view(np.uint32), d2.view(np.uint32))
     assert np.count_nonzero(t != grca.GRCA_MISS_TRI) > 5000
+
+
+def test_degenerate_inputs(ctx):
+    _say("degenerate inputs: zero-area, repeated-index and collinear triangles, a plane "
+         "through the emitter, triangles straddling range_min, duplicates, and full-sphere "
+         "sensors exactly above a grid vertex and grid edges (nadir channel)")
+    v, f, sensors, dup = synth.degenerate_scene()
+    for k, s in enumerate(sensors):
+        rep, d, t = _parity(ctx, s, v, f, scene_id=7, sensor_id=40 + k, label=f"degenerate {k}")
+        # exact duplicates have bitwise equal distances: the smaller id must win
+        assert not np.any(t == dup[1]), "the larger id of a duplicated triangle won"
+        print(f"degenerate sensor {k}", rep["counts"], flush=True)
