@@ -160,8 +160,9 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}); this "
-              "build has no multi-GPU path: sensors or triangles would shard across GPUs as "
-              "described in DESIGN.md.", file=sys.stderr)
+              "build has no multi-GPU path. Sensors would shard across GPUs with a scene "
+              "replica each (disjoint outputs, no exchange), or triangles would shard with "
+              "one element-wise 64-bit MIN reduction of the packed keys.", file=sys.stderr)
         sys.exit(2)
 
     import torch

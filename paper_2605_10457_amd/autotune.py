@@ -56,9 +56,9 @@ def tune(ctx, ids, n_rays: int, reps: int = 5, max_rounds: int = 2, log=None) ->
     tri = torch.empty(n_rays, dtype=torch.int32, device="cuda")
     best = {k: ctx.get_options()[k] for k in ORDER}
     ctx.set_options(**best)
-    ref_t = None
     best_ms = time_cast(torch, ctx, ids, dist, tri, reps)
     ref_t = tri.clone()
+    ref_d = dist.view(torch.int32).clone()
     history = [(dict(best), best_ms)]
     for rnd in range(max_rounds):
         changed = False
@@ -69,7 +69,7 @@ def tune(ctx, ids, n_rays: int, reps: int = 5, max_rounds: int = 2, log=None) ->
                 cand = dict(best, **{k: v})
                 ctx.set_options(**cand)
                 ms = time_cast(torch, ctx, ids, dist, tri, reps)
-                if not torch.equal(tri, ref_t):
+                if not (torch.equal(tri, ref_t) and torch.equal(dist.view(torch.int32), ref_d)):
                     raise RuntimeError(f"options {cand} changed the result")
                 history.append((cand, ms))
                 if log:

@@ -30,9 +30,10 @@ constexpr double TWO_PI = 6.283185307179586476925286766559;
 constexpr float TWO_PI_F = 6.28318530717958647692f;
 constexpr float PI_F = 3.14159265358979323846f;
 
-// Conservative margins of the FP32 bounds pass (see the design doc for the error
-// budget): elevation margin in sine units, azimuth margin in radians, and
-// the |sin(elevation)| beyond which the azimuth arc is taken as the full turn.
+// Conservative margins of the FP32 bounds pass, each at least ten times the
+// FP32 error it covers (local frame, bounded atan2, table rounding):
+// elevation margin in sine units, azimuth margin in radians, and the
+// |sin(elevation)| beyond which the azimuth arc is taken as the full turn.
 constexpr float ETA_SIN = 4e-6f;
 constexpr float MARGIN_AZ = 2e-5f;
 constexpr float MARGIN_AZ_POLE = 1e-6f;
