@@ -313,6 +313,39 @@ grca_status grca_workspace_synchronize(grca_context* ctx, grca_workspace* ws, vo
 /* As grca_last_stats for the most recent cast on workspace `ws` (waits for it). */
 grca_status grca_workspace_stats(grca_context* ctx, grca_workspace* ws, grca_stats* out);
 
+/* ---- a cast that allocates nothing ---------------------------------------------- */
+
+/* For callers that cannot allocate device memory: code recorded under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * As grca_cast with device outputs (GRCA_MEM_DEVICE must be set; the
+ * optional flag is GRCA_CULL_BACKFACE), except that every transient buffer
+ * (counters, the cast's sensor and scene descriptors, the per-ray keys and
+ * the work queues) is carved from one static device array of
+ * GRCA_NOALLOC_SCRATCH_BYTES per device, which the library holds from
+ * grca_create until the process ends.  The call allocates nothing (no
+ * hipMalloc, hipFree or host heap) and is asynchronous on hip_stream; the
+ * scene and sensors must have been set up beforehand.
+ * Limits and errors:
+ *  - at most GRCA_NOALLOC_MAX_SENSORS sensors; INVALID_ARG beyond, for host
+ *    outputs, or for GRCA_CAST_ALL_PAIRS;
+ *  - CAPACITY at once when the cast's rays leave too little of the array for
+ *    its work queues (8 bytes per ray of keys plus at least
+ *    GRCA_NOALLOC_MIN_QUEUE_BYTES): the outputs are not written;
+ *  - the work queues get the rest of the array, at most
+ *    grca_options.item_capacity / large_capacity entries.  A queue overflow
+ *    cannot be recast here (that would allocate): grca_synchronize on the
+ *    same stream returns CAPACITY for it, and those outputs are incomplete.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents: calls that overlap on one device (other streams, other
+ * contexts, other threads) race and corrupt each other's results.  Calls
+ * issued one after another on one stream do not overlap. */
+#define GRCA_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define GRCA_NOALLOC_MAX_SENSORS 64u
+#define GRCA_NOALLOC_MIN_QUEUE_BYTES (2u << 20)
+grca_status grca_cast_noalloc(grca_context* ctx, const uint32_t* sensor_ids, uint32_t num_sensors,
+                              float* out_distance_dev, uint32_t* out_tri_dev, uint32_t flags,
+                              void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -181,6 +182,17 @@ struct grca_frame {
   uint32_t lost = 0;       // overflowed launches not recast, not yet reported
 };
 
+constexpr uint32_t MAX_CAST_SENSORS = 4096;
+
+// The plan of one cast: sensors grouped by scene, key offsets in caller order.
+struct Plan {
+  std::vector<DevSensor> sens;
+  std::vector<DevScene> scenes;
+  uint32_t total_tiles = 0;  // bounds tiles (BOUNDS_TILE triangles) over the cast's scenes
+  uint64_t rays = 0;
+  uint64_t pairs = 0;
+};
+
 struct grca_context {
   int device = 0;
   int num_cu = 0;
@@ -192,6 +204,22 @@ struct grca_context {
   std::set<grca_workspace*> workspaces;  // the default one and the caller's
   std::set<grca_frame*> frames;
   std::string err;
+  // the planner's temporaries, reserved at creation for the largest cast
+  // (4096 sensors), so that planning a cast never allocates
+  std::vector<const SensorData*> plan_sd;
+  std::vector<uint64_t> plan_off;
+  std::vector<uint32_t> plan_order;
+  // no-allocation casts: the device address of this device's static scratch
+  // array, the plan (reserved for GRCA_NOALLOC_MAX_SENSORS), the summary of
+  // the last such cast (pinned) and its completion event
+  void* na_scratch = nullptr;
+  Plan* na_plan = nullptr;
+  Summary* na_sum = nullptr;
+  hipEvent_t na_ev = nullptr;
+  bool na_live = false;   // may still be running (scene or sensor changes wait for it)
+  bool na_check = false;  // its summary has not been inspected by grca_synchronize
+  uint32_t na_nids = 0;
+  uint32_t na_ids[GRCA_NOALLOC_MAX_SENSORS] = {};
 };
 
 namespace {
@@ -220,6 +248,15 @@ grca_status fail(const grca_context* ctx, grca_status code, const std::string& m
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Device bytes of one work-queue slot: the item and its first candidate index.
+constexpr uint64_t ITEM_BYTES = sizeof(Item) + sizeof(uint32_t);
+
+void free_items(grca_workspace* ws) {
+  dfree(ws->items);
+  dfree(ws->item_cs);
+  ws->item_cap = 0;
+}
+
 // Grow the workspace buffers.  Only called while no cast is in flight on it.
 grca_status ws_reserve(grca_context* ctx, grca_workspace* ws, uint64_t rays, uint64_t items,
                        uint64_t large, uint32_t nsens, uint32_t nscenes, uint64_t scratch,
@@ -234,9 +271,7 @@ grca_status ws_reserve(grca_context* ctx, grca_workspace* ws, uint64_t rays, uin
   items = (items + NSHARD - 1) / NSHARD * NSHARD;
   large = (large + NSHARD - 1) / NSHARD * NSHARD;
   if (items > ws->item_cap) {
-    dfree(ws->items);
-    dfree(ws->item_cs);
-    ws->item_cap = 0;
+    free_items(ws);
     HIPCHK(dmalloc(&ws->items, items));
     HIPCHK(dmalloc(&ws->item_cs, items));
     ws->item_cap = items;
@@ -281,8 +316,7 @@ grca_status ws_reserve(grca_context* ctx, grca_workspace* ws, uint64_t rays, uin
     HIPCHK(dmalloc(&ws->out_tri, outs));
     ws->out_cap = outs;
   }
-  ws->bytes = ws->key_cap * 8 + (ws->item_cap + ws->large_cap) * sizeof(Item) +
-              ws->item_cap * sizeof(uint32_t) +
+  ws->bytes = ws->key_cap * 8 + ws->item_cap * ITEM_BYTES + ws->large_cap * sizeof(Item) +
               (uint64_t)RING * (ws->sens_cap * sizeof(DevSensor) + ws->scene_cap * sizeof(DevScene)) +
               ws->scratch_cap * sizeof(Statics) + ws->out_cap * 8 + sizeof(Counters);
   return GRCA_OK;
@@ -302,7 +336,7 @@ void ws_free(grca_workspace* ws) {
   if (!ws) return;
   for (int i = 0; i < RING; ++i)
     if (ws->ev[i]) (void)hipEventSynchronize(ws->ev[i]);
-  dfree(ws->keys); dfree(ws->items); dfree(ws->item_cs); dfree(ws->large); dfree(ws->cnt);
+  dfree(ws->keys); free_items(ws); dfree(ws->large); dfree(ws->cnt);
   dfree(ws->dsens); dfree(ws->dscenes); dfree(ws->scratch);
   dfree(ws->out_dist); dfree(ws->out_tri);
   if (ws->cnt_host) (void)hipHostFree(ws->cnt_host);
@@ -313,14 +347,6 @@ void ws_free(grca_workspace* ws) {
   delete ws;
 }
 
-// The plan of one cast: sensors grouped by scene, key offsets in caller order.
-struct Plan {
-  std::vector<DevSensor> sens;
-  std::vector<DevScene> scenes;
-  uint32_t total_tiles = 0;  // bounds tiles (BOUNDS_TILE triangles) over the cast's scenes
-  uint64_t rays = 0;
-  uint64_t pairs = 0;
-};
 
 // A sensor's device record, without the per-cast fields (output offset,
 // scene slot, single-sided flag).
@@ -361,12 +387,16 @@ DevSensor sensor_record(const SensorData& S) {
   return d;
 }
 
+// Allocates nothing when P's vectors already hold n sensors and n scenes
+// (the context's temporaries are reserved for the largest cast).
 grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32_t block,
                       Plan& P, uint32_t flags = 0) {
   if (n == 0) return fail(ctx, GRCA_ERR_INVALID_ARG, "num_sensors must be >= 1");
-  if (n > 4096) return fail(ctx, GRCA_ERR_INVALID_ARG, "at most 4096 sensors per cast");
-  std::vector<const SensorData*> sd(n);
-  std::vector<uint64_t> offs(n);
+  if (n > MAX_CAST_SENSORS) return fail(ctx, GRCA_ERR_INVALID_ARG, "at most 4096 sensors per cast");
+  std::vector<const SensorData*>& sd = ctx->plan_sd;
+  std::vector<uint64_t>& offs = ctx->plan_off;
+  sd.resize(n);
+  offs.resize(n);
   uint64_t off = 0;
   for (uint32_t i = 0; i < n; ++i) {
     auto it = ctx->sensors.find(ids[i]);
@@ -382,10 +412,14 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
   }
   if (off >= (1ull << 32)) return fail(ctx, GRCA_ERR_INVALID_ARG, "more than 2^32 rays in one cast");
   P.rays = off;
-  std::vector<uint32_t> order(n);
+  P.pairs = 0;
+  std::vector<uint32_t>& order = ctx->plan_order;
+  order.resize(n);
   for (uint32_t i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-    return sd[a]->desc.scene_id < sd[b]->desc.scene_id;
+  // grouped by scene, in call order within a scene (std::sort works in place)
+  std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+    const uint32_t sa = sd[a]->desc.scene_id, sb = sd[b]->desc.scene_id;
+    return sa != sb ? sa < sb : a < b;
   });
   P.sens.resize(n);
   P.scenes.clear();
@@ -433,11 +467,70 @@ uint32_t persist_blocks(const grca_context* ctx) {
   return std::max(1u, waves / 4u);
 }
 
+// The device buffers one cast's kernels use.  Queues are NSHARD regions of
+// icap (items and their candidate starts) and lcap (large records) entries.
+struct CastBufs {
+  const DevSensor* dsens;
+  const DevScene* dscenes;
+  unsigned long long* keys;
+  Item* items;
+  uint32_t* item_cs;
+  uint32_t icap;
+  Item* large;
+  uint32_t lcap;
+  Counters* cnt;
+  Statics* statics;  // all-pairs only: one per triangle of the largest scene
+};
+
+// The kernel sequence of one cast: key init, then bounds + binning,
+// expansion and intersection (or the all-pairs reference), then resolve.
+// With `ev` (culled casts), events ev[0..4] are recorded after init, bounds,
+// expansion, intersection and resolve.
+grca_status launch_cast(grca_context* ctx, const Plan& P, const CastBufs& B, float* dist,
+                        uint32_t* tri, uint32_t flags, hipStream_t st,
+                        hipEvent_t* ev = nullptr) {
+  const grca_options& o = ctx->opt;
+  const uint32_t n = (uint32_t)P.rays;
+  HIPCHK(launch_init(B.keys, n, B.cnt, st));
+  if (ev) HIPCHK(hipEventRecord(ev[0], st));
+  if (flags & GRCA_CAST_ALL_PAIRS) {
+    for (uint32_t k = 0; k < P.sens.size(); ++k) {
+      const DevSensor& d = P.sens[k];
+      HIPCHK(launch_allpairs(B.dscenes, B.dsens, k, P.scenes[d.scene].ntri, d.gamma * d.chi,
+                             B.statics, B.keys, st));
+    }
+  } else {
+    HIPCHK(launch_bounds(B.dscenes, (uint32_t)P.scenes.size(), P.total_tiles, o.bounds_block,
+                         B.dsens, o.small_channels, o.small_rays, B.items, B.item_cs, B.icap,
+                         B.large, B.lcap, B.cnt, o.group_cull, o.inline_max, B.keys, st));
+    if (ev) HIPCHK(hipEventRecord(ev[1], st));
+    const uint32_t pb = persist_blocks(ctx);
+    HIPCHK(launch_expand(B.dscenes, B.dsens, B.large, B.items, B.item_cs, B.icap, B.lcap,
+                         o.row_chunk, B.cnt, pb, st));
+    if (ev) HIPCHK(hipEventRecord(ev[2], st));
+    HIPCHK(launch_isect(B.dscenes, B.dsens, (uint32_t)P.sens.size(), B.items, B.item_cs, B.icap,
+                        o.isect_ticket, B.cnt, B.keys, pb, st));
+    if (ev) HIPCHK(hipEventRecord(ev[3], st));
+  }
+  HIPCHK(launch_resolve(B.keys, n, dist, tri, B.cnt, st));
+  if (ev) HIPCHK(hipEventRecord(ev[4], st));
+  return GRCA_OK;
+}
+
+// The buffers of workspace `ws` for a cast whose descriptors are in ring
+// slot `slot`.
+CastBufs ws_bufs(grca_workspace* ws, uint32_t slot) {
+  return CastBufs{ws->dsens + (size_t)slot * ws->sens_cap,
+                  ws->dscenes + (size_t)slot * ws->scene_cap,
+                  ws->keys, ws->items, ws->item_cs,
+                  (uint32_t)(ws->item_cap / NSHARD), ws->large,
+                  (uint32_t)(ws->large_cap / NSHARD), ws->cnt, ws->scratch};
+}
+
 // Enqueue the kernels of one cast into ring slot `slot` (the slot is free and
 // the workspace buffers are large enough).
 grca_status enqueue_kernels(grca_context* ctx, grca_workspace* ws, uint32_t slot, const Plan& P,
                             float* dist, uint32_t* tri, uint32_t flags, hipStream_t st) {
-  const grca_options& o = ctx->opt;
   DevSensor* dsens = ws->dsens + (size_t)slot * ws->sens_cap;
   DevScene* dscenes = ws->dscenes + (size_t)slot * ws->scene_cap;
   std::memcpy(ws->dsens_host + (size_t)slot * ws->sens_cap, P.sens.data(),
@@ -448,27 +541,8 @@ grca_status enqueue_kernels(grca_context* ctx, grca_workspace* ws, uint32_t slot
                         P.sens.size() * sizeof(DevSensor), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(dscenes, ws->dscenes_host + (size_t)slot * ws->scene_cap,
                         P.scenes.size() * sizeof(DevScene), hipMemcpyHostToDevice, st));
-  const uint32_t n = (uint32_t)P.rays;
-  const uint32_t icap = (uint32_t)(ws->item_cap / NSHARD);  // per shard
-  const uint32_t lcap = (uint32_t)(ws->large_cap / NSHARD);
-  HIPCHK(launch_init(ws->keys, n, ws->cnt, st));
-  if (flags & GRCA_CAST_ALL_PAIRS) {
-    for (uint32_t k = 0; k < P.sens.size(); ++k) {
-      const DevSensor& d = P.sens[k];
-      HIPCHK(launch_allpairs(dscenes, dsens, k, P.scenes[d.scene].ntri, d.gamma * d.chi,
-                             ws->scratch, ws->keys, st));
-    }
-  } else {
-    HIPCHK(launch_bounds(dscenes, (uint32_t)P.scenes.size(), P.total_tiles, o.bounds_block,
-                         dsens, o.small_channels, o.small_rays, ws->items, ws->item_cs, icap,
-                         ws->large, lcap, ws->cnt, o.group_cull, o.inline_max, ws->keys, st));
-    const uint32_t pb = persist_blocks(ctx);
-    HIPCHK(launch_expand(dscenes, dsens, ws->large, ws->items, ws->item_cs, icap, lcap,
-                         o.row_chunk, ws->cnt, pb, st));
-    HIPCHK(launch_isect(dscenes, dsens, (uint32_t)P.sens.size(), ws->items, ws->item_cs, icap,
-                        o.isect_ticket, ws->cnt, ws->keys, pb, st));
-  }
-  HIPCHK(launch_resolve(ws->keys, n, dist, tri, ws->cnt, st));
+  const grca_status rc = launch_cast(ctx, P, ws_bufs(ws, slot), dist, tri, flags, st);
+  if (rc != GRCA_OK) return rc;
   HIPCHK(hipMemcpyAsync(ws->cnt_host + slot, &ws->cnt->sum, sizeof(Summary),
                         hipMemcpyDeviceToHost, st));
   HIPCHK(hipEventRecord(ws->ev[slot], st));
@@ -519,7 +593,7 @@ grca_status ws_drain(grca_context* ctx, grca_workspace* ws) {
       uint64_t items = ws->item_cap, large = ws->large_cap;
       rc = grown_caps(ctx, ws->cnt_host[slot], items, large);
       if (rc != GRCA_OK) { R.live = false; return rc; }
-      dfree(ws->items); dfree(ws->item_cs); ws->item_cap = 0;
+      free_items(ws);
       dfree(ws->large); ws->large_cap = 0;
       rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
       if (rc != GRCA_OK) { R.live = false; return rc; }
@@ -553,6 +627,39 @@ grca_status settle_users(grca_context* ctx, int64_t scene_id, int64_t sensor_id,
 }  // namespace
 
 // =============================================================== context
+namespace {
+// Device address of each device's no-allocation scratch array, looked up
+// once per device (with that device current) by the first context on it.
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// Set-up of the no-allocation cast (the device is current): the scratch
+// array's device address, the planner's reserved temporaries, the pinned
+// summary and the completion event.
+grca_status noalloc_init(grca_context* ctx) {
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    void* p = ctx->device < 64 ? g_scratch_ptr[ctx->device] : nullptr;
+    if (!p) {
+      HIPCHK(noalloc_scratch_address(&p));
+      if (!p) return fail(ctx, GRCA_ERR_DEVICE, "no device address for the scratch array");
+      if (ctx->device < 64) g_scratch_ptr[ctx->device] = p;
+    }
+    ctx->na_scratch = p;
+  }
+  ctx->plan_sd.reserve(MAX_CAST_SENSORS);
+  ctx->plan_off.reserve(MAX_CAST_SENSORS);
+  ctx->plan_order.reserve(MAX_CAST_SENSORS);
+  ctx->na_plan = new Plan();
+  ctx->na_plan->sens.reserve(GRCA_NOALLOC_MAX_SENSORS);
+  ctx->na_plan->scenes.reserve(GRCA_NOALLOC_MAX_SENSORS);
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&ctx->na_sum), sizeof(Summary)));
+  std::memset(ctx->na_sum, 0, sizeof(Summary));
+  HIPCHK(hipEventCreateWithFlags(&ctx->na_ev, hipEventDisableTiming));
+  return GRCA_OK;
+}
+}  // namespace
+
 extern "C" grca_status grca_create(int hip_device, grca_context** out) {
   grca_context* ctx = nullptr;
   if (!out) return GRCA_ERR_INVALID_ARG;
@@ -584,9 +691,8 @@ extern "C" grca_status grca_create(int hip_device, grca_context** out) {
   ctx->opt.item_capacity = 1u << 20;
   ctx->opt.large_capacity = 1u << 16;
   ctx->def_ws = new grca_workspace();
-  if (ws_init(ctx, ctx->def_ws) != GRCA_OK) {
-    ws_free(ctx->def_ws);
-    delete ctx;
+  if (ws_init(ctx, ctx->def_ws) != GRCA_OK || noalloc_init(ctx) != GRCA_OK) {
+    grca_destroy(ctx);
     return GRCA_ERR_DEVICE;
   }
   ctx->workspaces.insert(ctx->def_ws);
@@ -601,6 +707,9 @@ extern "C" void grca_destroy(grca_context* ctx) {
   ws_free(ctx->def_ws);
   for (auto& kv : ctx->scenes) free_scene(kv.second);
   for (auto& kv : ctx->sensors) free_sensor(kv.second);
+  if (ctx->na_sum) (void)hipHostFree(ctx->na_sum);
+  if (ctx->na_ev) (void)hipEventDestroy(ctx->na_ev);
+  delete ctx->na_plan;
   delete ctx;
 }
 
@@ -1208,6 +1317,81 @@ extern "C" grca_status grca_synchronize(grca_context* ctx, void* hip_stream) {
     grca_status rc = ws_drain(ctx, ctx->def_ws);
     if (rc != GRCA_OK) return rc;
     HIPCHK(hipStreamSynchronize(as_stream(hip_stream)));
+    if (ctx->na_check) {
+      // the last no-allocation cast: its queues could not grow
+      HIPCHK(hipEventSynchronize(ctx->na_ev));
+      ctx->na_live = false;
+      ctx->na_check = false;
+      if (ctx->na_sum->overflow)
+        return fail(ctx, GRCA_ERR_CAPACITY,
+                    "a no-allocation cast overflowed its fixed work queues (its outputs are "
+                    "incomplete); cast it with grca_cast, or with fewer rays");
+    }
+    return GRCA_OK;
+  })
+}
+
+extern "C" grca_status grca_cast_noalloc(grca_context* ctx, const uint32_t* sensor_ids,
+                                         uint32_t num_sensors, float* out_distance_dev,
+                                         uint32_t* out_tri_dev, uint32_t flags,
+                                         void* hip_stream) {
+  if (!ctx) return GRCA_ERR_INVALID_ARG;
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!ctx->na_scratch) return fail(ctx, GRCA_ERR_DEVICE, "no-allocation scratch not set up");
+    if (!(flags & GRCA_MEM_DEVICE))
+      return fail(ctx, GRCA_ERR_INVALID_ARG, "grca_cast_noalloc writes device outputs only");
+    if (flags & ~(GRCA_MEM_DEVICE | GRCA_CULL_BACKFACE))
+      return fail(ctx, GRCA_ERR_INVALID_ARG,
+                  "grca_cast_noalloc accepts GRCA_MEM_DEVICE and GRCA_CULL_BACKFACE only");
+    if (num_sensors > GRCA_NOALLOC_MAX_SENSORS)
+      return fail(ctx, GRCA_ERR_INVALID_ARG, "grca_cast_noalloc takes at most 64 sensors");
+    if (num_sensors && !sensor_ids) return fail(ctx, GRCA_ERR_INVALID_ARG, "NULL sensor id list");
+    Plan& P = *ctx->na_plan;
+    grca_status rc = make_plan(ctx, sensor_ids, num_sensors, ctx->opt.bounds_block, P, flags);
+    if (rc != GRCA_OK) return rc;
+    // carve the scratch array: counters, descriptors, keys, then the queues
+    const size_t total = GRCA_NOALLOC_SCRATCH_BYTES;
+    unsigned char* const base = static_cast<unsigned char*>(ctx->na_scratch);
+    size_t used = 0;
+    auto take = [&](size_t bytes) {
+      unsigned char* p = base + used;
+      used += (bytes + 255u) & ~(size_t)255u;
+      return p;
+    };
+    Counters* cnt = reinterpret_cast<Counters*>(take(sizeof(Counters)));
+    DevSensor* dsens = reinterpret_cast<DevSensor*>(take(sizeof(DevSensor) * GRCA_NOALLOC_MAX_SENSORS));
+    DevScene* dscenes = reinterpret_cast<DevScene*>(take(sizeof(DevScene) * GRCA_NOALLOC_MAX_SENSORS));
+    const size_t key_bytes = ((size_t)P.rays * 8u + 255u) & ~(size_t)255u;
+    if (used + key_bytes + GRCA_NOALLOC_MIN_QUEUE_BYTES > total)
+      return fail(ctx, GRCA_ERR_CAPACITY,
+                  "grca_cast_noalloc: " + std::to_string(P.rays) +
+                      " rays leave too little of the 64 MiB scratch array for the work queues");
+    unsigned long long* keys = reinterpret_cast<unsigned long long*>(take(key_bytes));
+    // an eighth of the rest for large records, the remainder for items and
+    // their candidate starts; both within the options' capacities
+    uint64_t lcap = std::min<uint64_t>(ctx->opt.large_capacity, (total - used) / 8u / sizeof(Item));
+    lcap = std::max<uint64_t>(lcap / NSHARD, 1u) * NSHARD;
+    Item* large = reinterpret_cast<Item*>(take(lcap * sizeof(Item)));
+    uint64_t icap = std::min<uint64_t>(ctx->opt.item_capacity, (total - used - 768u) / ITEM_BYTES);
+    icap = std::max<uint64_t>(icap / NSHARD, 1u) * NSHARD;
+    Item* items = reinterpret_cast<Item*>(take(icap * sizeof(Item)));
+    uint32_t* item_cs = reinterpret_cast<uint32_t*>(take(icap * sizeof(uint32_t)));
+    if (used > total) return fail(ctx, GRCA_ERR_CAPACITY, "grca_cast_noalloc: scratch layout");
+    hipStream_t st = as_stream(hip_stream);
+    // the cast's descriptors travel in kernel arguments (no host staging)
+    HIPCHK(launch_put(dsens, P.sens.data(), P.sens.size() * sizeof(DevSensor), st));
+    HIPCHK(launch_put(dscenes, P.scenes.data(), P.scenes.size() * sizeof(DevScene), st));
+    const CastBufs B{dsens, dscenes, keys, items, item_cs, (uint32_t)(icap / NSHARD),
+                     large, (uint32_t)(lcap / NSHARD), cnt, nullptr};
+    rc = launch_cast(ctx, P, B, out_distance_dev, out_tri_dev, flags, st);
+    if (rc != GRCA_OK) return rc;
+    HIPCHK(hipMemcpyAsync(ctx->na_sum, &cnt->sum, sizeof(Summary), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(ctx->na_ev, st));
+    ctx->na_live = true;
+    ctx->na_check = true;
+    ctx->na_nids = num_sensors;
+    std::copy(sensor_ids, sensor_ids + num_sensors, ctx->na_ids);
     return GRCA_OK;
   })
 }
@@ -1350,31 +1534,16 @@ grca_status enqueue_frame(grca_context* ctx, grca_frame* fr, const Plan& P, hipS
                           hipEvent_t* ev) {
   SceneData& sc = ctx->scenes.at(fr->scene_id);
   grca_workspace* ws = fr->ws;
-  const grca_options& o = ctx->opt;
-  const uint32_t n = (uint32_t)P.rays;
-  const uint32_t icap = (uint32_t)(ws->item_cap / NSHARD);  // per shard
-  const uint32_t lcap = (uint32_t)(ws->large_cap / NSHARD);
-  const uint32_t pb = persist_blocks(ctx);
   if (ev) HIPCHK(hipEventRecord(ev[0], st));
   if (sc.pose_in) {
     grca_status rc = enqueue_pose_kernels(ctx, sc, st);
     if (rc != GRCA_OK) return rc;
   }
   if (ev) HIPCHK(hipEventRecord(ev[1], st));
-  HIPCHK(launch_init(ws->keys, n, ws->cnt, st));
-  if (ev) HIPCHK(hipEventRecord(ev[2], st));
-  HIPCHK(launch_bounds(ws->dscenes, (uint32_t)P.scenes.size(), P.total_tiles, o.bounds_block,
-                       ws->dsens, o.small_channels, o.small_rays, ws->items, ws->item_cs, icap,
-                       ws->large, lcap, ws->cnt, o.group_cull, o.inline_max, ws->keys, st));
-  if (ev) HIPCHK(hipEventRecord(ev[3], st));
-  HIPCHK(launch_expand(ws->dscenes, ws->dsens, ws->large, ws->items, ws->item_cs, icap, lcap,
-                       o.row_chunk, ws->cnt, pb, st));
-  if (ev) HIPCHK(hipEventRecord(ev[4], st));
-  HIPCHK(launch_isect(ws->dscenes, ws->dsens, (uint32_t)P.sens.size(), ws->items, ws->item_cs,
-                      icap, o.isect_ticket, ws->cnt, ws->keys, pb, st));
-  if (ev) HIPCHK(hipEventRecord(ev[5], st));
-  HIPCHK(launch_resolve(ws->keys, n, fr->out_dist, fr->out_tri, ws->cnt, st));
-  if (ev) HIPCHK(hipEventRecord(ev[6], st));
+  // the frame's tables live in ring slot 0
+  const grca_status rc = launch_cast(ctx, P, ws_bufs(ws, 0), fr->out_dist, fr->out_tri,
+                                     GRCA_MEM_DEVICE, st, ev ? ev + 2 : nullptr);
+  if (rc != GRCA_OK) return rc;
   HIPCHK(hipMemcpyAsync(ws->cnt_host, &ws->cnt->sum, sizeof(Summary), hipMemcpyDeviceToHost, st));
   return GRCA_OK;
 }
@@ -1469,7 +1638,7 @@ grca_status frame_settle(grca_context* ctx, grca_frame* fr, hipStream_t st) {
     uint64_t items = ws->item_cap, large = ws->large_cap;
     grca_status rc = grown_caps(ctx, want, items, large);
     if (rc != GRCA_OK) { R.live = false; return rc; }
-    dfree(ws->items); dfree(ws->item_cs); ws->item_cap = 0;
+    free_items(ws);
     dfree(ws->large); ws->large_cap = 0;
     rc = ws_reserve(ctx, ws, 0, items, large, 0, 0, 0, 0);
     if (rc != GRCA_OK) { R.live = false; return rc; }
@@ -1516,6 +1685,13 @@ grca_status settle_users(grca_context* ctx, int64_t scene_id, int64_t sensor_id,
     if (!busy) continue;
     const grca_status rc = ws_drain(ctx, ws);
     if (rc != GRCA_OK) return rc;
+  }
+  if (ctx->na_live) {
+    const std::vector<uint32_t> na(ctx->na_ids, ctx->na_ids + ctx->na_nids);
+    if (reads(na)) {
+      HIPCHK(hipEventSynchronize(ctx->na_ev));
+      ctx->na_live = false;
+    }
   }
   for (grca_frame* fr : ctx->frames) {
     if ((int64_t)fr->scene_id != scene_id && !reads(fr->ids)) continue;

@@ -1735,14 +1735,14 @@ hipError_t launch_isect(const DevScene* scenes, const DevSensor* sens, uint32_t 
 }
 
 hipError_t launch_allpairs(const DevScene* scenes, const DevSensor* sens, uint32_t sensor,
-                           uint32_t ntri, uint32_t nrays, Statics* scratch,
+                           uint32_t ntri, uint32_t nrays, Statics* statics,
                            unsigned long long* keys, hipStream_t st) {
   if (ntri == 0 || nrays == 0) return hipSuccess;
   hipLaunchKernelGGL(statics_kernel, dim3(cdiv(ntri, 256)), dim3(256), 0, st, scenes, sens,
-                     sensor, scratch);
+                     sensor, statics);
   const uint32_t chunk = 4096;
   hipLaunchKernelGGL(allpairs_kernel, dim3(cdiv(nrays, 256), cdiv(ntri, chunk)), dim3(256), 0,
-                     st, sens, sensor, scratch, ntri, chunk, keys);
+                     st, sens, sensor, statics, ntri, chunk, keys);
   return hipGetLastError();
 }
 
@@ -1802,6 +1802,51 @@ hipError_t launch_copy(const float* src, float* dst, uint32_t n, hipStream_t st)
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(copy_range_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------ no-allocation casts
+// Work memory of the no-allocation cast: counters, the cast's sensor and
+// scene descriptors, the keys and the work queues, carved by the host from
+// this one array.  Each device the library runs on holds its own copy for
+// the life of the process.  Host code must not pass the array's name to a
+// kernel (on the host it names a stand-in, not device memory): it uses the
+// device address that noalloc_scratch_address returns.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch_address(void** out) {
+  return hipGetSymbolAddress(out, HIP_SYMBOL(scratch));
+}
+
+// Copies a small host record into device memory through the kernel's
+// arguments: nothing is staged in host memory that a later call could
+// overwrite before the copy runs, and nothing is allocated.
+struct PutBlob {
+  uint32_t words;
+  uint32_t w[PUT_BLOB_WORDS];
+};
+static_assert(sizeof(PutBlob) <= 4096, "kernel arguments are limited to 4 KiB");
+
+__global__ void put_kernel(uint32_t* __restrict__ dst, PutBlob b) {
+  for (uint32_t i = threadIdx.x; i < b.words; i += blockDim.x) dst[i] = b.w[i];
+}
+
+hipError_t launch_put(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes % 4u != 0u || reinterpret_cast<uintptr_t>(dst) % 4u != 0u) return hipErrorInvalidValue;
+  const uint32_t* s = static_cast<const uint32_t*>(src);
+  uint32_t* d = static_cast<uint32_t*>(dst);
+  size_t left = bytes / 4u;
+  while (left) {
+    PutBlob b;
+    b.words = (uint32_t)std::min<size_t>(left, PUT_BLOB_WORDS);
+    for (uint32_t i = 0; i < b.words; ++i) b.w[i] = s[i];
+    hipLaunchKernelGGL(put_kernel, dim3(1), dim3(256), 0, st, d, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    s += b.words;
+    d += b.words;
+    left -= b.words;
+  }
+  return hipSuccess;
 }
 
 }  // namespace grca

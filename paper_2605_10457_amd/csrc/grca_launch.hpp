@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "grca.h"
 #include "grca_device.hpp"
 
 namespace grca {
@@ -69,6 +70,16 @@ hipError_t order_triangles(uint32_t* idx, uint32_t* orig, uint32_t ntri, const f
                            const float* y, const float* z, uint32_t nv, const uint32_t* vgroup,
                            hipStream_t st);
 hipError_t launch_iota(uint32_t* a, uint32_t n, hipStream_t st);
+
+// The no-allocation cast's work memory: a static device array of
+// NOALLOC_SCRATCH_BYTES, one per device.  noalloc_scratch_address gives its
+// device address on the current device (call it once per device, with that
+// device current); launch_put copies a small host record (a multiple of 4
+// bytes) to device memory through kernel arguments, allocating nothing.
+constexpr size_t NOALLOC_SCRATCH_BYTES = GRCA_NOALLOC_SCRATCH_BYTES;
+constexpr uint32_t PUT_BLOB_WORDS = 1000;
+hipError_t noalloc_scratch_address(void** out);
+hipError_t launch_put(void* dst, const void* src, size_t bytes, hipStream_t st);
 hipError_t launch_fill(uint32_t* a, uint32_t n, uint32_t v, hipStream_t st);
 
 }  // namespace grca

@@ -30,6 +30,9 @@ GRCA_MEM_DEVICE = 1
 GRCA_UPDATE_VERTICES_ONLY = 2
 GRCA_CULL_BACKFACE = 4
 GRCA_CAST_ALL_PAIRS = 8
+GRCA_NOALLOC_SCRATCH_BYTES = 64 << 20
+GRCA_NOALLOC_MAX_SENSORS = 64
+GRCA_NOALLOC_MIN_QUEUE_BYTES = 2 << 20
 
 _STATUS = {1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "CAPACITY", 5: "NOT_FOUND"}
 
@@ -122,6 +125,7 @@ def load() -> ctypes.CDLL:
         "grca_cast_ws": ([P, P, P, U32, P, P, P], ctypes.c_int),
         "grca_workspace_synchronize": ([P, P, P], ctypes.c_int),
         "grca_workspace_stats": ([P, P, ctypes.POINTER(Stats)], ctypes.c_int),
+        "grca_cast_noalloc": ([P, P, U32, P, P, U32, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -140,7 +144,7 @@ def exported_symbols() -> list[str]:
         "grca_frame_launch", "grca_frame_synchronize", "grca_frame_destroy",
         "grca_frame_profile",
         "grca_workspace_create", "grca_workspace_destroy", "grca_cast_ws",
-        "grca_workspace_synchronize", "grca_workspace_stats",
+        "grca_workspace_synchronize", "grca_workspace_stats", "grca_cast_noalloc",
     ]
 
 
@@ -277,6 +281,14 @@ def grca_cast(ctx, sensor_ids, out_distance, out_tri, flags=0, stream=None):
         flags |= GRCA_MEM_DEVICE
     _check(ctx, load().grca_cast(ctx, _ptr(ids), ids.shape[0], _ptr(out_distance), _ptr(out_tri),
                                  flags, _stream(stream)))
+
+
+def grca_cast_noalloc(ctx, sensor_ids, out_distance, out_tri, flags=0, stream=None):
+    """grca_cast into device outputs with no allocation (fixed static scratch)."""
+    ids = np.ascontiguousarray(sensor_ids, np.uint32).reshape(-1)
+    _check(ctx, load().grca_cast_noalloc(ctx, _ptr(ids), ids.shape[0], _ptr(out_distance),
+                                         _ptr(out_tri), flags | GRCA_MEM_DEVICE,
+                                         _stream(stream)))
 
 
 def grca_synchronize(ctx, stream=None):
@@ -416,6 +428,9 @@ class Context:
         t = np.empty(n_rays, np.uint32)
         grca_cast(self.h, sensor_ids, d, t, flags)
         return d, t
+
+    def cast_noalloc(self, sensor_ids, out_distance=None, out_tri=None, flags=0, stream=None):
+        grca_cast_noalloc(self.h, sensor_ids, out_distance, out_tri, flags, stream)
 
     def synchronize(self, stream=None):
         grca_synchronize(self.h, stream)
