@@ -80,6 +80,8 @@ typedef struct {
   uint32_t flags; /* bit 0: single-sided (cull back faces) */
   const float* azimuth_offset_rad; /* optional, chi values: theta*_R = theta_R + offset_R */
   const uint8_t* ray_mask;         /* optional, gamma*chi values: 0 = ray switched off  */
+  const float* channel_elevation_offset_rad; /* optional, gamma values: phi*_C = phi_C +
+                                                offset_C (per-channel vertical noise)     */
 } oracle_sensor;
 
 /* ---- small vector helpers (FP64) ---------------------------------------- */
@@ -109,7 +111,9 @@ void oracle_ray_direction(const oracle_sensor* s, uint32_t C, uint32_t R, double
   double theta = ((double)R - floor(chi / 2.0)) * dtheta;
   /* angular noise (appendix "Ray Noise Simulation"): a pre-stored perturbed azimuth */
   if (s->azimuth_offset_rad) theta += (double)s->azimuth_offset_rad[R];
-  const double phi = (double)s->channel_elevation_rad[C];
+  double phi = (double)s->channel_elevation_rad[C];
+  /* per-channel vertical noise (same appendix): a pre-stored perturbed elevation */
+  if (s->channel_elevation_offset_rad) phi += (double)s->channel_elevation_offset_rad[C];
   const double ct = cos(theta), st = sin(theta), cp = cos(phi), sp = sin(phi);
   for (int k = 0; k < 3; ++k)
     d[k] = ct * cp * (double)s->forward[k] + st * cp * (double)s->right[k] +

@@ -54,6 +54,7 @@ class OracleSensor(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("azimuth_offset_rad", ctypes.POINTER(ctypes.c_float)),
         ("ray_mask", ctypes.POINTER(ctypes.c_uint8)),
+        ("channel_elevation_offset_rad", ctypes.POINTER(ctypes.c_float)),
     ]
 
 
@@ -115,6 +116,11 @@ class _Sensor:
         if sensor.get("ray_mask") is not None:
             self.mask = np.ascontiguousarray(sensor["ray_mask"], np.uint8).reshape(-1)
             s.ray_mask = self.mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        self.el_off = None
+        if sensor.get("elevation_offset") is not None:
+            self.el_off = _f32(sensor["elevation_offset"])
+            s.channel_elevation_offset_rad = self.el_off.ctypes.data_as(
+                ctypes.POINTER(ctypes.c_float))
         self.s = s
 
     @property

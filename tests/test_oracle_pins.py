@@ -358,6 +358,48 @@ def test_constant_azimuth_offset_equals_yawed_sensor():
         assert np.allclose(da, db, atol=1e-7)
 
 
+def test_elevation_offsets_on_a_ground_plane():
+    """Per-channel elevation offsets (vertical noise) large enough for
+    neighbouring channels to swap order: every ray meets the ground z = 0 at
+    t = h / -sin(phi_C + offset_C) (up to the normalisation of the FP32
+    basis), in the cell that plane geometry gives."""
+    v, f, g = _ground_scene()
+    h = 1.8
+    elev = synth.elevations_uniform(-40, -5, 10)
+    step = float(elev[1] - elev[0])
+    off = (0.8 * step * np.where(np.arange(10) % 2 == 0, 1.0, -1.0)).astype(np.float32)
+    s = dict(_sensor(origin=(0.3, -0.2, h), yaw=0.4, elev=elev, rays=48, rmax=60.0),
+             elevation_offset=off)
+    pert = elev.astype(np.float64) + off.astype(np.float64)
+    assert np.any(np.diff(pert) < 0)  # the perturbed table is not ascending
+    out = O.cast(s, v, f)
+    chi = 48
+    checked = 0
+    for gidx in range(10 * chi):
+        C, R = divmod(gidx, chi)
+        ph = float(pert[C])
+        th = (R - chi // 2) * (float(s["fov"]) / chi)
+        d = (math.cos(th) * math.cos(ph) * s["forward"].astype(np.float64)
+             + math.sin(th) * math.cos(ph) * s["right"].astype(np.float64)
+             + math.sin(ph) * s["up"].astype(np.float64))
+        d /= np.linalg.norm(d)
+        ox, oy, oz = (float(c) for c in s["origin"])
+        t = oz / -d[2]  # = h |d| / -sin(phi*) for the basis as stored (FP32)
+        x, y = ox + t * d[0], oy + t * d[1]
+        k, near = _ground_cell(g, x, y)
+        t_o, k_o = out["t"][gidx], int(out["tri"][gidx])
+        if t > 60.0 or k is None:
+            if near > 1e-6:
+                assert k_o == O.MISS
+            continue
+        if near < 1e-9:
+            continue
+        assert k_o == k, (gidx, k_o, k)
+        assert abs(t_o - t) <= 1e-12 * t
+        checked += 1
+    assert checked > 100
+
+
 def test_ray_mask_switches_rays_off():
     v, f = synth.small_random_scene(4, n_tris=60)
     s = _sensor(origin=(0.1, 0.2, 0.05), elev=synth.elevations_full_sphere(8), rays=32, rmax=40.0)
