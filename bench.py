@@ -137,6 +137,12 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=16, help="oracle rays per sensor")
+    ap.add_argument("--no-lossy", action="store_true",
+                    help="skip the leg of the paper's lossy accelerations (timed casts and "
+                         "their hit-distance match rate on the oracle sample)")
+    ap.add_argument("--lossy-frames", type=int, default=1,
+                    help="frames of the lossy leg's Hit%% floor (each adds an oracle sample of "
+                         "--cpu-rays rays per sensor)")
     ap.add_argument("--serving-seconds", type=float, default=3.0,
                     help="seconds of Poisson arrivals of the serving leg (16 clients with "
                          "resident scenes; 0 to skip)")
@@ -199,7 +205,7 @@ def main():
         tuning = args.tuning
     for kv in args.opt:
         k, v = kv.split("=")
-        opts[k] = int(v)
+        opts[k] = float(v) if k == "eps_area" else int(v)
     ctx.set_options(**opts)
     ids = grca.load_workload(ctx, wl, scene_id=0, frame=0, stream=stream)
     torch.cuda.synchronize()
@@ -352,9 +358,25 @@ def main():
                 "traffic": load_traffic(f"{dom}_kernel"),
                 "work": f"{nbytes} algorithmic bytes per launch"}
     rtic_s = stats["rtic"] / (stage_ms["isect"] * 1e-3)
+    # the streaming passes against HBM, with their algorithmic bytes: pose
+    # reads 12 B of rest position (+12 B normal and 4 B phase when deforming)
+    # and writes 12 B per dynamic vertex; init writes the 8 B key of each ray;
+    # resolve reads it and writes 4 B distance + 4 B triangle id
+    n_rigid_v = int(np.sum(sc.rigid.vertex_count)) if sc.rigid is not None else 0
+    n_def_v = int(sum(g.vertex_count for g in sc.deform))
+    stream_bytes = {"pose": 24 * n_rigid_v + 40 * n_def_v, "init": 8 * n_rays,
+                    "resolve": 16 * n_rays}
+    streaming = {}
+    for k, nb in stream_bytes.items():
+        gbs = nb / (stage_ms[k] * 1e-3) / 1e9
+        streaming[k] = {"bytes": int(nb), "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    atomics = {"per_frame": int(stats["atomics"]),
+               "per_s": stats["atomics"] / (stage_ms["isect"] * 1e-3),
+               "per_rtic": stats["atomics"] / max(1, stats["rtic"])}
 
     # ---------------- CPU baseline: the oracle on a bounded sample
     cpu = None
+    samples = {}  # frame -> [(rays, oracle result)] per sensor
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         from tests import parity
@@ -373,6 +395,7 @@ def main():
             tc = time.perf_counter()
             orc = O.cast(s, v_or, sc.indices, rays=rays)
             t_cpu += time.perf_counter() - tc
+            samples.setdefault(args.warmup + args.steps - 1, []).append((rays, orc))
             threads = orc["threads"]
             tot_rays += len(rays)
             sel = offs[s_i] + rays.astype(np.int64)
@@ -385,6 +408,10 @@ def main():
                "seconds": t_cpu, "extrapolated_frame_s": t_cpu * n_rays / tot_rays,
                "parity_on_sample": {"violations": int(bad), **counts}}
         log(f"cpu oracle: {tot_rays} rays in {t_cpu:.1f}s on {threads} threads; parity {counts} bad={bad}")
+
+    lossy = None
+    if not args.no_lossy and samples:
+        lossy = lossy_leg(torch, ctx, stream, wl, ids, sizes, mats, samples, args, dist, tri)
 
     out = {
         "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
@@ -409,15 +436,89 @@ def main():
         "host_wall_ms_per_frame": wall_batched * 1e3 / args.steps,
         "stage_ms": stage_ms,
         "rtic_per_frame": stats["rtic"], "rtic_per_s": rtic_s,
+        "isect_atomics": atomics,
+        "streaming_hbm": streaming,
         "work": {k: stats[k] for k in ("pairs_tested", "sphere_tests", "pairs_evaluated", "rect_items",
                                        "large_records", "row_items")},
         "range_sweep": sweep,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "lossy": lossy,
     }
     ctx.close()
     out["serving"] = serving_leg(args.serving_seconds) if args.serving_seconds > 0 else None
     print(json.dumps(out), flush=True)
+
+
+def lossy_leg(torch, ctx, stream, wl, ids, sizes, mats, samples, args, dist, tri) -> dict:
+    """The paper's lossy accelerations (opt-in cast flags), each alone and all
+    together, against the exact cast: median ms per batched cast of all
+    sensors (grca_cast, device outputs, no graph) and the Hit% floor, the worst over
+    the sampled frames of the share of sampled rays whose hit distance matches
+    the FP64 oracle within 1 mm or that both miss (the paper's accuracy
+    criterion), also over the rays the oracle sees hit."""
+    from oracle import oracle as O
+    from paper_2605_10457_amd import grca, synth
+    from tests import parity
+    modes = {"exact": 0, "area": grca.GRCA_LOSSY_AREA, "cspan": grca.GRCA_LOSSY_CSPAN,
+             "rspan": grca.GRCA_LOSSY_RSPAN,
+             "all": grca.GRCA_LOSSY_AREA | grca.GRCA_LOSSY_CSPAN | grca.GRCA_LOSSY_RSPAN}
+    sc = wl.scene
+    offs = np.cumsum([0] + sizes)
+    frames = sorted(samples)
+    rng = np.random.default_rng(11)
+    while len(frames) < args.lossy_frames:  # more frames, each with its own oracle sample
+        f = frames[-1] + 1
+        v_or = oracle_pose(sc, f)
+        samples[f] = []
+        for s_i, s in enumerate(wl.sensors):
+            rays = np.sort(rng.choice(sizes[s_i], args.cpu_rays, replace=False)).astype(np.uint32)
+            samples[f].append((rays, O.cast(s, v_or, sc.indices, rays=rays)))
+        frames.append(f)
+    res = {m: {"ms": [], "rate": [], "rate_hits": [], "stats": None} for m in modes}
+    for f in frames:
+        ctx.scene_pose(0, sc.instance_matrices(f), synth.deform_time(f), stream)
+        # the GPU idled through the oracle: bring its clocks back up first
+        t_end = time.perf_counter() + 1.0
+        while time.perf_counter() < t_end:
+            for _ in range(20):
+                ctx.cast(ids, dist, tri, stream=stream)
+            ctx.synchronize(stream)
+        for m, fl in modes.items():
+            for _ in range(2):
+                ctx.cast(ids, dist, tri, flags=fl, stream=stream)
+            ctx.synchronize(stream)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(10)]
+            for a, b in ev:
+                a.record(stream)
+                ctx.cast(ids, dist, tri, flags=fl, stream=stream)
+                b.record(stream)
+            ctx.synchronize(stream)
+            res[m]["ms"] += [a.elapsed_time(b) for a, b in ev]
+            res[m]["stats"] = ctx.last_stats()
+            d = dist.cpu().numpy()
+            match, match_h = [], []
+            for s_i, (rays, orc) in enumerate(samples[f]):
+                mk = parity.hit_match(orc, d[offs[s_i] + rays.astype(np.int64)])
+                match.append(mk)
+                match_h.append(mk[np.isfinite(orc["t"])])
+            res[m]["rate"].append(float(np.mean(np.concatenate(match))))
+            hh = np.concatenate(match_h)
+            res[m]["rate_hits"].append(float(np.mean(hh)) if hh.size else 1.0)
+    out = {}
+    for m in modes:
+        r = res[m]
+        out[m] = {"ms": float(np.median(r["ms"])), "hit_floor": min(r["rate"]),
+                  "hit_floor_on_hits": min(r["rate_hits"]),
+                  "rtic": r["stats"]["rtic"], "rect_items": r["stats"]["rect_items"],
+                  "large_records": r["stats"]["large_records"]}
+        log(f"lossy {m}: {out[m]}")
+    out["sample"] = (f"{args.cpu_rays} seeded rays per sensor x {len(wl.sensors)} sensors x "
+                     f"{len(frames)} frame(s); match = hit distance within 1 mm of the FP64 "
+                     f"oracle, or both miss")
+    out["eps_area"] = ctx.get_options()["eps_area"]
+    return out
 
 
 def serving_leg(seconds: float) -> dict:

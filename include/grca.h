@@ -69,6 +69,23 @@ typedef enum {
                                         culling; the reference for "culling never drops
                                         a hit").  Same per-pair arithmetic, so culled and
                                         all-pairs outputs are bitwise equal.            */
+/* The paper's lossy accelerations, opt-in per cast (grca_cast), off by default.
+ * Each only drops candidate pairs, so every ray's result is the exact cast's or a
+ * farther hit or a miss (the paper's accuracy section names them as the causes
+ * of its below-100% hit rates). */
+#define GRCA_LOSSY_AREA 16u          /* apparent-area cull (early pass step 1, Eq.
+                                        apparent_area): skip a (triangle, origin) pair
+                                        whose solid angle A (c - o) . n / |c - o|^3 is
+                                        below grca_options.eps_area                    */
+#define GRCA_LOSSY_CSPAN 32u         /* channel span by two binary searches with the
+                                        GACP-T boolean predicate started at the channel
+                                        midway between the vertices' nearest channels
+                                        (section 3.6) instead of the exact elevation
+                                        extent                                          */
+#define GRCA_LOSSY_RSPAN 64u         /* ray span from the three vertex azimuths rounded
+                                        to the nearest ray (section 3.7, Eq. all_cw),
+                                        without margins; pairs failing the all-CW test
+                                        take the large class                          */
 
 /* ---- context ------------------------------------------------------------- */
 
@@ -175,6 +192,11 @@ typedef struct {
   const uint8_t* ray_mask;            /* optional (NULL = all on), gamma * chi host values
                                          at C * chi + R: 0 switches ray (C, R) off; it then
                                          reports a miss (non-spinning / animated patterns)  */
+  const float* channel_elevation_offset_rad; /* optional (NULL = none), gamma host values:
+                                         channel C's rays have elevation phi_C + offset_C
+                                         (per-channel vertical noise, appendix "Ray Noise
+                                         Simulation"); |phi_C + offset_C| <= pi/2; the
+                                         perturbed elevations need not stay ascending       */
 } grca_sensor_desc;
 
 /* Create or replace sensor `sensor_id`.  Builds the per-sensor channel and
@@ -224,6 +246,8 @@ typedef struct {
                                bounding-sphere test)                                 */
   uint64_t sphere_tests;    /* of pairs_tested: those not culled by the tile's bounding-
                                sphere test, tested against the triangle's own sphere */
+  uint64_t atomics;         /* 64-bit atomic minima the intersection pass issued on the
+                               per-ray keys (hits not ruled out by the key read first)  */
 } grca_stats;
 grca_status grca_last_stats(grca_context* ctx, grca_stats* out);
 
@@ -250,7 +274,8 @@ typedef struct {
   uint32_t isect_ticket;     /* candidate pairs per ticket of the intersection pass
                                 (a wave's unit of dynamic work), 64..2^20, multiple
                                 of 64; never changes results                          */
-  uint32_t reserved;         /* must be 0                                              */
+  float eps_area;            /* epsilon_A of GRCA_LOSSY_AREA (steradians), finite, >= 0;
+                                default 1e-6 (Table tunable_params)                   */
   uint64_t item_capacity;    /* initial work-queue capacity (items)                    */
   uint64_t large_capacity;   /* initial large-record queue capacity                    */
 } grca_options;

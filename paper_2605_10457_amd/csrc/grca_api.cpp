@@ -67,6 +67,7 @@ struct SensorData {
   float elev0 = 0.0f, inv_delev = 1.0f, elev_tol = 0.0f;  // channel grid (bounds pass)
   double dtheta = 0.0;
   float az_noise = 0.0f;
+  float el_noise = 0.0f;  // max |channel elevation offset| (vertical noise), widened
   bool wrap = false;
 };
 
@@ -381,9 +382,12 @@ DevSensor sensor_record(const SensorData& S) {
   d.last_chan = (float)(d.gamma - 1u);
   d.elev0_g = d.elev0 * d.inv_delev;
   d.az_noise = S.az_noise;
+  d.el_noise = S.el_noise;
   d.key_offset = 0;
   d.scene = 0;
   d.cull_back = 0;
+  d.lossy = 0;
+  d.eps_area = 0.0f;
   return d;
 }
 
@@ -446,6 +450,8 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
     d.key_offset = (uint32_t)offs[i];
     d.scene = (uint32_t)(P.scenes.size() - 1);
     d.cull_back = 0;
+    d.lossy = flags & (GRCA_LOSSY_AREA | GRCA_LOSSY_CSPAN | GRCA_LOSSY_RSPAN);
+    d.eps_area = ctx->opt.eps_area;
     if (flags & GRCA_CULL_BACKFACE) {
       const float* f = S.desc.forward;
       const float* r = S.desc.right;
@@ -502,7 +508,9 @@ grca_status launch_cast(grca_context* ctx, const Plan& P, const CastBufs& B, flo
   } else {
     HIPCHK(launch_bounds(B.dscenes, (uint32_t)P.scenes.size(), P.total_tiles, o.bounds_block,
                          B.dsens, o.small_channels, o.small_rays, B.items, B.item_cs, B.icap,
-                         B.large, B.lcap, B.cnt, o.group_cull, o.inline_max, B.keys, st));
+                         B.large, B.lcap, B.cnt, o.group_cull, o.inline_max,
+                         (flags & (GRCA_LOSSY_CSPAN | GRCA_LOSSY_RSPAN)) != 0,
+                         B.keys, st));
     if (ev) HIPCHK(hipEventRecord(ev[1], st));
     const uint32_t pb = persist_blocks(ctx);
     HIPCHK(launch_expand(B.dscenes, B.dsens, B.large, B.items, B.item_cs, B.icap, B.lcap,
@@ -687,7 +695,7 @@ extern "C" grca_status grca_create(int hip_device, grca_context** out) {
   ctx->opt.group_cull = 1;
   ctx->opt.inline_max = 0;
   ctx->opt.isect_ticket = 2048;
-  ctx->opt.reserved = 0;
+  ctx->opt.eps_area = 1e-6f;
   ctx->opt.item_capacity = 1u << 20;
   ctx->opt.large_capacity = 1u << 16;
   ctx->def_ws = new grca_workspace();
@@ -1141,6 +1149,18 @@ extern "C" grca_status grca_sensor_config(grca_context* ctx, uint32_t sensor_id,
       }
       az_noise = az_noise * 1.0001f + 1e-7f;
     }
+    float el_noise = 0.0f;
+    if (s->channel_elevation_offset_rad) {
+      for (uint32_t j = 0; j < s->num_channels; ++j) {
+        const float o = s->channel_elevation_offset_rad[j];
+        if (!std::isfinite(o) ||
+            std::fabs((double)s->channel_elevation_rad[j] + (double)o) > half_pi + 1e-6)
+          return fail(ctx, GRCA_ERR_INVALID_ARG,
+                      "elevation offset not finite or the perturbed elevation beyond pi/2");
+        el_noise = std::max(el_noise, std::fabs(o));
+      }
+      el_noise = el_noise * 1.0001f + 1e-7f;
+    }
     HIPCHK(hipSetDevice(ctx->device));
     SensorData sd;
     sd.desc = *s;
@@ -1156,13 +1176,16 @@ extern "C" grca_status grca_sensor_config(grca_context* ctx, uint32_t sensor_id,
         tol = std::max(tol, std::fabs((double)sd.elev[j] - (e0 + (double)j * step)));
       sd.elev0 = sd.elev[0];
       sd.inv_delev = (float)(1.0 / step);
-      // + the FP32 rounding of 1 / step over the whole table
-      sd.elev_tol = (float)(tol * (1.0 + 1e-6) + 1e-6);
+      // + the FP32 rounding of 1 / step over the whole table, + the largest
+      // elevation offset (the perturbed channels lie within it of the grid)
+      sd.elev_tol = (float)(tol * (1.0 + 1e-6) + 1e-6) + el_noise;
     }
     sd.desc.channel_elevation_rad = nullptr;
     sd.dtheta = (double)s->fov_rad / (double)s->rays_per_channel;
     sd.wrap = std::fabs((double)s->fov_rad - kTwoPi) <= 1e-6;
     sd.az_noise = az_noise;
+    sd.el_noise = el_noise;
+    sd.desc.channel_elevation_offset_rad = nullptr;
     sd.desc.azimuth_offset_rad = nullptr;
     sd.desc.ray_mask = nullptr;
     // bins of at most a quarter of the smallest gap between channel sines, so
@@ -1179,27 +1202,33 @@ extern "C" grca_status grca_sensor_config(grca_context* ctx, uint32_t sensor_id,
     hipError_t e = hipSuccess;
     float* elev_d = nullptr;
     float* off_d = nullptr;
+    float* eoff_d = nullptr;
     if ((e = dmalloc(&sd.chan, g)) != hipSuccess || (e = dmalloc(&sd.chan_d, g)) != hipSuccess ||
         (e = dmalloc(&sd.sin_tab, g)) != hipSuccess || (e = dmalloc(&sd.az, c)) != hipSuccess ||
         (e = dmalloc(&sd.lut, sd.lut_size)) != hipSuccess || (e = dmalloc(&elev_d, g)) != hipSuccess ||
         (s->azimuth_offset_rad && (e = dmalloc(&off_d, c)) != hipSuccess) ||
+        (s->channel_elevation_offset_rad && (e = dmalloc(&eoff_d, g)) != hipSuccess) ||
         (s->ray_mask && (e = dmalloc(&sd.mask, (size_t)g * c)) != hipSuccess)) {
       cleanup();
       dfree(elev_d);
       dfree(off_d);
+      dfree(eoff_d);
       return fail(ctx, GRCA_ERR_OUT_OF_MEMORY, std::string("sensor tables: ") + hipGetErrorString(e));
     }
     e = hipMemcpy(elev_d, sd.elev.data(), 4ull * g, hipMemcpyHostToDevice);
     if (e == hipSuccess && off_d)
       e = hipMemcpy(off_d, s->azimuth_offset_rad, 4ull * c, hipMemcpyHostToDevice);
+    if (e == hipSuccess && eoff_d)
+      e = hipMemcpy(eoff_d, s->channel_elevation_offset_rad, 4ull * g, hipMemcpyHostToDevice);
     if (e == hipSuccess && sd.mask)
       e = hipMemcpy(sd.mask, s->ray_mask, (size_t)g * c, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-      e = launch_sensor_tables(elev_d, g, c, sd.dtheta, off_d, sd.chan, sd.chan_d, sd.sin_tab,
+      e = launch_sensor_tables(elev_d, eoff_d, g, c, sd.dtheta, off_d, sd.chan, sd.chan_d, sd.sin_tab,
                                sd.az, sd.lut_size, sd.lut, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     dfree(elev_d);
     dfree(off_d);
+    dfree(eoff_d);
     if (e != hipSuccess) {
       cleanup();
       return fail(ctx, GRCA_ERR_DEVICE, std::string("sensor tables: ") + hipGetErrorString(e));
@@ -1418,6 +1447,7 @@ grca_status stats_of(grca_context* ctx, grca_workspace* ws, grca_stats* out) {
   out->overflowed = R.overflowed;
   out->pairs_evaluated = c.pairs;
   out->sphere_tests = c.tests;
+  out->atomics = c.atomics;
   return GRCA_OK;
 }
 }  // namespace
@@ -1455,7 +1485,8 @@ extern "C" grca_status grca_set_options(grca_context* ctx, const grca_options* o
   if (o->inline_max > 4096) return fail(ctx, GRCA_ERR_INVALID_ARG, "inline_max outside [0, 4096]");
   if (o->isect_ticket < 64 || o->isect_ticket > (1u << 20) || o->isect_ticket % 64 != 0)
     return fail(ctx, GRCA_ERR_INVALID_ARG, "isect_ticket must be a multiple of 64 in [64, 2^20]");
-  if (o->reserved != 0) return fail(ctx, GRCA_ERR_INVALID_ARG, "reserved must be 0");
+  if (!std::isfinite(o->eps_area) || o->eps_area < 0.0f)
+    return fail(ctx, GRCA_ERR_INVALID_ARG, "eps_area must be finite and >= 0");
   if (o->persist_waves_cu < 1 || o->persist_waves_cu > 32)
     return fail(ctx, GRCA_ERR_INVALID_ARG, "persist_waves_cu outside [1, 32]");
   if (o->item_capacity < 64 || o->item_capacity > 0xFFFFFFF0ull ||

@@ -56,11 +56,13 @@ struct DevSensor {
   double theta_start_d, inv_dtheta_d, period_idx_d;
   const float2* chan;   // (cos phi_j, sin phi_j), FP32
   const double2* chan_d; // (cos phi_j, sin phi_j), FP64
-  const float* sin_tab; // sin phi_j (FP32, equal to chan[j].y), ascending
+  const float* sin_tab; // sin phi_j of the nominal table (FP32), ascending (chan and
+                        // chan_d hold the perturbed elevations under vertical noise)
   const ChanBin* bins;  // lut_size bins of the sine -> channel lookup
   const float2* az;     // (cos theta_R, sin theta_R), FP32 (offsets included)
   const uint8_t* mask;  // optional active-ray mask at C * chi + R (nullptr: all on)
   float az_noise;       // max |azimuth offset| (radians), widens every azimuth span
+  float el_noise;       // max |elevation offset| (radians), widens every channel span
   // the channel elevations as a uniform grid, for the first test of the
   // bounds pass: every channel j lies within elev_tol of elev0 + j / inv_delev
   float elev0, inv_delev, elev_tol;
@@ -69,6 +71,10 @@ struct DevSensor {
   // (dmin (1 + 1e-5), dmax (1 - 1e-5))), the elevation margin 2e-5 +
   // elev_tol, the last channel index gamma - 1 and elev0 * inv_delev
   float cull_dmax, in_dmax, in_dmin, elev_m, last_chan, elev0_g;
+  // the paper's lossy accelerations enabled for this cast (GRCA_LOSSY_* bits;
+  // 0 in an exact cast) and the apparent-area threshold epsilon_A
+  uint32_t lossy;
+  float eps_area;
 };
 
 // Triangles per tile of the bounds pass: one wave, two triangles per lane.
@@ -104,7 +110,8 @@ struct alignas(256) Shard {
   unsigned long long rtic;  // candidate pairs executed from this shard (statistic)
   unsigned long long pairs; // (triangle, origin) spans computed (statistic)
   unsigned long long tests; // (triangle, origin) bounding-sphere tests (statistic)
-  uint32_t pad[54];
+  unsigned long long atomics; // 64-bit atomic minima issued on keys (statistic)
+  uint32_t pad[52];
 };
 static_assert(sizeof(Shard) == 256, "one shard counter per 256-byte line");
 
@@ -129,6 +136,7 @@ struct Summary {
   unsigned long long rtic;   // candidate pairs executed
   unsigned long long pairs;  // (triangle, origin) spans computed
   unsigned long long tests;  // (triangle, origin) bounding-sphere tests
+  unsigned long long atomics; // 64-bit atomic minima issued on keys
   Sticky sticky;             // the sticky record as this cast left it
 };
 

@@ -236,6 +236,114 @@ __device__ inline float atan2_right(float y, float x) {
   return y < 0.0f ? -r : r;
 }
 
+// Ray span of a (triangle, sensor) pair from its vertices in local
+// coordinates (x forward, y right): the azimuth arc widened by the FP32
+// margins, as one or two ray-index ranges (r0, r1), or the whole turn when
+// `full` is set or the arc is too wide.  Returns false when no ray falls in
+// it (`full` is set when the whole turn is taken).  `smax_abs` is the
+// largest |sine of elevation| of the triangle, which sets the pole margin.
+__device__ inline bool ray_span(const float (&x)[3], const float (&y)[3], float smax_abs,
+                                bool& full, const DevSensor& s, Span& sp) {
+  const uint32_t chi = s.chi;
+  sp.r1_start = 0; sp.r1_count = 0;
+  if (!full) {
+    // Azimuth of vertex 0, and the offsets of vertices 1 and 2 from it.  An
+    // offset of tangent t = cross / dot with |t| <= 0.1 lies in
+    // [t - |t|^3/3, t + |t|^3/3] (atan's alternating series), so small
+    // triangles need one atan2 instead of three; other offsets take the full
+    // atan2 difference, wrapped to (-pi, pi].
+    const float t0 = atan2_bounded(y[0], x[0]);
+    float lo = 0.0f, hi = 0.0f;
+#pragma unroll
+    for (int k = 1; k < 3; ++k) {
+      const float cr = fmaf(x[0], y[k], -(y[0] * x[k]));
+      const float dt = fmaf(x[0], x[k], y[0] * y[k]);
+      if (dt > 0.0f && fabsf(cr) <= 0.1f * dt) {
+        const float t = cr * __builtin_amdgcn_rcpf(dt);
+        const float c3 = fabsf(t) * t * t * (1.0f / 3.0f);
+        lo = fminf(lo, t - c3);
+        hi = fmaxf(hi, t + c3);
+      } else {
+        float d = atan2_bounded(y[k], x[k]) - t0;
+        if (d > PI_F) d -= TWO_PI_F;
+        if (d < -PI_F) d += TWO_PI_F;
+        lo = fminf(lo, d);
+        hi = fmaxf(hi, d);
+      }
+    }
+    if (hi - lo > PI_F - 1e-3f) {
+      full = true;
+    } else {
+      // 1 / max(cos(max |elevation|), 1e-3) by the hardware reciprocal square
+      // root (1 ulp suffices for a margin term)
+      const float inv_cos = __builtin_amdgcn_rsqf(fmaxf(fmaf(-smax_abs, smax_abs, 1.0f), 1e-6f));
+      const float m = MARGIN_AZ + MARGIN_AZ_POLE * inv_cos + s.az_noise;
+      float a = t0 + lo - m - s.theta_start;
+      a -= TWO_PI_F * floorf(a * (1.0f / TWO_PI_F));
+      if (a < 0.0f) a = 0.0f;
+      const float w = (hi - lo) + 2.0f * m;
+      const float fa = a * s.inv_dtheta;
+      const float fb = (a + w) * s.inv_dtheta;
+      const int ra = (int)ceilf(fa);
+      const int rb = (int)floorf(fb);
+      if (s.wrap) {
+        int cnt = rb - ra + 1;
+        if (cnt <= 0) return false;
+        if (cnt > (int)chi) cnt = (int)chi;
+        // a lies in [0, 2 pi] up to rounding, so ra lies in [0, chi + 1]
+        sp.r0_start = (uint32_t)ra >= chi ? (uint32_t)ra - chi : (uint32_t)ra;
+        sp.r0_count = (uint32_t)cnt;
+      } else {
+        sp.r0_count = 0;
+        if (ra <= (int)chi - 1 && rb >= ra) {
+          const int e0 = rb < (int)chi - 1 ? rb : (int)chi - 1;
+          sp.r0_start = (uint32_t)ra;
+          sp.r0_count = (uint32_t)(e0 - ra + 1);
+        }
+        const float fb2 = (a + w - TWO_PI_F) * s.inv_dtheta;
+        if (fb2 >= 0.0f) {
+          int e1 = (int)floorf(fb2);
+          if (e1 > (int)chi - 1) e1 = (int)chi - 1;
+          sp.r1_start = 0;
+          sp.r1_count = (uint32_t)(e1 + 1);
+          if (sp.r0_count && sp.r0_start <= (uint32_t)e1) {  // overlap: merge
+            sp.r1_count = 0;
+            sp.r0_start = 0;
+            sp.r0_count = chi;
+          }
+        }
+        if (sp.r0_count == 0 && sp.r1_count == 0) return false;
+        if (sp.r0_count == 0) {
+          sp.r0_start = sp.r1_start; sp.r0_count = sp.r1_count; sp.r1_count = 0;
+        }
+      }
+    }
+  }
+  if (full) {
+    sp.r0_start = 0;
+    sp.r0_count = chi;
+    sp.r1_count = 0;
+  }
+  return true;
+}
+
+// The apparent-area cull of the paper's early pass (step 1, Eq.
+// apparent_area), opt-in (GRCA_LOSSY_AREA): true when the triangle's solid
+// angle A (c - o) . n_hat / |c - o|^3, from its local vertices, is below
+// eps.  Both sides squared, so it needs no back-face test first.
+__device__ inline bool below_apparent_area(const float (&x)[3], const float (&y)[3],
+                                           const float (&z)[3], float eps) {
+  const float e1x = x[1] - x[0], e1y = y[1] - y[0], e1z = z[1] - z[0];
+  const float e2x = x[2] - x[0], e2y = y[2] - y[0], e2z = z[2] - z[0];
+  const float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+  const float cx = (x[0] + x[1] + x[2]) * (1.0f / 3.0f);
+  const float cy = (y[0] + y[1] + y[2]) * (1.0f / 3.0f);
+  const float cz = (z[0] + z[1] + z[2]) * (1.0f / 3.0f);
+  const float a = 0.5f * fmaf(cx, nx, fmaf(cy, ny, cz * nz));  // A (c - o) . n_hat
+  const float c2 = fmaf(cx, cx, fmaf(cy, cy, cz * cz));
+  return a * a < eps * eps * c2 * c2 * c2;
+}
+
 // Conservative candidate span of one (triangle, sensor) pair, FP32.
 // Returns false when no ray of the sensor can reach the triangle.
 __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const float (&vz)[3],
@@ -250,6 +358,8 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
     z[k] = fmaf(dx, s.u[0], fmaf(dy, s.u[1], dz * s.u[2]));
     r2[k] = fmaf(x[k], x[k], fmaf(y[k], y[k], z[k] * z[k]));
   }
+  // the opt-in lossy apparent-area cull (the same for every lane of a cast)
+  if ((s.lossy & GRCA_LOSSY_AREA) && below_apparent_area(x, y, z, s.eps_area)) return false;
   // Vertical axis through the origin vs the triangle's horizontal projection
   // (first, so that the world-space vertices and the sensor's f and r are
   // not needed past this point).
@@ -340,8 +450,9 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
     }
   }
   const float smax_abs = fmaxf(fabsf(s_lo), fabsf(s_hi));
-  s_lo -= ETA_SIN;
-  s_hi += ETA_SIN;
+  // (vertical noise: |sin(phi + o) - sin(phi)| <= |o|)
+  s_lo -= ETA_SIN + s.el_noise;
+  s_hi += ETA_SIN + s.el_noise;
   // both bin loads in flight together
   const ChanBin e_lo = load_bin(s.bins + chan_bin(s, s_lo));
   const ChanBin e_hi = load_bin(s.bins + chan_bin(s, s_hi));
@@ -352,88 +463,269 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
   sp.c_count = c_end - c_from;
   if (smax_abs > S_POLE) full = true;
 
-  const uint32_t chi = s.chi;
-  sp.r1_start = 0; sp.r1_count = 0;
-  if (!full) {
-    // Azimuth of vertex 0, and the offsets of vertices 1 and 2 from it.  An
-    // offset of tangent t = cross / dot with |t| <= 0.1 lies in
-    // [t - |t|^3/3, t + |t|^3/3] (atan's alternating series), so small
-    // triangles need one atan2 instead of three; other offsets take the full
-    // atan2 difference, wrapped to (-pi, pi].
-    const float t0 = atan2_bounded(y[0], x[0]);
-    float lo = 0.0f, hi = 0.0f;
-#pragma unroll
-    for (int k = 1; k < 3; ++k) {
-      const float cr = fmaf(x[0], y[k], -(y[0] * x[k]));
-      const float dt = fmaf(x[0], x[k], y[0] * y[k]);
-      if (dt > 0.0f && fabsf(cr) <= 0.1f * dt) {
-        const float t = cr * __builtin_amdgcn_rcpf(dt);
-        const float c3 = fabsf(t) * t * t * (1.0f / 3.0f);
-        lo = fminf(lo, t - c3);
-        hi = fmaxf(hi, t + c3);
-      } else {
-        float d = atan2_bounded(y[k], x[k]) - t0;
-        if (d > PI_F) d -= TWO_PI_F;
-        if (d < -PI_F) d += TWO_PI_F;
-        lo = fminf(lo, d);
-        hi = fmaxf(hi, d);
-      }
-    }
-    if (hi - lo > PI_F - 1e-3f) {
-      full = true;
-    } else {
-      // 1 / max(cos(max |elevation|), 1e-3) by the hardware reciprocal square
-      // root (1 ulp suffices for a margin term)
-      const float inv_cos = __builtin_amdgcn_rsqf(fmaxf(fmaf(-smax_abs, smax_abs, 1.0f), 1e-6f));
-      const float m = MARGIN_AZ + MARGIN_AZ_POLE * inv_cos + s.az_noise;
-      float a = t0 + lo - m - s.theta_start;
-      a -= TWO_PI_F * floorf(a * (1.0f / TWO_PI_F));
-      if (a < 0.0f) a = 0.0f;
-      const float w = (hi - lo) + 2.0f * m;
-      const float fa = a * s.inv_dtheta;
-      const float fb = (a + w) * s.inv_dtheta;
-      const int ra = (int)ceilf(fa);
-      const int rb = (int)floorf(fb);
-      if (s.wrap) {
-        int cnt = rb - ra + 1;
-        if (cnt <= 0) return false;
-        if (cnt > (int)chi) cnt = (int)chi;
-        // a lies in [0, 2 pi] up to rounding, so ra lies in [0, chi + 1]
-        sp.r0_start = (uint32_t)ra >= chi ? (uint32_t)ra - chi : (uint32_t)ra;
-        sp.r0_count = (uint32_t)cnt;
-      } else {
-        sp.r0_count = 0;
-        if (ra <= (int)chi - 1 && rb >= ra) {
-          const int e0 = rb < (int)chi - 1 ? rb : (int)chi - 1;
-          sp.r0_start = (uint32_t)ra;
-          sp.r0_count = (uint32_t)(e0 - ra + 1);
-        }
-        const float fb2 = (a + w - TWO_PI_F) * s.inv_dtheta;
-        if (fb2 >= 0.0f) {
-          int e1 = (int)floorf(fb2);
-          if (e1 > (int)chi - 1) e1 = (int)chi - 1;
-          sp.r1_start = 0;
-          sp.r1_count = (uint32_t)(e1 + 1);
-          if (sp.r0_count && sp.r0_start <= (uint32_t)e1) {  // overlap: merge
-            sp.r1_count = 0;
-            sp.r0_start = 0;
-            sp.r0_count = chi;
-          }
-        }
-        if (sp.r0_count == 0 && sp.r1_count == 0) return false;
-        if (sp.r0_count == 0) {
-          sp.r0_start = sp.r1_start; sp.r0_count = sp.r1_count; sp.r1_count = 0;
-        }
-      }
-    }
-  }
-  if (full) {
-    sp.r0_start = 0;
-    sp.r0_count = chi;
-    sp.r1_count = 0;
-  }
+  if (!ray_span(x, y, smax_abs, full, s, sp)) return false;
   sp.large = full || sp.c_count > small_c || sp.r0_count > small_r ||
              (sp.r1_count > small_r);
+  return true;
+}
+
+// ------------------------------------------------------------ lossy modes
+// The paper's own early pass, opt-in (GRCA_LOSSY_* cast flags): FP32 with
+// no margins, so rays near a triangle's angular boundary can lose their hit
+// (its accuracy section lists these as causes 1, 2 and 3).
+
+// GACP-T boolean predicate (section 3.5, "Boolean predicate"): does the cone
+// of elevation phi (sine sphi) around the up axis through the origin cross
+// the triangle?  Local coordinates (z up), |p_k| given as inv[k] = 1 / |p_k|.
+// Vertex classification first: all below the origin's horizontal plane (for
+// phi > 0; above, for phi < 0) -> no; all inside the cone -> no; some inside
+// and some outside -> yes; all outside -> the apex-ray check (the axis ray
+// of the cone's side hits the triangle, and the triangle lies within
+// range_max |sin phi| of the origin; its plane distance stands in for the
+// closest-point distance), then the per-edge quadratic
+//   (e_A^2 - s^2 |e|^2) l^2 + 2 (e_A h - s^2 p.e) l + (h^2 - s^2 |p|^2) = 0
+// with a root l in [0, 1] on the cone's forward half.  phi = 0 is the plane
+// case: the heights change sign.
+__device__ inline bool gacp_t(const float (&x)[3], const float (&y)[3], const float (&z)[3],
+                              const float (&inv)[3], float sphi, bool apex_up, bool apex_dn,
+                              float plane_dist, float dmax) {
+  if (sphi == 0.0f) {
+    const bool pos = z[0] > 0.0f || z[1] > 0.0f || z[2] > 0.0f;
+    const bool neg = z[0] < 0.0f || z[1] < 0.0f || z[2] < 0.0f;
+    return (pos && neg) || z[0] == 0.0f || z[1] == 0.0f || z[2] == 0.0f;
+  }
+  const float sg = sphi > 0.0f ? 1.0f : -1.0f;
+  const float sa = fabsf(sphi);
+  float h[3];
+  int inside = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    h[k] = sg * z[k];
+    inside += (h[k] * inv[k] >= sa) ? 1 : 0;
+  }
+  if (h[0] < 0.0f && h[1] < 0.0f && h[2] < 0.0f) return false;  // wrong half-space
+  if (inside == 3) return false;
+  if (inside > 0) return true;
+  if ((sg > 0.0f ? apex_up : apex_dn) && plane_dist <= dmax * sa) return true;
+  const float s2 = sa * sa;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int k1 = (k + 1) % 3;
+    const float ex = x[k1] - x[k], ey = y[k1] - y[k], ez = z[k1] - z[k];
+    const float ea = sg * ez;
+    const float pe = fmaf(x[k], ex, fmaf(y[k], ey, z[k] * ez));
+    const float ee = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+    const float pp = fmaf(x[k], x[k], fmaf(y[k], y[k], z[k] * z[k]));
+    const float c2 = fmaf(ea, ea, -s2 * ee);
+    const float c1 = 2.0f * fmaf(ea, h[k], -s2 * pe);
+    const float c0 = fmaf(h[k], h[k], -s2 * pp);
+    const float disc = fmaf(c1, c1, -4.0f * c2 * c0);
+    if (disc < 0.0f) continue;
+    float l0, l1;
+    if (c2 == 0.0f) {
+      if (c1 == 0.0f) continue;
+      l0 = l1 = -c0 / c1;
+    } else {
+      const float sq = sqrtf(disc);
+      l0 = (-c1 - sq) / (2.0f * c2);
+      l1 = (-c1 + sq) / (2.0f * c2);
+    }
+    if (l0 >= 0.0f && l0 <= 1.0f && fmaf(l0, ea, h[k]) >= 0.0f) return true;
+    if (l1 >= 0.0f && l1 <= 1.0f && fmaf(l1, ea, h[k]) >= 0.0f) return true;
+  }
+  return false;
+}
+
+// span_of with the paper's lossy steps enabled by s.lossy:
+//  GRCA_LOSSY_AREA   cull when the apparent area A (c - o) . n / |c - o|^3
+//                    (early pass step 1) is below eps_area;
+//  GRCA_LOSSY_CSPAN  the channel span by two binary searches with gacp_t,
+//                    both started at C_mid, the channel midway between the
+//                    vertices' nearest channels on the uniform grid (section
+//                    3.6); no crossing at C_mid discards the pair;
+//  GRCA_LOSSY_RSPAN  when all three vertices lie on one side of the sensor
+//                    (all-front along the centre ray, all-right or all-left,
+//                    Eq. all_cw; always for fields of view up to 180
+//                    degrees), the ray span from the vertex azimuths rounded
+//                    to the nearest ray and clamped to the sensor (section
+//                    3.7); otherwise the pair takes the large class, whose
+//                    per-channel arcs are exact.
+// Steps not enabled are the exact ones of span_of.
+__device__ inline bool span_of_lossy(const float (&vx)[3], const float (&vy)[3],
+                                     const float (&vz)[3], const DevSensor& s, uint32_t small_c,
+                                     uint32_t small_r, bool need_range, bool need_pole,
+                                     Span& sp) {
+  const uint32_t lossy = s.lossy;
+  float x[3], y[3], z[3], r2[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float dx = vx[k] - s.o[0], dy = vy[k] - s.o[1], dz = vz[k] - s.o[2];
+    x[k] = fmaf(dx, s.f[0], fmaf(dy, s.f[1], dz * s.f[2]));
+    y[k] = fmaf(dx, s.r[0], fmaf(dy, s.r[1], dz * s.r[2]));
+    z[k] = fmaf(dx, s.u[0], fmaf(dy, s.u[1], dz * s.u[2]));
+    r2[k] = fmaf(x[k], x[k], fmaf(y[k], y[k], z[k] * z[k]));
+  }
+  if ((lossy & GRCA_LOSSY_AREA) && below_apparent_area(x, y, z, s.eps_area)) return false;
+  // face normal n = e1 x e2 (|n| = 2 A), local axes
+  const float e1x = x[1] - x[0], e1y = y[1] - y[0], e1z = z[1] - z[0];
+  const float e2x = x[2] - x[0], e2y = y[2] - y[0], e2z = z[2] - z[0];
+  const float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+  // the up axis through the origin against the triangle's horizontal projection
+  bool pierce = false;
+  {
+    float e[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int k1 = (k + 1) % 3;
+      e[k] = x[k] * (y[k1] - y[k]) - y[k] * (x[k1] - x[k]);
+    }
+    pierce = (e[0] >= 0.0f && e[1] >= 0.0f && e[2] >= 0.0f) ||
+             (e[0] <= 0.0f && e[1] <= 0.0f && e[2] <= 0.0f);
+  }
+  bool pole = false;
+  if (need_pole) pole = pierce;
+  const float dmin = s.dmin, dmax = s.dmax;
+  if (need_range) {
+    const float r2max = fmaxf(r2[0], fmaxf(r2[1], r2[2]));
+    if (r2max < dmin * dmin) return false;
+    const float r2min = fminf(r2[0], fminf(r2[1], r2[2]));
+    // plane distance as the closest-point distance: beyond range_max
+    const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+    const float g = fmaf(x[0], nx, fmaf(y[0], ny, z[0] * nz));
+    if (nn > 0.0f && g * g > dmax * dmax * nn && r2min > dmax * dmax) return false;
+  }
+  const float r2min = fminf(r2[0], fminf(r2[1], r2[2]));
+  if (!(r2min > 1e-24f)) return span_of(vx, vy, vz, s, small_c, small_r, need_range, need_pole, sp);
+  float inv[3], sn[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    inv[k] = __builtin_amdgcn_rsqf(r2[k]);
+    sn[k] = z[k] * inv[k];
+  }
+  const uint32_t gamma = s.gamma;
+  uint32_t c_from, c_end;
+  bool full = false;
+  // largest |sine of elevation| (the azimuth margin near the poles)
+  float smax_abs = fmaxf(fabsf(sn[0]), fmaxf(fabsf(sn[1]), fabsf(sn[2])));
+  if (lossy & GRCA_LOSSY_CSPAN) {
+    // apex ray: the up (down) axis meets the triangle's plane above (below)
+    // the origin inside the triangle
+    const float g = fmaf(x[0], nx, fmaf(y[0], ny, z[0] * nz));  // n . p0
+    const bool up = pierce && nz != 0.0f && g / nz > 0.0f;
+    const bool dn = pierce && nz != 0.0f && g / nz < 0.0f;
+    const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+    const float plane_dist = nn > 0.0f ? fabsf(g) * __builtin_amdgcn_rsqf(nn) : 0.0f;
+    int cmin = (int)gamma, cmax = -1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float ci = rintf((asinf(fminf(fmaxf(sn[k], -1.0f), 1.0f)) - s.elev0) * s.inv_delev);
+      const int c = (int)fminf(fmaxf(ci, 0.0f), (float)(gamma - 1u));
+      cmin = min(cmin, c);
+      cmax = max(cmax, c);
+    }
+    const int cmid = (cmin + cmax + 1) / 2;
+    auto crosses = [&](int j) {
+      return gacp_t(x, y, z, inv, s.sin_tab[j], up, dn, plane_dist, dmax);
+    };
+    if (!crosses(cmid)) return false;
+    int lo = 0, hi = cmid;
+    while (lo < hi) {
+      const int m = (lo + hi) / 2;
+      if (crosses(m)) hi = m; else lo = m + 1;
+    }
+    c_from = (uint32_t)lo;
+    lo = cmid;
+    hi = (int)gamma - 1;
+    while (lo < hi) {
+      const int m = (lo + hi + 1) / 2;
+      if (crosses(m)) lo = m; else hi = m - 1;
+    }
+    c_end = (uint32_t)lo + 1u;
+    if (pole) full = true;
+  } else {
+    // the exact elevation extent of span_of
+    float s_lo = fminf(sn[0], fminf(sn[1], sn[2]));
+    float s_hi = fmaxf(sn[0], fmaxf(sn[1], sn[2]));
+    float cmn = 1.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int k1 = (k + 1) % 3;
+      cmn = fminf(cmn, fmaf(x[k], x[k1], fmaf(y[k], y[k1], z[k] * z[k1])) * inv[k] * inv[k1]);
+    }
+    const float kb = __builtin_amdgcn_rsqf(fmaxf(0.5f * (1.0f + cmn), 1e-12f)) * (1.0f + 1e-6f);
+    if (s_hi > 0.0f) s_hi = fminf(s_hi * kb, 1.0f);
+    if (s_lo < 0.0f) s_lo = fmaxf(s_lo * kb, -1.0f);
+    if (pole) {
+      full = true;
+      const bool up = z[0] > 0.0f && z[1] > 0.0f && z[2] > 0.0f;
+      const bool dn = z[0] < 0.0f && z[1] < 0.0f && z[2] < 0.0f;
+      if (!dn) s_hi = 1.0f;
+      if (!up) s_lo = -1.0f;
+    }
+    smax_abs = fmaxf(fabsf(s_lo), fabsf(s_hi));
+    if (smax_abs > S_POLE) full = true;
+    s_lo -= ETA_SIN + s.el_noise;
+    s_hi += ETA_SIN + s.el_noise;
+    c_from = chan_search(s, s_lo, false);
+    c_end = chan_search(s, s_hi, true);
+  }
+  if (c_from >= c_end) return false;
+  sp.c_from = c_from;
+  sp.c_count = c_end - c_from;
+  sp.r1_start = 0;
+  sp.r1_count = 0;
+  const uint32_t chi = s.chi;
+  if (!full && (lossy & GRCA_LOSSY_RSPAN)) {
+    bool all_cw = !s.wrap && (float)chi <= s.period_idx * 0.5f;  // field of view <= 180 deg
+    if (!all_cw) {
+      // centre ray (channel floor(gamma / 2), azimuth 0) and a right vector
+      // by Gram-Schmidt from the up axis (the forward axis near the poles)
+      const float2 cc = s.chan[gamma / 2u];
+      const float dx = cc.x, dz = cc.y;  // (cos phi_c, 0, sin phi_c)
+      const bool steep = fabsf(dz) >= 0.9f;
+      const float wx = steep ? 1.0f : 0.0f, wz = steep ? 0.0f : 1.0f;
+      const float wd = wx * dx + wz * dz;
+      float ux = wx - wd * dx, uz = wz - wd * dz;
+      const float iu = __builtin_amdgcn_rsqf(fmaf(ux, ux, uz * uz));
+      ux *= iu;
+      uz *= iu;
+      // r_perp = d x u_perp, d and u_perp in the x-z plane: (0, dz ux - dx uz, 0)
+      const float ry = dz * ux - dx * uz;
+      bool front = true, right = true, left = true;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        front = front && fmaf(x[k], dx, z[k] * dz) > 0.0f;
+        right = right && y[k] * ry > 0.0f;
+        left = left && y[k] * ry < 0.0f;
+      }
+      all_cw = front || right || left;
+    }
+    if (all_cw) {
+      int rmin = (int)chi, rmax = -1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float t = atan2f(y[k], x[k]);
+        const float ri = rintf((t - s.theta_start) * s.inv_dtheta);
+        const int r = (int)fminf(fmaxf(ri, 0.0f), (float)(chi - 1u));
+        rmin = min(rmin, r);
+        rmax = max(rmax, r);
+      }
+      sp.r0_start = (uint32_t)rmin;
+      sp.r0_count = (uint32_t)(rmax - rmin + 1);
+    } else {
+      full = true;  // the seam case: large class
+    }
+    if (full) {
+      sp.r0_start = 0;
+      sp.r0_count = chi;
+    }
+    sp.large = full || sp.c_count > small_c || sp.r0_count > small_r;
+    return true;
+  }
+  // the exact azimuth arc of span_of
+  if (smax_abs > S_POLE) full = true;
+  if (!ray_span(x, y, smax_abs, full, s, sp)) return false;
+  sp.large = full || sp.c_count > small_c || sp.r0_count > small_r || sp.r1_count > small_r;
   return true;
 }
 
@@ -600,11 +892,8 @@ __device__ inline uint32_t item_candidates(const Item& it) {
 // the spills cost more than the extra wave gains).
 constexpr int BOUNDS_WAVES_PER_SIMD = 7;
 
-template <int WPB, bool INLINE>
-__global__ __launch_bounds__(WPB * 64, INLINE ? 1
-                                              : (4 * BOUNDS_WAVES_PER_SIMD / WPB > 0
-                                                     ? 4 * BOUNDS_WAVES_PER_SIMD / WPB
-                                                     : 1)) void bounds_kernel(
+template <int WPB, bool INLINE, bool LOSSY>
+__global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SIMD) void bounds_kernel(
     const DevScene* __restrict__ scenes, uint32_t nscenes, uint32_t total_tiles,
     const DevSensor* __restrict__ sens, uint32_t small_c, uint32_t small_r,
     Item* __restrict__ items, uint32_t* __restrict__ item_cs, uint32_t item_scap,
@@ -787,8 +1076,10 @@ __global__ __launch_bounds__(WPB * 64, INLINE ? 1
     const DevSensor& s = *reinterpret_cast<const DevSensor*>(
         reinterpret_cast<const char*>(sens) + __umul24(pn, (uint32_t)sizeof(DevSensor)));
     Span sp;
-    const bool ok = live && span_of(px, py, pz, s, small_c, small_r, (e >> 7) & 1u,
-                                    (e >> 8) & 1u, sp);
+    const bool ok = live && (LOSSY ? span_of_lossy(px, py, pz, s, small_c, small_r, (e >> 7) & 1u,
+                                                   (e >> 8) & 1u, sp)
+                                   : span_of(px, py, pz, s, small_c, small_r, (e >> 7) & 1u,
+                                             (e >> 8) & 1u, sp));
     const uint32_t chan = ok ? (sp.c_from | (sp.c_count << 16)) : 0u;
     const bool is_large = ok && sp.large;
     bool rect0 = ok && !sp.large;
@@ -1266,9 +1557,9 @@ __device__ inline Cand cand_read(int own, uint32_t f, const ItemInfo* in_w,
   return o;
 }
 // The ray test against the owner's statics, and the atomic for a hit that
-// can improve on the key read.
+// can improve on the key read (returns whether one was issued).
 template <bool LDS_SENS>
-__device__ inline void cand_finish(const Cand& o, int own, const float4 (*st_w)[64],
+__device__ inline uint32_t cand_finish(const Cand& o, int own, const float4 (*st_w)[64],
                                    const ItemInfo* in_w, const IsectSensor* sen,
                                    const DevSensor* sens, unsigned long long* keys) {
   const uint32_t ow = (uint32_t)own;
@@ -1280,7 +1571,11 @@ __device__ inline void cand_finish(const Cand& o, int own, const float4 (*st_w)[
   const float dmin = LDS_SENS ? sen[sid].dmin : sens[sid].dmin;
   const float dmax = LDS_SENS ? sen[sid].dmax : sens[sid].dmax;
   const unsigned long long key = ray_test(st, o.cp.x, o.cp.y, o.ca.x, o.ca.y, dmin, dmax, inf.tri);
-  if (o.on && key < o.seen) key_min(keys, o.kidx, key);
+  if (o.on && key < o.seen) {
+    key_min(keys, o.kidx, key);
+    return 1u;
+  }
+  return 0u;
 }
 
 // Inclusive prefix maximum over the wave (identity -1) with DPP row shifts
@@ -1343,6 +1638,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
   const bool any_mask = __syncthreads_or(has_mask) != 0;
   const ShardWalk sw = shard_walk(WPB);
   unsigned long long rtic = 0ull;  // wave-uniform
+  uint32_t natom = 0;              // atomic minima this lane issued
   for (uint32_t sh = sw.first; sh < NSHARD; sh += sw.step) {
     const unsigned long long nc = cnt->items[sh].nc;
     const uint32_t n_items = min((uint32_t)nc, item_scap);
@@ -1440,7 +1736,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
 #pragma unroll
           for (int j = 0; j < ISECT_SLOTS; ++j)
             if (j == 0 || base + 64u * j + lane < total)
-              cand_finish<LDS_SENS>(c[j], own[j], st_s[w], in_s[w], sen_s, sens, keys);
+              natom += cand_finish<LDS_SENS>(c[j], own[j], st_s[w], in_s[w], sen_s, sens, keys);
         }
         wave_sync();
         if (last) break;
@@ -1448,6 +1744,9 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     }
   }
   if (lane == 0 && rtic) atomicAdd(&cnt->items[sw.first].rtic, rtic);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) natom += __shfl_xor(natom, o, 64);
+  if (lane == 0 && natom) atomicAdd(&cnt->items[sw.first].atomics, (unsigned long long)natom);
 }
 
 // ------------------------------------------------------------------ all pairs
@@ -1511,7 +1810,7 @@ __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint
     uint32_t ni = (uint32_t)cnt->items[l].nc, nl = (uint32_t)cnt->large[l].nc;
     uint32_t nr = cnt->items[l].rows;
     unsigned long long rt = cnt->items[l].rtic, pr = cnt->items[l].pairs;
-    unsigned long long te = cnt->items[l].tests;
+    unsigned long long te = cnt->items[l].tests, at = cnt->items[l].atomics;
     uint32_t mi = ni, ml = nl;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -1521,6 +1820,7 @@ __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint
       rt += __shfl_xor(rt, o, 64);
       pr += __shfl_xor(pr, o, 64);
       te += __shfl_xor(te, o, 64);
+      at += __shfl_xor(at, o, 64);
       mi = max(mi, (uint32_t)__shfl_xor(mi, o, 64));
       ml = max(ml, (uint32_t)__shfl_xor(ml, o, 64));
     }
@@ -1529,6 +1829,7 @@ __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint
       S.n_items = ni; S.n_large = nl; S.n_rows = nr; S.overflow = cnt->overflow;
       S.max_items_shard = mi; S.max_large_shard = ml; S.rtic = rt; S.pairs = pr;
       S.tests = te;
+      S.atomics = at;
       Sticky k = cnt->sticky;
       if (cnt->overflow) {
         k.overflow |= cnt->overflow;
@@ -1606,17 +1907,21 @@ __global__ __launch_bounds__(256) void pose_kernel(
 }
 
 // ------------------------------------------------------------------ sensor tables
-__global__ void sensor_tables_kernel(const float* __restrict__ elev, uint32_t gamma, uint32_t chi,
-                                     double dtheta, const float* __restrict__ az_off,
-                                     float2* __restrict__ chan, double2* __restrict__ chan_d,
-                                     float* __restrict__ sin_tab, float2* __restrict__ az) {
+__global__ void sensor_tables_kernel(const float* __restrict__ elev, const float* __restrict__ el_off,
+                                     uint32_t gamma, uint32_t chi, double dtheta,
+                                     const float* __restrict__ az_off, float2* __restrict__ chan,
+                                     double2* __restrict__ chan_d, float* __restrict__ sin_tab,
+                                     float2* __restrict__ az) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < gamma) {
+    // the nominal elevation for the channel search, the perturbed one
+    // (vertical noise) for the rays
     const double p = (double)elev[i];
-    const double c = cos(p), s = sin(p);
+    const double q = el_off ? p + (double)el_off[i] : p;
+    const double c = cos(q), s = sin(q);
     chan[i] = make_float2((float)c, (float)s);
     chan_d[i] = make_double2(c, s);
-    sin_tab[i] = (float)s;
+    sin_tab[i] = (float)sin(p);
   }
   if (i < chi) {
     // theta_R = (R - floor(chi / 2)) * dtheta (section 3.1, centred start)
@@ -1683,20 +1988,25 @@ hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t tota
                          uint32_t block, const DevSensor* sens, uint32_t small_c, uint32_t small_r,
                          Item* items, uint32_t* item_cs, uint32_t item_scap, Item* large,
                          uint32_t large_scap, Counters* cnt, uint32_t group_cull,
-                         uint32_t inline_max, unsigned long long* keys, hipStream_t st) {
+                         uint32_t inline_max, bool lossy, unsigned long long* keys,
+                         hipStream_t st) {
   if (total_tiles == 0) return hipSuccess;
 #define GRCA_BOUNDS_CASE(B)                                                                   \
   case B: {                                                                                   \
     constexpr uint32_t W = B / 64;                                                            \
     const uint32_t nb = cdiv(total_tiles, W);                                                 \
-    if (inline_max) {                                                                         \
-      hipLaunchKernelGGL((bounds_kernel<W, true>), dim3(nb), dim3(B), 0, st, scenes, nscenes,  \
-                         total_tiles, sens, small_c, small_r, items, item_cs, item_scap, large, \
-                         large_scap, cnt, group_cull, inline_max, keys);                       \
+    if (lossy) {                                                                              \
+      hipLaunchKernelGGL((bounds_kernel<W, false, true>), dim3(nb), dim3(B), 0, st, scenes,    \
+                         nscenes, total_tiles, sens, small_c, small_r, items, item_cs,         \
+                         item_scap, large, large_scap, cnt, group_cull, 0u, keys);             \
+    } else if (inline_max) {                                                                  \
+      hipLaunchKernelGGL((bounds_kernel<W, true, false>), dim3(nb), dim3(B), 0, st, scenes,    \
+                         nscenes, total_tiles, sens, small_c, small_r, items, item_cs,         \
+                         item_scap, large, large_scap, cnt, group_cull, inline_max, keys);     \
     } else {                                                                                  \
-      hipLaunchKernelGGL((bounds_kernel<W, false>), dim3(nb), dim3(B), 0, st, scenes, nscenes, \
-                         total_tiles, sens, small_c, small_r, items, item_cs, item_scap, large, \
-                         large_scap, cnt, group_cull, 0u, keys);                               \
+      hipLaunchKernelGGL((bounds_kernel<W, false, false>), dim3(nb), dim3(B), 0, st, scenes,   \
+                         nscenes, total_tiles, sens, small_c, small_r, items, item_cs,         \
+                         item_scap, large, large_scap, cnt, group_cull, 0u, keys);             \
     }                                                                                         \
     break;                                                                                    \
   }
@@ -1770,13 +2080,13 @@ hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* r
   return hipGetLastError();
 }
 
-hipError_t launch_sensor_tables(const float* elev, uint32_t gamma, uint32_t chi, double dtheta,
-                                const float* az_off, float2* chan, double2* chan_d,
-                                float* sin_tab, float2* az, uint32_t lut_size, ChanBin* lut,
-                                hipStream_t st) {
+hipError_t launch_sensor_tables(const float* elev, const float* el_off, uint32_t gamma,
+                                uint32_t chi, double dtheta, const float* az_off, float2* chan,
+                                double2* chan_d, float* sin_tab, float2* az, uint32_t lut_size,
+                                ChanBin* lut, hipStream_t st) {
   const uint32_t n = gamma > chi ? gamma : chi;
-  hipLaunchKernelGGL(sensor_tables_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, elev, gamma,
-                     chi, dtheta, az_off, chan, chan_d, sin_tab, az);
+  hipLaunchKernelGGL(sensor_tables_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, elev, el_off,
+                     gamma, chi, dtheta, az_off, chan, chan_d, sin_tab, az);
   hipLaunchKernelGGL(sensor_lut_kernel, dim3(cdiv(lut_size, 256)), dim3(256), 0, st, sin_tab,
                      gamma, lut_size, lut);
   return hipGetLastError();

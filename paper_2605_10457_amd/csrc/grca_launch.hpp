@@ -33,7 +33,8 @@ hipError_t launch_bounds(const DevScene* scenes, uint32_t nscenes, uint32_t tota
                          uint32_t block, const DevSensor* sens, uint32_t small_c, uint32_t small_r,
                          Item* items, uint32_t* item_cs, uint32_t item_scap, Item* large,
                          uint32_t large_scap, Counters* cnt, uint32_t group_cull,
-                         uint32_t inline_max, unsigned long long* keys, hipStream_t st);
+                         uint32_t inline_max, bool lossy, unsigned long long* keys,
+                         hipStream_t st);
 hipError_t launch_expand(const DevScene* scenes, const DevSensor* sens, const Item* large,
                          Item* items, uint32_t* item_cs, uint32_t item_scap, uint32_t large_scap,
                          uint32_t row_chunk, Counters* cnt, uint32_t nblocks, hipStream_t st);
@@ -52,10 +53,13 @@ hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* r
                        const float* rz, const float* nx, const float* ny, const float* nz,
                        const float* phase, const DeformParam* groups, const double* pose_in,
                        float* x, float* y, float* z, hipStream_t st);
-hipError_t launch_sensor_tables(const float* elev, uint32_t gamma, uint32_t chi, double dtheta,
-                                const float* az_off, float2* chan, double2* chan_d,
-                                float* sin_tab, float2* az, uint32_t lut_size, ChanBin* lut,
-                                hipStream_t st);
+// Per-sensor tables: chan / chan_d from the elevations plus the optional
+// per-channel offsets (vertical noise), sin_tab and the lookup from the
+// nominal (ascending) elevations, az from the azimuth grid plus offsets.
+hipError_t launch_sensor_tables(const float* elev, const float* el_off, uint32_t gamma,
+                                uint32_t chi, double dtheta, const float* az_off, float2* chan,
+                                double2* chan_d, float* sin_tab, float2* az, uint32_t lut_size,
+                                ChanBin* lut, hipStream_t st);
 hipError_t launch_validate(const float* xyz, uint32_t nv, const uint32_t* idx, uint64_t nidx,
                            uint32_t* bad, hipStream_t st);
 hipError_t launch_soa(const float* xyz, uint32_t nv, float* x, float* y, float* z,

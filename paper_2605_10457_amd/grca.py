@@ -30,6 +30,9 @@ GRCA_MEM_DEVICE = 1
 GRCA_UPDATE_VERTICES_ONLY = 2
 GRCA_CULL_BACKFACE = 4
 GRCA_CAST_ALL_PAIRS = 8
+GRCA_LOSSY_AREA = 16
+GRCA_LOSSY_CSPAN = 32
+GRCA_LOSSY_RSPAN = 64
 GRCA_NOALLOC_SCRATCH_BYTES = 64 << 20
 GRCA_NOALLOC_MAX_SENSORS = 64
 GRCA_NOALLOC_MIN_QUEUE_BYTES = 2 << 20
@@ -58,6 +61,7 @@ class SensorDesc(ctypes.Structure):
         ("range_max", ctypes.c_float),
         ("azimuth_offset_rad", ctypes.POINTER(ctypes.c_float)),
         ("ray_mask", ctypes.POINTER(ctypes.c_uint8)),
+        ("channel_elevation_offset_rad", ctypes.POINTER(ctypes.c_float)),
     ]
 
 
@@ -71,7 +75,8 @@ class Stats(ctypes.Structure):
                 ("rect_items", ctypes.c_uint64), ("large_records", ctypes.c_uint64),
                 ("row_items", ctypes.c_uint64), ("rtic", ctypes.c_uint64),
                 ("recasts", ctypes.c_uint32), ("overflowed", ctypes.c_uint32),
-                ("pairs_evaluated", ctypes.c_uint64), ("sphere_tests", ctypes.c_uint64)]
+                ("pairs_evaluated", ctypes.c_uint64), ("sphere_tests", ctypes.c_uint64),
+                ("atomics", ctypes.c_uint64)]
 
 
 class Options(ctypes.Structure):
@@ -79,7 +84,7 @@ class Options(ctypes.Structure):
                 ("row_chunk", ctypes.c_uint32), ("bounds_block", ctypes.c_uint32),
                 ("persist_waves_cu", ctypes.c_uint32), ("group_cull", ctypes.c_uint32),
                 ("inline_max", ctypes.c_uint32),
-                ("isect_ticket", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("isect_ticket", ctypes.c_uint32), ("eps_area", ctypes.c_float),
                 ("item_capacity", ctypes.c_uint64),
                 ("large_capacity", ctypes.c_uint64)]
 
@@ -261,6 +266,10 @@ def make_sensor_desc(sensor: dict, scene_id: int):
         m = np.ascontiguousarray(sensor["ray_mask"], np.uint8).reshape(-1)
         d.ray_mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         keep.append(m)
+    if sensor.get("elevation_offset") is not None:
+        eo = np.ascontiguousarray(sensor["elevation_offset"], np.float32)
+        d.channel_elevation_offset_rad = eo.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        keep.append(eo)
     return d, keep
 
 
@@ -304,13 +313,16 @@ def grca_last_stats(ctx) -> dict:
 def grca_get_options(ctx) -> dict:
     o = Options()
     _check(ctx, load().grca_get_options(ctx, ctypes.byref(o)))
-    return {f: int(getattr(o, f)) for f, _ in Options._fields_}
+    return {f: (float(getattr(o, f)) if t is ctypes.c_float else int(getattr(o, f)))
+            for f, t in Options._fields_}
 
 
 def grca_set_options(ctx, **kw):
     cur = grca_get_options(ctx)
     cur.update(kw)
-    o = Options(**{k: int(v) for k, v in cur.items()})
+    types = dict(Options._fields_)
+    o = Options(**{k: (float(v) if types[k] is ctypes.c_float else int(v))
+                   for k, v in cur.items()})
     _check(ctx, load().grca_set_options(ctx, ctypes.byref(o)))
 
 

@@ -181,3 +181,21 @@ def assert_parity(rep: dict, label: str = ""):
     c = rep["counts"]
     msg = f"{label} {c} first clean mismatches {rep['bad_clean'][:5]} flagged {rep['bad_flag'][:5]}"
     assert c["clean_mismatch"] == 0 and c["flagged_unacceptable"] == 0, msg
+
+
+def hit_match(orc: dict, gpu_dist: np.ndarray, tol_m: float = 1e-3) -> np.ndarray:
+    """Per ray: the GPU answer matches the oracle's hit distance within
+    `tol_m` metres, or both miss (the hit-distance criterion of the paper's
+    accuracy section, 1 mm absolute)."""
+    t = orc["t"]
+    d = np.asarray(gpu_dist, np.float64)
+    both_miss = np.isinf(t) & np.isinf(d)
+    close = np.isfinite(t) & np.isfinite(d) & (np.abs(d - t) <= tol_m)
+    return both_miss | close
+
+
+def sort_keys(dist: np.ndarray, tri: np.ndarray) -> np.ndarray:
+    """The 64-bit closest-hit keys (order-preserving distance bits above the
+    triangle id) of distances >= 0 (or +inf) and ids, as uint64."""
+    b = np.asarray(dist, np.float32).view(np.uint32).astype(np.uint64) | np.uint64(0x80000000)
+    return (b << np.uint64(32)) | np.asarray(tri, np.uint32).astype(np.uint64)

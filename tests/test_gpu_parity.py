@@ -250,6 +250,35 @@ def test_azimuth_noise_and_ray_mask(ctx):
         ctx.sensor_config(6, dict(s, azimuth_offset=np.full(512, 2 * step, np.float32)), 0)
 
 
+def test_elevation_noise_crossing_channels(ctx):
+    _say("per-channel elevation offsets (vertical noise) that make neighbouring channels "
+         "cross, with azimuth offsets on top: oracle parity and culled == all-pairs")
+    wl = synth.config1()
+    v, f = wl.scene.vertices, wl.scene.indices
+    s = wl.sensors[0]
+    rng = np.random.default_rng(21)
+    step = float(s["elevation"][1] - s["elevation"][0])
+    alt = np.where(np.arange(32) % 2 == 0, 1.0, -1.0)
+    eo = (alt * rng.uniform(0.55, 0.9, 32) * step).astype(np.float32)
+    pert = s["elevation"].astype(np.float64) + eo
+    assert np.any(np.diff(pert) < 0)
+    az = rng.uniform(-0.4, 0.4, 512).astype(np.float32) * float(s["fov"]) / 512
+    noisy = dict(s, elevation_offset=eo, azimuth_offset=az)
+    ctx.scene_update(0, v, f)
+    rep, d, t = _parity(ctx, noisy, v, f, sensor_id=7, label="elevation noise")
+    assert rep["counts"]["hits"] > 5000
+    # a full-sphere grid with offsets of a full channel step at random
+    full = synth.sensor((0.4, -0.3, 1.7), 0.9, synth.elevations_full_sphere(24), 128, 360.0,
+                        0.05, 80.0)
+    st = float(full["elevation"][1] - full["elevation"][0])
+    eo2 = (rng.uniform(-1.0, 1.0, 24) * st).astype(np.float32)
+    eo2[0] = max(eo2[0], 0.0)   # channels 0 and 23 sit at -90 and +82.5 degrees:
+    eo2[-1] = min(eo2[-1], 0.9 * st)  # stay within [-pi/2, pi/2]
+    _parity(ctx, dict(full, elevation_offset=eo2), v, f, sensor_id=8, label="full-sphere noise")
+    with pytest.raises(grca.GrcaError):
+        ctx.sensor_config(9, dict(full, elevation_offset=np.full(24, -0.5, np.float32)), 0)
+
+
 def test_colocated_heads(ctx):
     _say("co-located heads: 2 rigs of 4 x 90-degree heads (one head with a shorter range), "
          "one cast vs all-pairs per head and the oracle")
