@@ -149,6 +149,9 @@ def main():
     ap.add_argument("--ranges", default="10,50,100",
                     help="range_max values (m) of the range-culling sweep ('' to skip)")
     ap.add_argument("--range-steps", type=int, default=10)
+    ap.add_argument("--origin-sweep", type=int, default=0,
+                    help="also time frames of 1..N full-turn 128x4096 heads on the same scene, "
+                         "distributed over the ring's origins vs sharing the first one")
     ap.add_argument("--tuning", default="auto",
                     help="JSON file of grca options; 'auto' (default) takes the autotuner's "
                          "saved result for this GPU and workload if there is one, 'none' the "
@@ -409,6 +412,10 @@ def main():
                "parity_on_sample": {"violations": int(bad), **counts}}
         log(f"cpu oracle: {tot_rays} rays in {t_cpu:.1f}s on {threads} threads; parity {counts} bad={bad}")
 
+    origins = None
+    if args.origin_sweep > 0:
+        origins = origin_sweep(torch, ctx, stream, wl, mats, dist, tri, args)
+
     lossy = None
     if not args.no_lossy and samples:
         lossy = lossy_leg(torch, ctx, stream, wl, ids, sizes, mats, samples, args, dist, tri)
@@ -445,6 +452,8 @@ def main():
         "cpu_baseline": cpu,
         "lossy": lossy,
     }
+    if origins is not None:
+        out["origin_sweep"] = origins
     ctx.close()
     out["serving"] = serving_leg(args.serving_seconds) if args.serving_seconds > 0 else None
     print(json.dumps(out), flush=True)
@@ -519,6 +528,46 @@ def lossy_leg(torch, ctx, stream, wl, ids, sizes, mats, samples, args, dist, tri
                      f"oracle, or both miss")
     out["eps_area"] = ctx.get_options()["eps_area"]
     return out
+
+
+def origin_sweep(torch, ctx, stream, wl, mats, dist, tri, args) -> dict:
+    """Frames of 1..N full-turn 128x4096 heads on the workload's scene: one
+    upright head at each of the first N ring origins (distributed), or N
+    independently oriented heads sharing the first origin (co-located).  The
+    paper's co-location experiment, on this scene; mean batched frame time
+    and the pass's work counts."""
+    from paper_2605_10457_amd import grca, synth
+    origins = [s["origin"] for s in wl.sensors]
+    kmax = min(args.origin_sweep, len(origins), dist.numel() // (128 * 4096))
+    res = {"distributed": {}, "colocated": {}}
+    for mode in res:
+        for om in range(1, kmax + 1):
+            sens = (synth.distributed_heads(origins[:om]) if mode == "distributed"
+                    else synth.oriented_heads(origins[0], om))
+            ids_s = list(range(300, 300 + om))
+            for i, s in zip(ids_s, sens):
+                ctx.sensor_config(i, s, 0)
+            n = om * 128 * 4096
+            fr = grca.grca_frame_create(ctx.h, 0, ids_s, dist[:n], tri[:n])
+            for i in range(2):
+                grca.grca_frame_launch(ctx.h, fr, mats[i], synth.deform_time(i), stream)
+                grca.grca_frame_synchronize(ctx.h, fr, stream)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.range_steps)]
+            for k in range(args.range_steps):
+                f = args.warmup + k
+                ev[k][0].record(stream)
+                grca.grca_frame_launch(ctx.h, fr, mats[f], synth.deform_time(f), stream)
+                ev[k][1].record(stream)
+            torch.cuda.synchronize()
+            grca.grca_frame_synchronize(ctx.h, fr, stream)
+            st = ctx.last_stats()
+            ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+            res[mode][str(om)] = {"ms": ms, "sphere_tests": st["sphere_tests"],
+                                  "spans": st["pairs_evaluated"], "rtic": st["rtic"]}
+            log(f"origin sweep {mode} x{om}: {res[mode][str(om)]}")
+            grca.grca_frame_destroy(fr)
+    return res
 
 
 def serving_leg(seconds: float) -> dict:

@@ -383,6 +383,18 @@ DevSensor sensor_record(const SensorData& S) {
   d.elev0_g = d.elev0 * d.inv_delev;
   d.az_noise = S.az_noise;
   d.el_noise = S.el_noise;
+  d.fov_mode = 0;
+  if (!S.wrap) {
+    const double m = 1e-4 + S.az_noise;
+    const double lo = theta0 - m, hi = theta0 + (d.chi - 1u) * S.dtheta + m;
+    if (hi - lo < kTwoPi) {
+      d.fov_mode = hi - lo <= 0.5 * kTwoPi ? 1u : 2u;
+      d.fov_n[0] = (float)-std::sin(lo);
+      d.fov_n[1] = (float)std::cos(lo);
+      d.fov_n[2] = (float)std::sin(hi);
+      d.fov_n[3] = (float)-std::cos(hi);
+    }
+  }
   d.key_offset = 0;
   d.scene = 0;
   d.cull_back = 0;

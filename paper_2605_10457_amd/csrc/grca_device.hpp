@@ -8,6 +8,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace grca {
@@ -41,9 +42,14 @@ struct ChanBin {
 
 // Per-cast sensor descriptor (device memory; read with wave-uniform indices,
 // except in the span phase of the bounds pass, where each lane reads its own).
-struct DevSensor {
+struct alignas(16) DevSensor {
   float o[3], f[3], r[3], u[3];
   float dmin, dmax;
+  // max |elevation offset| (radians), widens every channel span; the paper's
+  // lossy accelerations enabled for this cast (GRCA_LOSSY_* bits, 0 in an
+  // exact cast).  Next to the range, so the span reads them in one load.
+  float el_noise;
+  uint32_t lossy;
   uint32_t gamma, chi;
   uint32_t key_offset; // O_n: first output slot of this sensor
   uint32_t wrap;       // 1: full spin, azimuth index wraps mod chi
@@ -62,7 +68,6 @@ struct DevSensor {
   const float2* az;     // (cos theta_R, sin theta_R), FP32 (offsets included)
   const uint8_t* mask;  // optional active-ray mask at C * chi + R (nullptr: all on)
   float az_noise;       // max |azimuth offset| (radians), widens every azimuth span
-  float el_noise;       // max |elevation offset| (radians), widens every channel span
   // the channel elevations as a uniform grid, for the first test of the
   // bounds pass: every channel j lies within elev_tol of elev0 + j / inv_delev
   float elev0, inv_delev, elev_tol;
@@ -71,11 +76,22 @@ struct DevSensor {
   // (dmin (1 + 1e-5), dmax (1 - 1e-5))), the elevation margin 2e-5 +
   // elev_tol, the last channel index gamma - 1 and elev0 * inv_delev
   float cull_dmax, in_dmax, in_dmin, elev_m, last_chan, elev0_g;
-  // the paper's lossy accelerations enabled for this cast (GRCA_LOSSY_* bits;
-  // 0 in an exact cast) and the apparent-area threshold epsilon_A
-  uint32_t lossy;
-  float eps_area;
+  float eps_area;  // the apparent-area threshold epsilon_A of GRCA_LOSSY_AREA
+  // a partial field of view as the wedge between two vertical planes through
+  // the origin, for the sphere tests: fov_mode 0 = no test (full spin, or a
+  // wedge that the margins widen to a full turn), 1 = the wedge is convex
+  // (at most pi wide: the intersection of the planes' inner half-spaces),
+  // 2 = wider (their union); fov_n = the inward unit normals (f and r
+  // components) of the start and end planes, each turned outward by 1e-4 rad
+  // plus the azimuth noise
+  uint32_t fov_mode;
+  float fov_n[4];
 };
+
+static_assert(sizeof(DevSensor) % 16 == 0 && offsetof(DevSensor, dmin) % 16 == 0 &&
+                  offsetof(DevSensor, lossy) ==
+                  offsetof(DevSensor, dmin) + 12,
+              "range, vertical noise and lossy bits form one aligned 16-byte block");
 
 // Triangles per tile of the bounds pass: one wave, two triangles per lane.
 constexpr uint32_t BOUNDS_TILE = 128;
@@ -244,7 +260,9 @@ __device__ inline unsigned long long ray_test(const Statics& st, float cphi, flo
   const float w1 = fmaf(st.n1x, dx, fmaf(st.n1y, dy, st.n1z * dz));
   const float w2 = fmaf(st.n2x, dx, fmaf(st.n2y, dy, st.n2z * dz));
   const float c = fmaf(st.Nx, dx, fmaf(st.Ny, dy, st.Nz * dz));
-  if (w0 >= 0.0f && w1 >= 0.0f && w2 >= 0.0f && c > 0.0f) {
+  // (the statics of a valid pair are finite, so the minimum of the three
+  // barycentric numerators is a plain comparison)
+  if (fminf(fminf(w0, w1), w2) >= 0.0f && c > 0.0f) {
     // hardware reciprocal (1 ulp) and one rounded product: t within 2 ulps
     // of h / c, the same at every call site
     const float t = st.h * __builtin_amdgcn_rcpf(c);

@@ -358,8 +358,12 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
     z[k] = fmaf(dx, s.u[0], fmaf(dy, s.u[1], dz * s.u[2]));
     r2[k] = fmaf(x[k], x[k], fmaf(y[k], y[k], z[k] * z[k]));
   }
+  // range, vertical noise and lossy bits in one 16-byte load
+  const float4 rn = *reinterpret_cast<const float4*>(&s.dmin);
+  const float dmin = rn.x, dmax = rn.y, el_noise = rn.z;
   // the opt-in lossy apparent-area cull (the same for every lane of a cast)
-  if ((s.lossy & GRCA_LOSSY_AREA) && below_apparent_area(x, y, z, s.eps_area)) return false;
+  if ((__float_as_uint(rn.w) & GRCA_LOSSY_AREA) && below_apparent_area(x, y, z, s.eps_area))
+    return false;
   // Vertical axis through the origin vs the triangle's horizontal projection
   // (first, so that the world-space vertices and the sensor's f and r are
   // not needed past this point).
@@ -392,7 +396,6 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
   }
   // range prefilter: the triangle lies inside the blind ball (convex), or its
   // bounding sphere lies beyond range_max.
-  const float dmin = s.dmin, dmax = s.dmax;
   if (need_range) {
     const float r2max = fmaxf(r2[0], fmaxf(r2[1], r2[2]));
     if (r2max < dmin * dmin * (1.0f - 1e-5f)) return false;
@@ -451,8 +454,8 @@ __device__ inline bool span_of(const float (&vx)[3], const float (&vy)[3], const
   }
   const float smax_abs = fmaxf(fabsf(s_lo), fabsf(s_hi));
   // (vertical noise: |sin(phi + o) - sin(phi)| <= |o|)
-  s_lo -= ETA_SIN + s.el_noise;
-  s_hi += ETA_SIN + s.el_noise;
+  s_lo -= ETA_SIN + el_noise;
+  s_hi += ETA_SIN + el_noise;
   // both bin loads in flight together
   const ChanBin e_lo = load_bin(s.bins + chan_bin(s, s_lo));
   const ChanBin e_hi = load_bin(s.bins + chan_bin(s, s_hi));
@@ -740,19 +743,42 @@ struct GroupVerdict {
   bool culled;      // no ray of the sensor can reach the group
   bool need_range;  // the group straddles range_min or range_max: test triangles
   bool need_pole;   // the group touches the vertical axis through the origin
+  bool need_fov;    // (AZ) the group straddles the edge of a partial field of view
 };
+
+// A sphere (centre at local lf, lr; distance D from the origin; radius r
+// widened) against the wedge of a partial field of view: `out` when it lies
+// wholly outside (no ray of the sensor can reach it), `in` when wholly
+// inside.  The signed distance of the centre from each bounding plane is one
+// dot product with the plane's inward normal, and every point of the sphere
+// lies within r of it.  The margin 1e-5 D covers the FP32 error of the local
+// frame and of the rounded normals (under 1e-6 D); the widening of the wedge
+// by 1e-4 rad covers the rounded ray directions.  NaN (D = 0) gives neither.
+struct FovVerdict {
+  bool out, in;
+};
+__device__ inline FovVerdict fov_verdict(float lf, float lr, float D, float r,
+                                         const DevSensor& s) {
+  const float a1 = fmaf(s.fov_n[0], lf, s.fov_n[1] * lr);
+  const float a2 = fmaf(s.fov_n[2], lf, s.fov_n[3] * lr);
+  const float rp = fmaf(1e-5f, D, r + 1e-6f);
+  const bool o1 = a1 < -rp, o2 = a2 < -rp, i1 = a1 > rp, i2 = a2 > rp;
+  const bool convex = s.fov_mode == 1u;
+  FovVerdict v;
+  v.out = s.fov_mode != 0u && (convex ? (o1 || o2) : (o1 && o2));
+  v.in = s.fov_mode == 0u || (convex ? (i1 && i2) : (i1 || i2));
+  return v;
+}
 
 // A bounding sphere (centre c, radius rad) against sensor `s`, without
 // memory access besides the sensor's fields and without branches (so that
-// the fields are read together); about 70 FP32 operations, 100 with AZ.
+// the fields are read together); about 70 FP32 operations, 80 with AZ.
 // Culled when the sphere lies beyond range_max, when no channel elevation
 // lies within alpha of the elevation of c, or (AZ, partial field of view)
-// when the azimuths it subtends miss the field of view.  For
+// when it lies outside the field of view's wedge.  For
 // sin(alpha) = r / D <= 1/2 every point of the sphere is within the angle
 // alpha <= asin(r / D) <= (r / D)(1 + (r / D)^2 / 3) of c's direction, so its
-// elevation is within alpha of c's; its azimuth is within asin(r / h) <=
-// 1.0472 r / h of c's when r / h <= 1/2 (h: c's distance from the vertical
-// axis).  The channels are taken as the uniform grid elev0 + j / inv_delev,
+// elevation is within alpha of c's.  The channels are taken as the uniform grid elev0 + j / inv_delev,
 // widened by elev_tol (the table's largest distance from that grid); the
 // margins cover the FP32 error of c's angles and of the ray test.
 // need_range: the sphere straddles range_min or range_max; need_pole: it
@@ -790,15 +816,11 @@ __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float r
   // with negated comparisons, so that a NaN keeps the sphere
   const bool band = (uint32_t)!(j_lo > j_hi) & (uint32_t)!(j_lo > s.last_chan) &
                     (uint32_t)!(j_hi < 0.0f);
-  uint32_t out_fov = 0u;
+  uint32_t out_fov = 0u, in_fov = 1u;
   if (AZ) {
-    const float beta = 1.0472f * r * __builtin_amdgcn_rcpf(hc) + 1e-4f + s.az_noise;
-    const float az = atan2_bounded(lr, lf);
-    const float half = 0.5f * (float)(s.chi - 1u) * __builtin_amdgcn_rcpf(s.inv_dtheta);
-    float d = az - (s.theta_start + half);
-    d -= TWO_PI_F * floorf((d + PI_F) * (1.0f / TWO_PI_F));
-    out_fov = (uint32_t)(s.wrap == 0u) & (uint32_t)(hc > 2.0f * r) &
-              (uint32_t)(fabsf(d) > half * 1.0001f + beta + 1e-4f);
+    const FovVerdict fv = fov_verdict(lf, lr, D, r, s);
+    out_fov = (uint32_t)fv.out;
+    in_fov = (uint32_t)fv.in;
   }
   // (bitwise: a short-circuit would add branches)
   const uint32_t far = (uint32_t)!near;
@@ -806,6 +828,7 @@ __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float r
   v.culled = (far & ((uint32_t)beyond | (uint32_t)!band | out_fov)) != 0u;
   v.need_range = ((uint32_t)near | (uint32_t)!inside) != 0u;
   v.need_pole = !(h2 > r2 * 1.0001f);
+  v.need_fov = in_fov == 0u;
   return v;
 }
 
@@ -1002,7 +1025,7 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
     gs[3] = first_lane(__builtin_amdgcn_sqrtf(wave_max_dpp(gr2)));
   }
   unsigned long long rtic = 0ull;  // candidates tested inline by this lane
-  unsigned long long g_cull = 0ull, g_range = ~0ull, g_pole = ~0ull;
+  unsigned long long g_cull = 0ull, g_range = ~0ull, g_pole = ~0ull, g_fov = 0ull;
   uint32_t tested = 0;     // triangle sphere tests of this wave (wave-uniform statistic)
   uint32_t evaluated = 0;  // spans computed by this wave (wave-uniform statistic)
   uint32_t head = 0, tail = 0;  // pairs taken from / queued into the ring
@@ -1015,22 +1038,32 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
         // the tile's verdicts for the next 64 sensors in one pass: lane k
         // tests sensor n + k
         const uint32_t ns = n + lane;
-        bool cul = false, nr = true, np = true;
+        bool cul = false, nr = true, np = true, nf = false;
         if (group_cull && ns < s_end) {
           const GroupVerdict gv = sphere_test<true>(gs[0], gs[1], gs[2], gs[3], sens[ns]);
           cul = gv.culled;
           nr = gv.need_range;
           np = gv.need_pole;
+          nf = gv.need_fov;
         }
         g_cull = first_lane(__ballot(cul));
         g_range = first_lane(__ballot(nr));
         g_pole = first_lane(__ballot(np));
+        g_fov = first_lane(__ballot(nf));
       }
       if (!((g_cull >> ln) & 1ull)) {  // wave-uniform
-        // both triangles of every lane (no branch: the sensor's fields are read once)
+        // both triangles of every lane (no branch: the sensor's fields are
+        // read once); where the tile straddles the edge of a partial field
+        // of view, the triangles' own azimuths are tested too
         const DevSensor& s = sens[n];
-        const GroupVerdict v0 = sphere_test<false>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s);
-        const GroupVerdict v1 = sphere_test<false>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s);
+        GroupVerdict v0, v1;
+        if ((g_fov >> ln) & 1ull) {
+          v0 = sphere_test<true>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s);
+          v1 = sphere_test<true>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s);
+        } else {
+          v0 = sphere_test<false>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s);
+          v1 = sphere_test<false>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s);
+        }
         tested += n_active;
         const bool gr = (g_range >> ln) & 1ull, gp = (g_pole >> ln) & 1ull;
         const bool keep0 = active[0] && !v0.culled;
@@ -1534,12 +1567,11 @@ __device__ inline Cand cand_read(int own, uint32_t f, const ItemInfo* in_w,
   // product below stays under 2^25: 24-bit multiplies.
   const uint32_t r_count = inf.rs & 0xFFFFu;
   const uint32_t local = (uint32_t)((int32_t)f + inf.bias);
-  uint32_t c = 0;
-  if (local >= r_count) {
-    c = (uint32_t)((float)local * inf.inv_rc);
-    if (__umul24(c, r_count) > local) --c;
-    else if (__umul24(c + 1, r_count) <= local) ++c;
-  }
+  // within 1 of the quotient (0 for local < r_count); two branch-free
+  // corrections make it exact
+  uint32_t c = (uint32_t)((float)local * inf.inv_rc);
+  c -= (uint32_t)(__umul24(c, r_count) > local);
+  c += (uint32_t)(__umul24(c + 1u, r_count) <= local);
   const uint32_t r = local - __umul24(c, r_count);
   const uint32_t ch = (inf.cr & 0xFFFFu) + c;
   uint32_t ray = (inf.cr >> 16) + r;
@@ -1551,9 +1583,11 @@ __device__ inline Cand cand_read(int own, uint32_t f, const ItemInfo* in_w,
   o.cp = gload_f2(sn.chan, ch * 8u);
   o.ca = gload_f2(sn.az, ray * 8u);
   o.kidx = sn.key_offset + gl;
-  // a single-copy-atomic read: another wave's atomicMin may land at any time
+  // a single-copy-atomic read: another wave's atomicMin may land at any time.
+  // Workgroup scope lets it hit a stale cache line; keys only decrease, so a
+  // stale value is never below the current one and only costs a redundant atomic.
   o.seen = __hip_atomic_load(const_cast<unsigned long long*>(keys) + o.kidx, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
   return o;
 }
 // The ray test against the owner's statics, and the atomic for a hit that
@@ -1578,15 +1612,20 @@ __device__ inline uint32_t cand_finish(const Cand& o, int own, const float4 (*st
   return 0u;
 }
 
-// Inclusive prefix maximum over the wave (identity -1) with DPP row shifts
-// and row broadcasts: no LDS round trips.
-__device__ inline int wave_incl_max(int v) {
-  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false));  // row_shr:1
-  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false));  // row_shr:2
-  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false));  // row_shr:4
-  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false));  // row_shr:8
-  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
-  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+// Inclusive prefix maximum over the wave of values >= 0, by DPP row shifts
+// and row broadcasts (no LDS round trips).  0 is the identity: lanes without
+// a source (bound_ctrl) and the rows a broadcast leaves out read 0, so each
+// step folds into one max instruction.
+__device__ inline uint32_t wave_incl_max0(uint32_t v) {
+#define GRCA_MAX0_STEP(CTRL, ROWS) \
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, true));
+  GRCA_MAX0_STEP(0x111, 0xf)  // row_shr:1
+  GRCA_MAX0_STEP(0x112, 0xf)  // row_shr:2
+  GRCA_MAX0_STEP(0x114, 0xf)  // row_shr:4
+  GRCA_MAX0_STEP(0x118, 0xf)  // row_shr:8
+  GRCA_MAX0_STEP(0x142, 0xa)  // row_bcast:15
+  GRCA_MAX0_STEP(0x143, 0xc)  // row_bcast:31
+#undef GRCA_MAX0_STEP
   return v;
 }
 
@@ -1627,7 +1666,7 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
     unsigned long long* __restrict__ keys) {
   __shared__ float4 st_s[WPB][3][64];  // the staged items' normals n0, n1, n2, N
   __shared__ ItemInfo in_s[WPB][64];
-  __shared__ int mark_s[WPB][64 * ISECT_SLOTS];
+  __shared__ uint32_t mark_s[WPB][64 * ISECT_SLOTS];  // owner + 1 at its first position, else 0
   __shared__ IsectSensor sen_s[64];
   const uint32_t w = wave_id();
   const uint32_t lane = lane_id();
@@ -1712,18 +1751,19 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
         // previous window's owner.  Each lane takes the positions p + 64 j:
         // all its candidates' table and key reads are in flight together.
         constexpr uint32_t WIN = 64u * ISECT_SLOTS;
-        int carry = -1;
+        uint32_t carry = 0;  // owner + 1 of the position before the window
         for (uint32_t base = 0; base < total; base += WIN) {
 #pragma unroll
-          for (int j = 0; j < ISECT_SLOTS; ++j) mark_s[w][64 * j + lane] = -1;
+          for (int j = 0; j < ISECT_SLOTS; ++j) mark_s[w][64 * j + lane] = 0u;
           wave_sync();
-          if (count && excl >= base && excl - base < WIN) mark_s[w][excl - base] = (int)lane;
+          if (count && excl >= base && excl - base < WIN) mark_s[w][excl - base] = lane + 1u;
           wave_sync();
           int own[ISECT_SLOTS];
 #pragma unroll
           for (int j = 0; j < ISECT_SLOTS; ++j) {
-            own[j] = max(wave_incl_max(mark_s[w][64 * j + lane]), carry);
-            carry = __builtin_amdgcn_readlane(own[j], 63);
+            const uint32_t o1 = max(wave_incl_max0(mark_s[w][64 * j + lane]), carry);
+            carry = (uint32_t)__builtin_amdgcn_readlane((int)o1, 63);
+            own[j] = (int)o1 - 1;
           }
           wave_sync();
           if (base + lane >= total) continue;  // and every later position

@@ -510,6 +510,37 @@ def colocated_rig(origins, heads: int = 4, channels: int = 128, rays: int = 4096
     return out
 
 
+def oriented_heads(origin, n: int, channels: int = 128, rays: int = 4096,
+                   range_max: float = 1000.0, tilt_deg: float = 20.0):
+    """n full-turn heads sharing one origin, independently oriented: head k
+    turned by 2*pi*k/n about the vertical and, for odd k, its spin axis tilted
+    by tilt_deg towards its forward direction; full-vertical channel grid."""
+    out = []
+    for k in range(n):
+        yaw = 2 * math.pi * k / n
+        tau = math.radians(tilt_deg) if k % 2 else 0.0
+        f = np.array([math.cos(yaw) * math.cos(tau), math.sin(yaw) * math.cos(tau),
+                      math.sin(tau)])
+        u = np.array([-math.cos(yaw) * math.sin(tau), -math.sin(yaw) * math.sin(tau),
+                      math.cos(tau)])
+        s = sensor(origin, yaw, elevations_full_sphere(channels), rays, 360.0,
+                   range_max=range_max)
+        s["forward"] = f.astype(np.float32)
+        s["up"] = u.astype(np.float32)
+        s["right"] = np.cross(f, u).astype(np.float32)
+        out.append(s)
+    return out
+
+
+def distributed_heads(origins, channels: int = 128, rays: int = 4096,
+                      range_max: float = 1000.0):
+    """One upright full-turn head at each origin (yaw towards the origin's
+    azimuth), full-vertical channel grid: the distributed counterpart of
+    oriented_heads."""
+    return [sensor(o, math.atan2(float(o[1]), float(o[0])), elevations_full_sphere(channels),
+                   rays, 360.0, range_max=range_max) for o in origins]
+
+
 def config4_colocated(seed_extra: int = 0, range_max: float = 1000.0,
                       scale: float = 1.0) -> Workload:
     """Config 4's scene seen by 2 rigs of 4 co-located 90-degree heads of 128x4096

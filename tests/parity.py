@@ -190,7 +190,9 @@ def hit_match(orc: dict, gpu_dist: np.ndarray, tol_m: float = 1e-3) -> np.ndarra
     t = orc["t"]
     d = np.asarray(gpu_dist, np.float64)
     both_miss = np.isinf(t) & np.isinf(d)
-    close = np.isfinite(t) & np.isfinite(d) & (np.abs(d - t) <= tol_m)
+    fin = np.isfinite(t) & np.isfinite(d)
+    close = np.zeros_like(fin)
+    close[fin] = np.abs(d[fin] - t[fin]) <= tol_m
     return both_miss | close
 
 

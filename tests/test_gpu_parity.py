@@ -279,6 +279,61 @@ def test_elevation_noise_crossing_channels(ctx):
         ctx.sensor_config(9, dict(full, elevation_offset=np.full(24, -0.5, np.float32)), 0)
 
 
+def _cylinders(radii, n_az, rows, height):
+    """Vertical cylinder shells around the z axis: n_az x rows quads, two
+    triangles each, per radius."""
+    vs, fs, base = [], [], 0
+    th = np.linspace(0.0, 2 * math.pi, n_az, endpoint=False)
+    zs = np.linspace(-height / 2, height / 2, rows + 1)
+    for r in radii:
+        x = np.repeat(r * np.cos(th)[None, :], rows + 1, 0)
+        y = np.repeat(r * np.sin(th)[None, :], rows + 1, 0)
+        z = np.repeat(zs[:, None], n_az, 1)
+        vs.append(np.stack([x, y, z], -1).reshape(-1, 3))
+        i = np.arange(rows)[:, None] * n_az
+        j = np.arange(n_az)[None, :]
+        a = base + i + j
+        b = base + i + (j + 1) % n_az
+        c, d = a + n_az, b + n_az
+        fs.append(np.stack([np.stack([a, b, c], -1), np.stack([b, d, c], -1)], 2).reshape(-1, 3))
+        base += (rows + 1) * n_az
+    return np.concatenate(vs).astype(np.float32), np.concatenate(fs).astype(np.uint32)
+
+
+def test_fov_edges_all_pairs(ctx):
+    _say("partial fields of view (30 to 350 deg, with and without azimuth offsets) inside "
+         "cylinder shells that cross every field-of-view edge: one cast vs all-pairs per sensor")
+    v, f = _cylinders([2.5, 7.0, 19.0, 45.0], 720, 6, 12.0)
+    v[:, 0] += 0.13
+    v[:, 1] -= 0.07
+    ctx.scene_update(0, v, f)
+    rng = np.random.default_rng(11)
+    fovs = [30.0, 90.0, 179.0, 180.0, 181.0, 270.0, 350.0, 90.0]
+    sens = []
+    for k, fov in enumerate(fovs):
+        s = synth.sensor((0.0, 0.0, rng.uniform(-1.0, 1.0)), rng.uniform(-math.pi, math.pi),
+                         synth.elevations_uniform(-30, 30, 16), 720, fov, 0.05, 200.0)
+        if k % 2:
+            step = float(s["fov"]) / 720
+            s["azimuth_offset"] = (rng.uniform(-0.45, 0.45, 720) * step).astype(np.float32)
+        sens.append(s)
+    ids = list(range(40, 40 + len(sens)))
+    for i, s in zip(ids, sens):
+        ctx.sensor_config(i, s, 0)
+    n1 = 16 * 720
+    d, t = _cast(ctx, ids, len(ids) * n1)
+    for k, i in enumerate(ids):
+        d2, t2 = _cast(ctx, [i], n1, grca.GRCA_CAST_ALL_PAIRS)
+        sl = slice(k * n1, (k + 1) * n1)
+        assert np.array_equal(t[sl], t2), f"fov {fovs[k]}: culled != all-pairs"
+        assert np.array_equal(d[sl].view(np.uint32), d2.view(np.uint32))
+    orc = O.cast(sens[5], v, f, rays=np.arange(0, n1, 13))
+    sel = orc["rays"]
+    rep = parity.check(sens[5], v, f, orc, d[5 * n1:6 * n1][sel], t[5 * n1:6 * n1][sel])
+    parity.assert_parity(rep, "fov 270")
+    assert np.count_nonzero(t != grca.GRCA_MISS_TRI) > len(ids) * n1 // 2
+
+
 def test_colocated_heads(ctx):
     _say("co-located heads: 2 rigs of 4 x 90-degree heads (one head with a shorter range), "
          "one cast vs all-pairs per head and the oracle")
