@@ -112,7 +112,7 @@ const char* grca_last_error(const grca_context* ctx);
  * emitters, as vertex and index buffers (the per-triangle vertex data the
  * appendix's early pass reads once per frame).
  *  vertices_xyz: num_vertices * 3 FP32, xyz-interleaved.  Stored on the device
- *                as structure-of-arrays x[], y[], z[].
+ *                as 16-byte (x, y, z, 0) records, one load per vertex.
  *  indices:      num_triangles * 3 uint32; triangle k uses vertices
  *                indices[3k..3k+2] and is reported as id k.
  *  flags:        GRCA_MEM_DEVICE for device pointers; GRCA_UPDATE_VERTICES_ONLY
@@ -120,7 +120,7 @@ const char* grca_last_error(const grca_context* ctx);
  * Errors: INVALID_ARG for an index >= num_vertices, a non-finite coordinate
  * (host inputs are validated on the host; device inputs by a device pass
  * before the scene is replaced), num_triangles >= 2^28 or num_vertices >=
- * 2^30 (kernels address both by 32-bit byte offsets).  Synchronous with
+ * 2^28 (kernels address both by 32-bit byte offsets).  Synchronous with
  * respect to `hip_stream` for host inputs. */
 grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id, const float* vertices_xyz,
                               uint32_t num_vertices, const uint32_t* indices,

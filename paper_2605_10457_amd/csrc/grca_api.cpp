@@ -30,7 +30,7 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 struct SceneData {
   uint32_t nv = 0, ntri = 0;
-  float *x = nullptr, *y = nullptr, *z = nullptr;
+  float4* v = nullptr;       // vertex positions (x, y, z, 0)
   uint32_t* idx = nullptr;   // index triples in tile order (Morton within dynamic groups)
   uint32_t* orig = nullptr;  // caller triangle id of each stored slot
   // rigid instances
@@ -84,7 +84,7 @@ void dfree(T*& p) {
 }
 
 void free_scene(SceneData& s) {
-  dfree(s.x); dfree(s.y); dfree(s.z); dfree(s.idx); dfree(s.orig);
+  dfree(s.v); dfree(s.idx); dfree(s.orig);
   dfree(s.rr_x); dfree(s.rr_y); dfree(s.rr_z); dfree(s.rigid_blocks);
   dfree(s.dr_x); dfree(s.dr_y); dfree(s.dr_z);
   dfree(s.dn_x); dfree(s.dn_y); dfree(s.dn_z); dfree(s.dphase);
@@ -114,7 +114,7 @@ hipError_t reorder_scene_dev(SceneData& sc, hipStream_t st) {
   for (uint32_t g = 0; e == hipSuccess && g < sc.n_groups; ++g)
     e = launch_fill(vg + sc.groups[g].vertex_start, sc.groups[g].vertex_count,
                     1u + sc.n_inst + g, st);
-  if (e == hipSuccess) e = order_triangles(sc.idx, sc.orig, sc.ntri, sc.x, sc.y, sc.z, sc.nv, vg, st);
+  if (e == hipSuccess) e = order_triangles(sc.idx, sc.orig, sc.ntri, sc.v, sc.nv, vg, st);
   (void)hipStreamSynchronize(st);
   dfree(vg);
   return e;
@@ -447,7 +447,7 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
     if (k == 0 || sd[order[k - 1]]->desc.scene_id != sid) {
       const SceneData& sc = ctx->scenes.at(sid);
       DevScene ds{};
-      ds.x = sc.x; ds.y = sc.y; ds.z = sc.z; ds.idx = sc.idx; ds.orig = sc.orig;
+      ds.v = sc.v; ds.idx = sc.idx; ds.orig = sc.orig;
       ds.ntri = sc.ntri;
       ds.tile_start = tiles;
       ds.sensor_begin = k;
@@ -756,9 +756,10 @@ extern "C" grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id,
     const bool dev = flags & GRCA_MEM_DEVICE;
     const bool vonly = flags & GRCA_UPDATE_VERTICES_ONLY;
     if (num_vertices > 0 && !vertices_xyz) return fail(ctx, GRCA_ERR_INVALID_ARG, "vertices is NULL");
-    // the bounds pass addresses indices and vertices by 32-bit byte offsets
+    // the kernels address indices (12 B per triangle) and vertices (16 B
+    // each) by 32-bit byte offsets
     if (num_triangles >= (1u << 28)) return fail(ctx, GRCA_ERR_INVALID_ARG, "too many triangles");
-    if (num_vertices >= (1u << 30)) return fail(ctx, GRCA_ERR_INVALID_ARG, "too many vertices");
+    if (num_vertices >= (1u << 28)) return fail(ctx, GRCA_ERR_INVALID_ARG, "too many vertices");
     auto it = ctx->scenes.find(scene_id);
     if (vonly) {
       if (it == ctx->scenes.end()) return fail(ctx, GRCA_ERR_NOT_FOUND, "unknown scene");
@@ -796,25 +797,23 @@ extern "C" grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id,
     }
     SceneData fresh;
     SceneData& sc = (it == ctx->scenes.end()) ? fresh : it->second;
-    const bool realloc_v = sc.nv != num_vertices || !sc.x;
+    const bool realloc_v = sc.nv != num_vertices || !sc.v;
     if (!vonly && it != ctx->scenes.end()) {
       // topology change drops dynamic-geometry declarations
       HIPCHK(hipStreamSynchronize(st));
       SceneData keep;
-      keep.x = sc.x; keep.y = sc.y; keep.z = sc.z; keep.idx = sc.idx; keep.orig = sc.orig;
+      keep.v = sc.v; keep.idx = sc.idx; keep.orig = sc.orig;
       keep.nv = sc.nv; keep.ntri = sc.ntri;
-      sc.x = sc.y = sc.z = nullptr; sc.idx = nullptr; sc.orig = nullptr;
+      sc.v = nullptr; sc.idx = nullptr; sc.orig = nullptr;
       free_scene(sc);
       sc = SceneData();
-      sc.x = keep.x; sc.y = keep.y; sc.z = keep.z; sc.idx = keep.idx; sc.orig = keep.orig;
+      sc.v = keep.v; sc.idx = keep.idx; sc.orig = keep.orig;
       sc.nv = keep.nv; sc.ntri = keep.ntri;
     }
     if (realloc_v) {
       HIPCHK(hipStreamSynchronize(st));
-      dfree(sc.x); dfree(sc.y); dfree(sc.z);
-      HIPCHK(dmalloc(&sc.x, std::max(1u, num_vertices)));
-      HIPCHK(dmalloc(&sc.y, std::max(1u, num_vertices)));
-      HIPCHK(dmalloc(&sc.z, std::max(1u, num_vertices)));
+      dfree(sc.v);
+      HIPCHK(dmalloc(&sc.v, std::max(1u, num_vertices)));
     }
     float* tmp = nullptr;
     if (num_vertices) {
@@ -824,7 +823,7 @@ extern "C" grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id,
         HIPCHK(hipMemcpyAsync(tmp, vertices_xyz, 12ull * num_vertices, hipMemcpyHostToDevice, st));
         src = tmp;
       }
-      HIPCHK(launch_soa(src, num_vertices, sc.x, sc.y, sc.z, st));
+      HIPCHK(launch_pad(src, num_vertices, sc.v, st));
     }
     if (!vonly) {
       if (sc.ntri != num_triangles || !sc.idx) {
@@ -864,18 +863,14 @@ extern "C" grca_status grca_scene_download(grca_context* ctx, uint32_t scene_id,
     HIPCHK(hipSetDevice(ctx->device));
     const SceneData& sc = it->second;
     const size_t nv = sc.nv;
-    std::vector<float> x(nv), y(nv), z(nv);
+    std::vector<float4> v(nv);
     hipStream_t st = as_stream(hip_stream);
-    if (nv) {
-      HIPCHK(hipMemcpyAsync(x.data(), sc.x, 4 * nv, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(y.data(), sc.y, 4 * nv, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(z.data(), sc.z, 4 * nv, hipMemcpyDeviceToHost, st));
-    }
+    if (nv) HIPCHK(hipMemcpyAsync(v.data(), sc.v, 16 * nv, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (size_t i = 0; i < nv; ++i) {
-      vertices_xyz_host[3 * i] = x[i];
-      vertices_xyz_host[3 * i + 1] = y[i];
-      vertices_xyz_host[3 * i + 2] = z[i];
+      vertices_xyz_host[3 * i] = v[i].x;
+      vertices_xyz_host[3 * i + 1] = v[i].y;
+      vertices_xyz_host[3 * i + 2] = v[i].z;
     }
     return GRCA_OK;
   })
@@ -973,9 +968,8 @@ extern "C" grca_status grca_scene_set_rigid(grca_context* ctx, uint32_t scene_id
     HIPCHK(dmalloc(&sc.rr_z, std::max<uint64_t>(total, 1)));
     uint64_t r = 0;
     for (uint32_t i = 0; i < num_instances; ++i) {
-      HIPCHK(launch_copy(sc.x + vertex_start[i], sc.rr_x + r, vertex_count[i], st));
-      HIPCHK(launch_copy(sc.y + vertex_start[i], sc.rr_y + r, vertex_count[i], st));
-      HIPCHK(launch_copy(sc.z + vertex_start[i], sc.rr_z + r, vertex_count[i], st));
+      HIPCHK(launch_split(sc.v + vertex_start[i], vertex_count[i], sc.rr_x + r, sc.rr_y + r,
+                          sc.rr_z + r, st));
       r += vertex_count[i];
     }
     std::vector<PoseBlock> pb = pose_blocks(0, sc.inst_start, sc.inst_count);
@@ -1042,9 +1036,7 @@ extern "C" grca_status grca_scene_set_deform(grca_context* ctx, uint32_t scene_i
     }
     uint64_t r = 0;
     for (uint32_t g = 0; g < num_groups; ++g) {
-      HIPCHK(launch_copy(sc.x + st_v[g], sc.dr_x + r, ct_v[g], st));
-      HIPCHK(launch_copy(sc.y + st_v[g], sc.dr_y + r, ct_v[g], st));
-      HIPCHK(launch_copy(sc.z + st_v[g], sc.dr_z + r, ct_v[g], st));
+      HIPCHK(launch_split(sc.v + st_v[g], ct_v[g], sc.dr_x + r, sc.dr_y + r, sc.dr_z + r, st));
       r += ct_v[g];
     }
     std::vector<PoseBlock> pb = pose_blocks(1, st_v, ct_v);
@@ -1067,9 +1059,9 @@ extern "C" grca_status grca_scene_set_deform(grca_context* ctx, uint32_t scene_i
 namespace {
 grca_status enqueue_pose_kernels(grca_context* ctx, SceneData& sc, hipStream_t st) {
   HIPCHK(launch_pose(sc.rigid_blocks, sc.n_rigid_blocks, sc.rr_x, sc.rr_y, sc.rr_z, nullptr,
-                     nullptr, nullptr, nullptr, nullptr, sc.pose_in, sc.x, sc.y, sc.z, st));
+                     nullptr, nullptr, nullptr, nullptr, sc.pose_in, sc.v, st));
   HIPCHK(launch_pose(sc.deform_blocks, sc.n_deform_blocks, sc.dr_x, sc.dr_y, sc.dr_z, sc.dn_x,
-                     sc.dn_y, sc.dn_z, sc.dphase, sc.dparams, sc.pose_in, sc.x, sc.y, sc.z, st));
+                     sc.dn_y, sc.dn_z, sc.dphase, sc.dparams, sc.pose_in, sc.v, st));
   return GRCA_OK;
 }
 

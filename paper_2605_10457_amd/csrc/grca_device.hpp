@@ -97,9 +97,7 @@ static_assert(sizeof(DevSensor) % 16 == 0 && offsetof(DevSensor, dmin) % 16 == 0
 constexpr uint32_t BOUNDS_TILE = 128;
 
 struct DevScene {
-  const float* x;
-  const float* y;
-  const float* z;
+  const float4* v;       // vertex positions (x, y, z, 0): one 16-byte load per vertex
   const uint32_t* idx;   // index triples in tile order
   const uint32_t* orig;  // caller triangle id of each stored slot (keys and outputs use it)
   uint32_t ntri;

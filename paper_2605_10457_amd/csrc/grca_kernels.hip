@@ -71,6 +71,15 @@ __device__ inline T gload(const T* base, uint32_t byte_off) {
   return *(GT*)((GC*)base + byte_off);
 }
 
+// A vertex (x, y, z; the fourth component is padding) at a 32-bit byte offset.
+__device__ inline float4 gload_v(const float4* base, uint32_t byte_off) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  typedef const v4f __attribute__((address_space(1))) GT;
+  typedef const char __attribute__((address_space(1))) GC;
+  const v4f q = *(GT*)((GC*)base + byte_off);
+  return make_float4(q.x, q.y, q.z, q.w);
+}
+
 __device__ inline float2 gload_f2(const float2* base, uint32_t byte_off) {
   const unsigned long long v = gload(reinterpret_cast<const unsigned long long*>(base), byte_off);
   return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
@@ -948,7 +957,7 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
   // the lane's two triangles; lanes past the scene's last triangle load the
   // tile's first one (no branch) and are masked.  Loads take the arrays'
   // scalar bases and 32-bit byte offsets (the library keeps every scene
-  // under 2^28 triangles and 2^30 vertices).
+  // under 2^28 triangles and 2^28 vertices).
   float v[2][9];
   bool active[2];
 #pragma unroll
@@ -961,9 +970,10 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
     for (int k = 0; k < 3; ++k) id[k] = gload(S.idx, (3u * tt + (uint32_t)k) * 4u);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      v[h][3 * k] = gload(S.x, id[k] * 4u);
-      v[h][3 * k + 1] = gload(S.y, id[k] * 4u);
-      v[h][3 * k + 2] = gload(S.z, id[k] * 4u);
+      const float4 p = gload_v(S.v, id[k] * 16u);
+      v[h][3 * k] = p.x;
+      v[h][3 * k + 1] = p.y;
+      v[h][3 * k + 2] = p.z;
     }
   }
   // bounding spheres (AABB centre, largest vertex distance) of the lane's
@@ -1370,10 +1380,10 @@ __global__ __launch_bounds__(WPB * 64) void expand_kernel(
       const DevScene& S = scenes[s.scene];
       const uint32_t t = L.tri;
       const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
+      const float4 p0 = S.v[i0], p1 = S.v[i1], p2 = S.v[i2];
       Statics st;
       double nrm[3][3];
-      if (!make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
-                        S.z[i2], s, st, nrm))
+      if (!make_statics(p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z, s, st, nrm))
         continue;
       // the three edge planes' angles, lane k computing edge k (one atan2
       // and one sqrt in the instruction stream instead of three each; the
@@ -1476,9 +1486,7 @@ struct IsectSensor {
   const uint8_t* mask;
   const uint32_t* idx;
   const uint32_t* orig;
-  const float* x;
-  const float* y;
-  const float* z;
+  const float4* v;
   float o[3], f[3], r[3], u[3];
   int32_t cull_back;
   uint32_t chi, key_offset;
@@ -1489,7 +1497,7 @@ __device__ inline IsectSensor isect_sensor(const DevScene* scenes, const DevSens
   const DevScene& S = scenes[s.scene];
   IsectSensor q;
   q.chan = s.chan; q.az = s.az; q.mask = s.mask;
-  q.idx = S.idx; q.orig = S.orig; q.x = S.x; q.y = S.y; q.z = S.z;
+  q.idx = S.idx; q.orig = S.orig; q.v = S.v;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     q.o[k] = s.o[k]; q.f[k] = s.f[k]; q.r[k] = s.r[k]; q.u[k] = s.u[k];
@@ -1717,11 +1725,10 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
             const uint32_t t = it.tri;
             const uint32_t v0 = gload(sq.idx, 12u * t), v1 = gload(sq.idx, 12u * t + 4u),
                            v2 = gload(sq.idx, 12u * t + 8u);
+            const float4 p0 = gload_v(sq.v, 16u * v0), p1 = gload_v(sq.v, 16u * v1),
+                         p2 = gload_v(sq.v, 16u * v2);
             Statics st;
-            if (make_statics(gload(sq.x, 4u * v0), gload(sq.y, 4u * v0), gload(sq.z, 4u * v0),
-                             gload(sq.x, 4u * v1), gload(sq.y, 4u * v1), gload(sq.z, 4u * v1),
-                             gload(sq.x, 4u * v2), gload(sq.y, 4u * v2), gload(sq.z, 4u * v2),
-                             sq, st)) {
+            if (make_statics(p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z, sq, st)) {
               count = hi - lo;
               st_s[w][0][lane] = make_float4(st.n0x, st.n0y, st.n0z, st.n1x);
               st_s[w][1][lane] = make_float4(st.n1y, st.n1z, st.n2x, st.n2y);
@@ -1797,9 +1804,9 @@ __global__ void statics_kernel(const DevScene* __restrict__ scenes, const DevSen
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= S.ntri) return;
   const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
+  const float4 p0 = S.v[i0], p1 = S.v[i1], p2 = S.v[i2];
   Statics st;
-  if (!make_statics(S.x[i0], S.y[i0], S.z[i0], S.x[i1], S.y[i1], S.z[i1], S.x[i2], S.y[i2],
-                    S.z[i2], s, st)) {
+  if (!make_statics(p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z, s, st)) {
     st = Statics{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1.0f, 0, 0, 0};
   }
   out[S.orig[t]] = st;  // the all-pairs pass walks the caller's triangle ids
@@ -1924,7 +1931,7 @@ __global__ __launch_bounds__(256) void pose_kernel(
     const float* __restrict__ ry, const float* __restrict__ rz, const float* __restrict__ nx,
     const float* __restrict__ ny, const float* __restrict__ nz, const float* __restrict__ phase,
     const DeformParam* __restrict__ groups, const double* __restrict__ pose_in,
-    float* __restrict__ x, float* __restrict__ y, float* __restrict__ z) {
+    float4* __restrict__ out) {
   const PoseBlock pb = blocks[blockIdx.x];
   const uint32_t i = threadIdx.x;
   if (i >= pb.count) return;
@@ -1933,16 +1940,17 @@ __global__ __launch_bounds__(256) void pose_kernel(
   const double px = rx[r], py = ry[r], pz = rz[r];
   if (pb.kind == 0) {
     const float* M = reinterpret_cast<const float*>(pose_in + 1) + 12ull * pb.group;
-    x[v] = (float)((double)M[0] * px + (double)M[1] * py + (double)M[2] * pz + (double)M[3]);
-    y[v] = (float)((double)M[4] * px + (double)M[5] * py + (double)M[6] * pz + (double)M[7]);
-    z[v] = (float)((double)M[8] * px + (double)M[9] * py + (double)M[10] * pz + (double)M[11]);
+    out[v] = make_float4(
+        (float)((double)M[0] * px + (double)M[1] * py + (double)M[2] * pz + (double)M[3]),
+        (float)((double)M[4] * px + (double)M[5] * py + (double)M[6] * pz + (double)M[7]),
+        (float)((double)M[8] * px + (double)M[9] * py + (double)M[10] * pz + (double)M[11]),
+        0.0f);
   } else {
     const DeformParam g = groups[pb.group];
     const double time = pose_in[0];
     const double wv = (double)g.amplitude * sin((double)g.omega * time + (double)phase[r]);
-    x[v] = (float)(px + wv * (double)nx[r]);
-    y[v] = (float)(py + wv * (double)ny[r]);
-    z[v] = (float)(pz + wv * (double)nz[r]);
+    out[v] = make_float4((float)(px + wv * (double)nx[r]), (float)(py + wv * (double)ny[r]),
+                         (float)(pz + wv * (double)nz[r]), 0.0f);
   }
 }
 
@@ -1999,19 +2007,20 @@ __global__ void validate_kernel(const float* __restrict__ xyz, uint32_t nv,
   if (idx && i < nidx && idx[i] >= nv) atomicOr(bad, 2u);
 }
 
-__global__ void soa_kernel(const float* __restrict__ xyz, uint32_t nv, float* __restrict__ x,
-                           float* __restrict__ y, float* __restrict__ z) {
+__global__ void pad_kernel(const float* __restrict__ xyz, uint32_t nv, float4* __restrict__ v) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nv) return;
-  x[i] = xyz[3ull * i];
-  y[i] = xyz[3ull * i + 1];
-  z[i] = xyz[3ull * i + 2];
+  v[i] = make_float4(xyz[3ull * i], xyz[3ull * i + 1], xyz[3ull * i + 2], 0.0f);
 }
 
-__global__ void copy_range_kernel(const float* __restrict__ src, float* __restrict__ dst,
-                                  uint32_t n) {
+__global__ void split_kernel(const float4* __restrict__ v, uint32_t n, float* __restrict__ x,
+                             float* __restrict__ y, float* __restrict__ z) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[i];
+  if (i >= n) return;
+  const float4 p = v[i];
+  x[i] = p.x;
+  y[i] = p.y;
+  z[i] = p.z;
 }
 
 // ================================================================== launchers
@@ -2113,10 +2122,10 @@ hipError_t launch_resolve(const unsigned long long* keys, uint32_t n, float* dis
 hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* rx, const float* ry,
                        const float* rz, const float* nx, const float* ny, const float* nz,
                        const float* phase, const DeformParam* groups, const double* pose_in,
-                       float* x, float* y, float* z, hipStream_t st) {
+                       float4* v, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
   hipLaunchKernelGGL(pose_kernel, dim3(nblocks), dim3(256), 0, st, blocks, rx, ry, rz, nx, ny,
-                     nz, phase, groups, pose_in, x, y, z);
+                     nz, phase, groups, pose_in, v);
   return hipGetLastError();
 }
 
@@ -2141,16 +2150,16 @@ hipError_t launch_validate(const float* xyz, uint32_t nv, const uint32_t* idx, u
   return hipGetLastError();
 }
 
-hipError_t launch_soa(const float* xyz, uint32_t nv, float* x, float* y, float* z,
-                      hipStream_t st) {
+hipError_t launch_pad(const float* xyz, uint32_t nv, float4* v, hipStream_t st) {
   if (nv == 0) return hipSuccess;
-  hipLaunchKernelGGL(soa_kernel, dim3(cdiv(nv, 256)), dim3(256), 0, st, xyz, nv, x, y, z);
+  hipLaunchKernelGGL(pad_kernel, dim3(cdiv(nv, 256)), dim3(256), 0, st, xyz, nv, v);
   return hipGetLastError();
 }
 
-hipError_t launch_copy(const float* src, float* dst, uint32_t n, hipStream_t st) {
+hipError_t launch_split(const float4* v, uint32_t n, float* x, float* y, float* z,
+                        hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_range_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, src, dst, n);
+  hipLaunchKernelGGL(split_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, v, n, x, y, z);
   return hipGetLastError();
 }
 

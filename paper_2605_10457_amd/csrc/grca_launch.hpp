@@ -52,7 +52,7 @@ hipError_t launch_resolve(const unsigned long long* keys, uint32_t n, float* dis
 hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* rx, const float* ry,
                        const float* rz, const float* nx, const float* ny, const float* nz,
                        const float* phase, const DeformParam* groups, const double* pose_in,
-                       float* x, float* y, float* z, hipStream_t st);
+                       float4* v, hipStream_t st);
 // Per-sensor tables: chan / chan_d from the elevations plus the optional
 // per-channel offsets (vertical noise), sin_tab and the lookup from the
 // nominal (ascending) elevations, az from the azimuth grid plus offsets.
@@ -62,17 +62,18 @@ hipError_t launch_sensor_tables(const float* elev, const float* el_off, uint32_t
                                 ChanBin* lut, hipStream_t st);
 hipError_t launch_validate(const float* xyz, uint32_t nv, const uint32_t* idx, uint64_t nidx,
                            uint32_t* bad, hipStream_t st);
-hipError_t launch_soa(const float* xyz, uint32_t nv, float* x, float* y, float* z,
-                      hipStream_t st);
-hipError_t launch_copy(const float* src, float* dst, uint32_t n, hipStream_t st);
+// caller's packed xyz -> padded (x, y, z, 0) vertices
+hipError_t launch_pad(const float* xyz, uint32_t nv, float4* v, hipStream_t st);
+// padded vertices -> three coordinate arrays (rest positions of the pose step)
+hipError_t launch_split(const float4* v, uint32_t n, float* x, float* y, float* z,
+                        hipStream_t st);
 
 // Tile order of a scene (grca_order.hip): rewrites idx (3 x ntri) in Morton
 // order of triangle centroids within each dynamic group (vgroup[v] = group of
 // vertex v) and permutes orig (caller triangle id of each slot) alike.
 // Synchronises `st`; allocates and frees its own temporaries.
-hipError_t order_triangles(uint32_t* idx, uint32_t* orig, uint32_t ntri, const float* x,
-                           const float* y, const float* z, uint32_t nv, const uint32_t* vgroup,
-                           hipStream_t st);
+hipError_t order_triangles(uint32_t* idx, uint32_t* orig, uint32_t ntri, const float4* v,
+                           uint32_t nv, const uint32_t* vgroup, hipStream_t st);
 hipError_t launch_iota(uint32_t* a, uint32_t n, hipStream_t st);
 
 // The no-allocation cast's work memory: a static device array of

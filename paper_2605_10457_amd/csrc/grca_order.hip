@@ -28,11 +28,11 @@ __device__ inline int ordered_int(float f) {
 __device__ inline float ordered_float(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7FFFFFFF); }
 
 // box[0..2] = min x, y, z and box[3..5] = max, as order-preserving ints
-__global__ void bbox_kernel(const float* __restrict__ x, const float* __restrict__ y,
-                            const float* __restrict__ z, uint32_t nv, int* __restrict__ box) {
+__global__ void bbox_kernel(const float4* __restrict__ vtx, uint32_t nv, int* __restrict__ box) {
   float mn[3] = {3.0e38f, 3.0e38f, 3.0e38f}, mx[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
-    const float v[3] = {x[i], y[i], z[i]};
+    const float4 p = vtx[i];
+    const float v[3] = {p.x, p.y, p.z};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       mn[k] = fminf(mn[k], v[k]);
@@ -76,17 +76,16 @@ __device__ inline uint32_t spread10(uint32_t v) {  // 10 bits to every third bit
 
 // key = dynamic group << 32 | 30-bit Morton code of the centroid
 __global__ void order_keys_kernel(const uint32_t* __restrict__ idx, uint32_t ntri,
-                                  const float* __restrict__ x, const float* __restrict__ y,
-                                  const float* __restrict__ z, const uint32_t* __restrict__ vgroup,
+                                  const float4* __restrict__ v, const uint32_t* __restrict__ vgroup,
                                   const int* __restrict__ box,
                                   unsigned long long* __restrict__ keys,
                                   uint32_t* __restrict__ slots) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntri) return;
   const uint32_t i0 = idx[3ull * t], i1 = idx[3ull * t + 1], i2 = idx[3ull * t + 2];
-  const float c[3] = {(x[i0] + x[i1] + x[i2]) * (1.0f / 3.0f),
-                      (y[i0] + y[i1] + y[i2]) * (1.0f / 3.0f),
-                      (z[i0] + z[i1] + z[i2]) * (1.0f / 3.0f)};
+  const float4 p0 = v[i0], p1 = v[i1], p2 = v[i2];
+  const float c[3] = {(p0.x + p1.x + p2.x) * (1.0f / 3.0f), (p0.y + p1.y + p2.y) * (1.0f / 3.0f),
+                      (p0.z + p1.z + p2.z) * (1.0f / 3.0f)};
   uint32_t code = 0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -135,9 +134,8 @@ hipError_t launch_fill(uint32_t* a, uint32_t n, uint32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t order_triangles(uint32_t* idx, uint32_t* orig, uint32_t ntri, const float* x,
-                           const float* y, const float* z, uint32_t nv, const uint32_t* vgroup,
-                           hipStream_t st) {
+hipError_t order_triangles(uint32_t* idx, uint32_t* orig, uint32_t ntri, const float4* v,
+                           uint32_t nv, const uint32_t* vgroup, hipStream_t st) {
   if (ntri < 2 || nv == 0) return hipSuccess;
   hipError_t e = hipSuccess;
   int* box = nullptr;
@@ -166,9 +164,9 @@ hipError_t order_triangles(uint32_t* idx, uint32_t* orig, uint32_t ntri, const f
   if ((e = hipMalloc(&orig_new, ntri * sizeof(uint32_t))) != hipSuccess) return done(e);
   hipLaunchKernelGGL(init_box_kernel, dim3(1), dim3(64), 0, st, box);
   hipLaunchKernelGGL(bbox_kernel, dim3(std::min<uint32_t>(cdiv(nv, 256), 1024u)), dim3(256), 0,
-                     st, x, y, z, nv, box);
-  hipLaunchKernelGGL(order_keys_kernel, dim3(cdiv(ntri, 256)), dim3(256), 0, st, idx, ntri, x, y,
-                     z, vgroup, box, k_in, s_in);
+                     st, v, nv, box);
+  hipLaunchKernelGGL(order_keys_kernel, dim3(cdiv(ntri, 256)), dim3(256), 0, st, idx, ntri, v,
+                     vgroup, box, k_in, s_in);
   if ((e = hipGetLastError()) != hipSuccess) return done(e);
   if ((e = hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, k_in, k_out, s_in, s_out,
                                               (int)ntri, 0, 64, st)) != hipSuccess)
