@@ -80,6 +80,19 @@ __device__ inline float4 gload_v(const float4* base, uint32_t byte_off) {
   return make_float4(q.x, q.y, q.z, q.w);
 }
 
+// A triangle's three vertex indices (12 bytes at a 4-byte aligned offset), in
+// one load.
+struct Tri3 {
+  uint32_t a, b, c;
+};
+__device__ inline Tri3 gload_tri(const uint32_t* base, uint32_t byte_off) {
+  typedef uint32_t v3u __attribute__((ext_vector_type(3)));
+  typedef const v3u __attribute__((address_space(1))) GT;
+  typedef const char __attribute__((address_space(1))) GC;
+  const v3u q = *(GT*)((GC*)base + byte_off);
+  return Tri3{q.x, q.y, q.z};
+}
+
 __device__ inline float2 gload_f2(const float2* base, uint32_t byte_off) {
   const unsigned long long v = gload(reinterpret_cast<const unsigned long long*>(base), byte_off);
   return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
@@ -965,9 +978,8 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
     const uint32_t t = tri0 + 64u * h + lane;
     active[h] = t < ntri;
     const uint32_t tt = active[h] ? t : tri0;
-    uint32_t id[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) id[k] = gload(S.idx, (3u * tt + (uint32_t)k) * 4u);
+    const Tri3 ti = gload_tri(S.idx, 12u * tt);
+    const uint32_t id[3] = {ti.a, ti.b, ti.c};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const float4 p = gload_v(S.v, id[k] * 16u);
@@ -1723,8 +1735,8 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
             // (global loads at 32-bit byte offsets: the pointers come from
             // LDS, and flat accesses would also wait behind the LDS counter)
             const uint32_t t = it.tri;
-            const uint32_t v0 = gload(sq.idx, 12u * t), v1 = gload(sq.idx, 12u * t + 4u),
-                           v2 = gload(sq.idx, 12u * t + 8u);
+            const Tri3 ti = gload_tri(sq.idx, 12u * t);
+            const uint32_t v0 = ti.a, v1 = ti.b, v2 = ti.c;
             const float4 p0 = gload_v(sq.v, 16u * v0), p1 = gload_v(sq.v, 16u * v1),
                          p2 = gload_v(sq.v, 16u * v2);
             Statics st;
