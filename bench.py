@@ -43,15 +43,16 @@ FLOPS_PER_RTIC = 22               # ray test: 2 mul (direction) + 4 dot products
 # * bounding-sphere test of one (triangle, origin) pair: offset 3, local
 #   frame 15, |.|^2 5, distance 2, range 2, angular radius 6, sqrt 1,
 #   elevation atan2 19, channel-grid indices 6;
-# * the same test of a 128-triangle tile against one origin, plus its
-#   azimuth test (angular half-width 5, atan2 20, offset from the field of
-#   view's centre 7, margin 1): 92;
+# * the same test of a 128-triangle tile against one origin: 59, plus, for a
+#   partial field of view, the wedge test (two signed plane distances 3 + 3,
+#   margin 3): 68;
 # * candidate span of one pair on the common path (no range or pole test,
 #   azimuth offsets by the series bound): transform 54, |p|^2 15, sines 6,
 #   edge bulge 27, margins 2, channel bins 4, atan2 of vertex 0 20, offsets of
 #   vertices 1-2 28, full-turn test 1, azimuth margin 6, ray-index range 12.
 FLOPS_PER_SPHERE = 59
-FLOPS_PER_TILE_TEST = 92
+FLOPS_PER_TILE_TEST = 59
+FLOPS_PER_WEDGE = 9
 FLOPS_PER_SPAN = 175
 
 
@@ -341,15 +342,18 @@ def main():
                 "work": f"{FLOPS_PER_RTIC} FP32 flops x {stats['rtic']} RTIC per launch"}
     elif dom == "bounds":
         # VALU-bound: FP32 flops of the tests and spans the pass computed
-        tile_tests = (-(-int(sc.num_triangles) // 128) * n_sens
-                      if opts.get("group_cull", 1) else 0)
-        flops = (FLOPS_PER_TILE_TEST * tile_tests + FLOPS_PER_SPHERE * stats["sphere_tests"] +
+        n_tiles = -(-int(sc.num_triangles) // 128) if opts.get("group_cull", 1) else 0
+        tile_tests = n_tiles * n_sens
+        wedge_tests = n_tiles * sum(1 for s in wl.sensors if float(s["fov"]) < 2 * np.pi - 1e-6)
+        flops = (FLOPS_PER_TILE_TEST * tile_tests + FLOPS_PER_WEDGE * wedge_tests +
+                 FLOPS_PER_SPHERE * stats["sphere_tests"] +
                  FLOPS_PER_SPAN * stats["pairs_evaluated"])
         achieved = flops / (stage_ms["bounds"] * 1e-3) / 1e12
         roof = {"kernel": "bounds_kernel", "bound": "alu", "achieved": achieved,
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                 "traffic": load_traffic("bounds_kernel"),
                 "work": f"{FLOPS_PER_TILE_TEST} FP32 flops x {tile_tests} tile tests + "
+                        f"{FLOPS_PER_WEDGE} x {wedge_tests} tile wedge tests + "
                         f"{FLOPS_PER_SPHERE} x {stats['sphere_tests']} triangle sphere tests + "
                         f"{FLOPS_PER_SPAN} x {stats['pairs_evaluated']} (triangle, origin) spans "
                         f"per launch"}
@@ -363,11 +367,12 @@ def main():
     rtic_s = stats["rtic"] / (stage_ms["isect"] * 1e-3)
     # the streaming passes against HBM, with their algorithmic bytes: pose
     # reads 12 B of rest position (+12 B normal and 4 B phase when deforming)
-    # and writes 12 B per dynamic vertex; init writes the 8 B key of each ray;
-    # resolve reads it and writes 4 B distance + 4 B triangle id
+    # and writes the 16 B vertex record per dynamic vertex; init writes the
+    # 8 B key of each ray; resolve reads it and writes 4 B distance + 4 B
+    # triangle id
     n_rigid_v = int(np.sum(sc.rigid.vertex_count)) if sc.rigid is not None else 0
     n_def_v = int(sum(g.vertex_count for g in sc.deform))
-    stream_bytes = {"pose": 24 * n_rigid_v + 40 * n_def_v, "init": 8 * n_rays,
+    stream_bytes = {"pose": 28 * n_rigid_v + 44 * n_def_v, "init": 8 * n_rays,
                     "resolve": 16 * n_rays}
     streaming = {}
     for k, nb in stream_bytes.items():

@@ -1058,9 +1058,8 @@ extern "C" grca_status grca_scene_set_deform(grca_context* ctx, uint32_t scene_i
 
 namespace {
 grca_status enqueue_pose_kernels(grca_context* ctx, SceneData& sc, hipStream_t st) {
-  HIPCHK(launch_pose(sc.rigid_blocks, sc.n_rigid_blocks, sc.rr_x, sc.rr_y, sc.rr_z, nullptr,
-                     nullptr, nullptr, nullptr, nullptr, sc.pose_in, sc.v, st));
-  HIPCHK(launch_pose(sc.deform_blocks, sc.n_deform_blocks, sc.dr_x, sc.dr_y, sc.dr_z, sc.dn_x,
+  HIPCHK(launch_pose(sc.rigid_blocks, sc.n_rigid_blocks, sc.rr_x, sc.rr_y, sc.rr_z,
+                     sc.deform_blocks, sc.n_deform_blocks, sc.dr_x, sc.dr_y, sc.dr_z, sc.dn_x,
                      sc.dn_y, sc.dn_z, sc.dphase, sc.dparams, sc.pose_in, sc.v, st));
   return GRCA_OK;
 }

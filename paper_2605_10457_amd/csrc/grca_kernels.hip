@@ -1937,20 +1937,24 @@ __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint
 }
 
 // ------------------------------------------------------------------ pose
-// Each block handles up to 256 vertices of one rigid instance or deform group.
+// One launch for both kinds: blocks [0, n_rigid) are rigid-instance blocks,
+// the rest deform-group blocks; each handles up to 256 vertices.
 __global__ __launch_bounds__(256) void pose_kernel(
-    const PoseBlock* __restrict__ blocks, const float* __restrict__ rx,
-    const float* __restrict__ ry, const float* __restrict__ rz, const float* __restrict__ nx,
+    const PoseBlock* __restrict__ rblocks, uint32_t n_rigid, const float* __restrict__ rrx,
+    const float* __restrict__ rry, const float* __restrict__ rrz,
+    const PoseBlock* __restrict__ dblocks, const float* __restrict__ drx,
+    const float* __restrict__ dry, const float* __restrict__ drz, const float* __restrict__ nx,
     const float* __restrict__ ny, const float* __restrict__ nz, const float* __restrict__ phase,
     const DeformParam* __restrict__ groups, const double* __restrict__ pose_in,
     float4* __restrict__ out) {
-  const PoseBlock pb = blocks[blockIdx.x];
+  const bool rigid = blockIdx.x < n_rigid;
+  const PoseBlock pb = rigid ? rblocks[blockIdx.x] : dblocks[blockIdx.x - n_rigid];
   const uint32_t i = threadIdx.x;
   if (i >= pb.count) return;
   const uint32_t v = pb.v_begin + i;
   const uint32_t r = pb.rest_begin + i;
-  const double px = rx[r], py = ry[r], pz = rz[r];
-  if (pb.kind == 0) {
+  if (rigid) {
+    const double px = rrx[r], py = rry[r], pz = rrz[r];
     const float* M = reinterpret_cast<const float*>(pose_in + 1) + 12ull * pb.group;
     out[v] = make_float4(
         (float)((double)M[0] * px + (double)M[1] * py + (double)M[2] * pz + (double)M[3]),
@@ -1958,6 +1962,7 @@ __global__ __launch_bounds__(256) void pose_kernel(
         (float)((double)M[8] * px + (double)M[9] * py + (double)M[10] * pz + (double)M[11]),
         0.0f);
   } else {
+    const double px = drx[r], py = dry[r], pz = drz[r];
     const DeformParam g = groups[pb.group];
     const double time = pose_in[0];
     const double wv = (double)g.amplitude * sin((double)g.omega * time + (double)phase[r]);
@@ -2131,13 +2136,15 @@ hipError_t launch_resolve(const unsigned long long* keys, uint32_t n, float* dis
   return hipGetLastError();
 }
 
-hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* rx, const float* ry,
-                       const float* rz, const float* nx, const float* ny, const float* nz,
-                       const float* phase, const DeformParam* groups, const double* pose_in,
-                       float4* v, hipStream_t st) {
-  if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(pose_kernel, dim3(nblocks), dim3(256), 0, st, blocks, rx, ry, rz, nx, ny,
-                     nz, phase, groups, pose_in, v);
+hipError_t launch_pose(const PoseBlock* rblocks, uint32_t n_rigid, const float* rrx,
+                       const float* rry, const float* rrz, const PoseBlock* dblocks,
+                       uint32_t n_deform, const float* drx, const float* dry, const float* drz,
+                       const float* nx, const float* ny, const float* nz, const float* phase,
+                       const DeformParam* groups, const double* pose_in, float4* v,
+                       hipStream_t st) {
+  if (n_rigid + n_deform == 0) return hipSuccess;
+  hipLaunchKernelGGL(pose_kernel, dim3(n_rigid + n_deform), dim3(256), 0, st, rblocks, n_rigid,
+                     rrx, rry, rrz, dblocks, drx, dry, drz, nx, ny, nz, phase, groups, pose_in, v);
   return hipGetLastError();
 }
 

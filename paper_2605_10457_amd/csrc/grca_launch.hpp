@@ -49,10 +49,14 @@ hipError_t launch_allpairs(const DevScene* scenes, const DevSensor* sens, uint32
 // also writes the cast's Summary from the queue counters
 hipError_t launch_resolve(const unsigned long long* keys, uint32_t n, float* dist, uint32_t* tri,
                           Counters* cnt, hipStream_t st);
-hipError_t launch_pose(const PoseBlock* blocks, uint32_t nblocks, const float* rx, const float* ry,
-                       const float* rz, const float* nx, const float* ny, const float* nz,
-                       const float* phase, const DeformParam* groups, const double* pose_in,
-                       float4* v, hipStream_t st);
+// both pose kinds in one launch: n_rigid rigid-instance blocks, then
+// n_deform deform-group blocks
+hipError_t launch_pose(const PoseBlock* rblocks, uint32_t n_rigid, const float* rrx,
+                       const float* rry, const float* rrz, const PoseBlock* dblocks,
+                       uint32_t n_deform, const float* drx, const float* dry, const float* drz,
+                       const float* nx, const float* ny, const float* nz, const float* phase,
+                       const DeformParam* groups, const double* pose_in, float4* v,
+                       hipStream_t st);
 // Per-sensor tables: chan / chan_d from the elevations plus the optional
 // per-channel offsets (vertical noise), sin_tab and the lookup from the
 // nominal (ascending) elevations, az from the azimuth grid plus offsets.
