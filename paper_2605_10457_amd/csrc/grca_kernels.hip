@@ -805,10 +805,13 @@ __device__ inline FovVerdict fov_verdict(float lf, float lr, float D, float r,
 // margins cover the FP32 error of c's angles and of the ray test.
 // need_range: the sphere straddles range_min or range_max; need_pole: it
 // touches the vertical axis through the origin.  Used for bounds tiles (AZ)
-// and for single triangles.
+// and for single triangles.  want_range / want_pole / want_fov (wave-uniform)
+// skip the parts whose verdict the caller will not use: false gives
+// need_range = need_pole = false and no field-of-view test.
 template <bool AZ>
 __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float rad,
-                                           const DevSensor& s) {
+                                           const DevSensor& s, bool want_range = true,
+                                           bool want_pole = true, bool want_fov = true) {
   const float dx = cx - s.o[0], dy = cy - s.o[1], dz = cz - s.o[2];
   const float lf = fmaf(dx, s.f[0], fmaf(dy, s.f[1], dz * s.f[2]));
   const float lr = fmaf(dx, s.r[0], fmaf(dy, s.r[1], dz * s.r[2]));
@@ -821,7 +824,6 @@ __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float r
   const float invD = __builtin_amdgcn_rsqf(D2);
   const float D = D2 * invD;
   const bool beyond = D - r > s.cull_dmax;
-  const bool inside = (uint32_t)(D + r < s.in_dmax) & (uint32_t)(D - r > s.in_dmin);
   const float sa = r * invD;
   const float m = fmaf(sa * sa * (1.0f / 3.0f), sa, sa) + s.elev_m;
   // elevation of c (in [-pi/2, pi/2], |error| <= 5e-7; NaN only at D = 0,
@@ -839,7 +841,7 @@ __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float r
   const bool band = (uint32_t)!(j_lo > j_hi) & (uint32_t)!(j_lo > s.last_chan) &
                     (uint32_t)!(j_hi < 0.0f);
   uint32_t out_fov = 0u, in_fov = 1u;
-  if (AZ) {
+  if (AZ && want_fov) {
     const FovVerdict fv = fov_verdict(lf, lr, D, r, s);
     out_fov = (uint32_t)fv.out;
     in_fov = (uint32_t)fv.in;
@@ -848,8 +850,12 @@ __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float r
   const uint32_t far = (uint32_t)!near;
   GroupVerdict v;
   v.culled = (far & ((uint32_t)beyond | (uint32_t)!band | out_fov)) != 0u;
-  v.need_range = ((uint32_t)near | (uint32_t)!inside) != 0u;
-  v.need_pole = !(h2 > r2 * 1.0001f);
+  v.need_range = false;
+  if (want_range) {
+    const bool inside = (uint32_t)(D + r < s.in_dmax) & (uint32_t)(D - r > s.in_dmin);
+    v.need_range = ((uint32_t)near | (uint32_t)!inside) != 0u;
+  }
+  v.need_pole = want_pole && !(h2 > r2 * 1.0001f);
   v.need_fov = in_fov == 0u;
   return v;
 }
@@ -1074,27 +1080,25 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
         g_fov = first_lane(__ballot(nf));
       }
       if (!((g_cull >> ln) & 1ull)) {  // wave-uniform
-        // both triangles of every lane (no branch: the sensor's fields are
-        // read once); where the tile straddles the edge of a partial field
-        // of view, the triangles' own azimuths are tested too
+        // both triangles of every lane (the sensor's fields are read once);
+        // the range, pole and field-of-view parts only where the tile's own
+        // test found the tile straddling a range limit, touching the
+        // vertical axis or straddling the edge of a partial field of view
         const DevSensor& s = sens[n];
-        GroupVerdict v0, v1;
-        if ((g_fov >> ln) & 1ull) {
-          v0 = sphere_test<true>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s);
-          v1 = sphere_test<true>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s);
-        } else {
-          v0 = sphere_test<false>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s);
-          v1 = sphere_test<false>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s);
-        }
-        tested += n_active;
         const bool gr = (g_range >> ln) & 1ull, gp = (g_pole >> ln) & 1ull;
+        const bool gf = (g_fov >> ln) & 1ull;
+        const GroupVerdict v0 =
+            sphere_test<true>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s, gr, gp, gf);
+        const GroupVerdict v1 =
+            sphere_test<true>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s, gr, gp, gf);
+        tested += n_active;
         const bool keep0 = active[0] && !v0.culled;
         const bool keep1 = active[1] && !v1.culled;
         const uint32_t tag = n << 9;
-        const uint32_t e0 = lane | ((uint32_t)(v0.need_range && gr) << 7) |
-                            ((uint32_t)(v0.need_pole && gp) << 8) | tag;
-        const uint32_t e1 = (64u + lane) | ((uint32_t)(v1.need_range && gr) << 7) |
-                            ((uint32_t)(v1.need_pole && gp) << 8) | tag;
+        const uint32_t e0 = lane | ((uint32_t)v0.need_range << 7) |
+                            ((uint32_t)v0.need_pole << 8) | tag;
+        const uint32_t e1 = (64u + lane) | ((uint32_t)v1.need_range << 7) |
+                            ((uint32_t)v1.need_pole << 8) | tag;
         const unsigned long long m0 = __ballot(keep0), m1 = __ballot(keep1);
         const uint32_t c0 = (uint32_t)__popcll(m0);
         if (keep0) ring[(tail + rank_in(m0)) % RING] = e0;
