@@ -31,6 +31,8 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 struct SceneData {
   uint32_t nv = 0, ntri = 0;
   float4* v = nullptr;       // vertex positions (x, y, z, 0)
+  float4* soup = nullptr;    // vertex records of the all-static triangles (slots [0, n_soup))
+  uint32_t n_soup = 0;
   uint32_t* idx = nullptr;   // index triples in tile order (Morton within dynamic groups)
   uint32_t* orig = nullptr;  // caller triangle id of each stored slot
   // rigid instances
@@ -84,7 +86,7 @@ void dfree(T*& p) {
 }
 
 void free_scene(SceneData& s) {
-  dfree(s.v); dfree(s.idx); dfree(s.orig);
+  dfree(s.v); dfree(s.soup); dfree(s.idx); dfree(s.orig);
   dfree(s.rr_x); dfree(s.rr_y); dfree(s.rr_z); dfree(s.rigid_blocks);
   dfree(s.dr_x); dfree(s.dr_y); dfree(s.dr_z);
   dfree(s.dn_x); dfree(s.dn_y); dfree(s.dn_z); dfree(s.dphase);
@@ -104,7 +106,10 @@ void free_sensor(SensorData& s) {
 // deforming range), so that the bounds pass's tiles and their halves are compact
 // and its tile-sphere test culls more.  `orig` keeps the caller's ids.
 hipError_t reorder_scene_dev(SceneData& sc, hipStream_t st) {
-  if (sc.ntri < 2 || sc.nv == 0) return hipSuccess;
+  dfree(sc.soup);
+  sc.soup = nullptr;
+  sc.n_soup = 0;
+  if (sc.ntri == 0 || sc.nv == 0) return hipSuccess;
   uint32_t* vg = nullptr;
   hipError_t e = dmalloc(&vg, sc.nv);
   if (e != hipSuccess) return e;
@@ -114,10 +119,26 @@ hipError_t reorder_scene_dev(SceneData& sc, hipStream_t st) {
   for (uint32_t g = 0; e == hipSuccess && g < sc.n_groups; ++g)
     e = launch_fill(vg + sc.groups[g].vertex_start, sc.groups[g].vertex_count,
                     1u + sc.n_inst + g, st);
-  if (e == hipSuccess) e = order_triangles(sc.idx, sc.orig, sc.ntri, sc.v, sc.nv, vg, st);
+  if (e == hipSuccess && sc.ntri >= 2)
+    e = order_triangles(sc.idx, sc.orig, sc.ntri, sc.v, sc.nv, vg, st);
+  uint32_t n_static = 0;
+  if (e == hipSuccess) e = count_static(sc.idx, sc.ntri, vg, &n_static, st);
   (void)hipStreamSynchronize(st);
   dfree(vg);
+  // the static triangles' vertex records (48 B each, addressed by 32-bit
+  // byte offsets: at most 2^32 / 48 triangles get one)
+  const uint32_t n_soup = std::min<uint32_t>(n_static, 0xFFFFFFFFu / 48u);
+  if (e == hipSuccess && n_soup) {
+    e = dmalloc(&sc.soup, 3ull * n_soup);
+    if (e == hipSuccess) e = launch_soup(sc.idx, sc.v, n_soup, sc.soup, st);
+    if (e == hipSuccess) sc.n_soup = n_soup;
+  }
   return e;
+}
+
+// Rewrite the static triangles' vertex records after their vertices changed.
+hipError_t refresh_soup(SceneData& sc, hipStream_t st) {
+  return launch_soup(sc.idx, sc.v, sc.n_soup, sc.soup, st);
 }
 
 }  // namespace
@@ -447,7 +468,7 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
     if (k == 0 || sd[order[k - 1]]->desc.scene_id != sid) {
       const SceneData& sc = ctx->scenes.at(sid);
       DevScene ds{};
-      ds.v = sc.v; ds.idx = sc.idx; ds.orig = sc.orig;
+      ds.v = sc.v; ds.soup = sc.soup; ds.n_soup = sc.n_soup; ds.idx = sc.idx; ds.orig = sc.orig;
       ds.ntri = sc.ntri;
       ds.tile_start = tiles;
       ds.sensor_begin = k;
@@ -843,6 +864,8 @@ extern "C" grca_status grca_scene_update(grca_context* ctx, uint32_t scene_id,
     if (!vonly) {
       grca_status rc = reorder_scene(ctx, sc, st);
       if (rc != GRCA_OK) return rc;
+    } else {
+      HIPCHK(refresh_soup(sc, st));
     }
     if (tmp) {
       HIPCHK(hipStreamSynchronize(st));

@@ -98,9 +98,16 @@ constexpr uint32_t BOUNDS_TILE = 128;
 
 struct DevScene {
   const float4* v;       // vertex positions (x, y, z, 0): one 16-byte load per vertex
+  // the static triangles' vertex records, three per triangle (48 B), for
+  // slots [0, n_soup): the tile order puts every triangle whose vertices are
+  // all static first; no pose moves them, so these copies stay current.  The
+  // intersection reads a static triangle here in one round trip instead of
+  // its indices and then its vertices
+  const float4* soup;
   const uint32_t* idx;   // index triples in tile order
   const uint32_t* orig;  // caller triangle id of each stored slot (keys and outputs use it)
   uint32_t ntri;
+  uint32_t n_soup;       // slots with a vertex record copy in `soup`
   uint32_t tile_start;   // first bounds tile (BOUNDS_TILE triangles) of this scene in the cast
   uint32_t sensor_begin; // sensor slots [sensor_begin, sensor_end) observe it
   uint32_t sensor_end;

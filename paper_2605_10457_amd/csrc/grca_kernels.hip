@@ -984,14 +984,17 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
     const uint32_t t = tri0 + 64u * h + lane;
     active[h] = t < ntri;
     const uint32_t tt = active[h] ? t : tri0;
+    // (indices, then the vertex records: reading the static triangles'
+    // record copies instead fetches 48 B per triangle where neighbouring
+    // triangles share vertices, and was slower here)
     const Tri3 ti = gload_tri(S.idx, 12u * tt);
-    const uint32_t id[3] = {ti.a, ti.b, ti.c};
+    const float4 p[3] = {gload_v(S.v, ti.a * 16u), gload_v(S.v, ti.b * 16u),
+                         gload_v(S.v, ti.c * 16u)};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const float4 p = gload_v(S.v, id[k] * 16u);
-      v[h][3 * k] = p.x;
-      v[h][3 * k + 1] = p.y;
-      v[h][3 * k + 2] = p.z;
+      v[h][3 * k] = p[k].x;
+      v[h][3 * k + 1] = p[k].y;
+      v[h][3 * k + 2] = p[k].z;
     }
   }
   // bounding spheres (AABB centre, largest vertex distance) of the lane's
@@ -1503,6 +1506,8 @@ struct IsectSensor {
   const uint32_t* idx;
   const uint32_t* orig;
   const float4* v;
+  const float4* soup;
+  uint32_t n_soup;
   float o[3], f[3], r[3], u[3];
   int32_t cull_back;
   uint32_t chi, key_offset;
@@ -1513,7 +1518,7 @@ __device__ inline IsectSensor isect_sensor(const DevScene* scenes, const DevSens
   const DevScene& S = scenes[s.scene];
   IsectSensor q;
   q.chan = s.chan; q.az = s.az; q.mask = s.mask;
-  q.idx = S.idx; q.orig = S.orig; q.v = S.v;
+  q.idx = S.idx; q.orig = S.orig; q.v = S.v; q.soup = S.soup; q.n_soup = S.n_soup;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     q.o[k] = s.o[k]; q.f[k] = s.f[k]; q.r[k] = s.r[k]; q.u[k] = s.u[k];
@@ -1738,11 +1743,19 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
                                             : isect_sensor(scenes, sens[it.sensor]);
             // (global loads at 32-bit byte offsets: the pointers come from
             // LDS, and flat accesses would also wait behind the LDS counter)
+            // (a static triangle's vertex records in one round trip)
             const uint32_t t = it.tri;
-            const Tri3 ti = gload_tri(sq.idx, 12u * t);
-            const uint32_t v0 = ti.a, v1 = ti.b, v2 = ti.c;
-            const float4 p0 = gload_v(sq.v, 16u * v0), p1 = gload_v(sq.v, 16u * v1),
-                         p2 = gload_v(sq.v, 16u * v2);
+            float4 p0, p1, p2;
+            if (t < sq.n_soup) {
+              p0 = gload_v(sq.soup, 48u * t);
+              p1 = gload_v(sq.soup, 48u * t + 16u);
+              p2 = gload_v(sq.soup, 48u * t + 32u);
+            } else {
+              const Tri3 ti = gload_tri(sq.idx, 12u * t);
+              p0 = gload_v(sq.v, 16u * ti.a);
+              p1 = gload_v(sq.v, 16u * ti.b);
+              p2 = gload_v(sq.v, 16u * ti.c);
+            }
             Statics st;
             if (make_statics(p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z, sq, st)) {
               count = hi - lo;

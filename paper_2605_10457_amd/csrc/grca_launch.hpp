@@ -79,6 +79,13 @@ hipError_t launch_split(const float4* v, uint32_t n, float* x, float* y, float* 
 hipError_t order_triangles(uint32_t* idx, uint32_t* orig, uint32_t ntri, const float4* v,
                            uint32_t nv, const uint32_t* vgroup, hipStream_t st);
 hipError_t launch_iota(uint32_t* a, uint32_t n, hipStream_t st);
+// Number of triangles whose three vertices are all in group 0 (static);
+// the tile order puts them first.  Synchronises `st`.
+hipError_t count_static(const uint32_t* idx, uint32_t ntri, const uint32_t* vgroup,
+                        uint32_t* n_static, hipStream_t st);
+// soup[3 t + k] = v[idx[3 t + k]] for the slots t < n
+hipError_t launch_soup(const uint32_t* idx, const float4* v, uint32_t n, float4* soup,
+                       hipStream_t st);
 
 // The no-allocation cast's work memory: a static device array of
 // NOALLOC_SCRATCH_BYTES, one per device.  noalloc_scratch_address gives its

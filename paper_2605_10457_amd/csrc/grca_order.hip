@@ -95,7 +95,10 @@ __global__ void order_keys_kernel(const uint32_t* __restrict__ idx, uint32_t ntr
     q = fminf(fmaxf(q, 0.0f), 1023.0f);
     code |= spread10((uint32_t)q) << k;
   }
-  keys[t] = ((unsigned long long)vgroup[i0] << 32) | code;
+  // the largest group of the three vertices: a triangle touching a dynamic
+  // vertex sorts after every all-static one
+  const uint32_t g = max(vgroup[i0], max(vgroup[i1], vgroup[i2]));
+  keys[t] = ((unsigned long long)g << 32) | code;
   slots[t] = t;
 }
 
@@ -111,6 +114,26 @@ __global__ void order_gather_kernel(const uint32_t* __restrict__ idx_in,
   idx_out[3ull * k + 1] = idx_in[3ull * t + 1];
   idx_out[3ull * k + 2] = idx_in[3ull * t + 2];
   orig_out[k] = orig_in[t];
+}
+
+// Triangles whose three vertices are all static (group 0), counted with one
+// atomic per wave.
+__global__ void count_static_kernel(const uint32_t* __restrict__ idx, uint32_t ntri,
+                                    const uint32_t* __restrict__ vgroup,
+                                    uint32_t* __restrict__ out) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  bool st = false;
+  if (t < ntri)
+    st = (vgroup[idx[3ull * t]] | vgroup[idx[3ull * t + 1]] | vgroup[idx[3ull * t + 2]]) == 0u;
+  const unsigned long long m = __ballot(st);
+  if ((threadIdx.x & 63u) == 0u && m) atomicAdd(out, (uint32_t)__popcll(m));
+}
+
+// The vertex records of slots [0, n): soup[3 t + k] = v[idx[3 t + k]].
+__global__ void soup_kernel(const uint32_t* __restrict__ idx, const float4* __restrict__ v,
+                            uint32_t n, float4* __restrict__ soup) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3ull * n) soup[i] = v[idx[i]];
 }
 
 __global__ void iota_kernel(uint32_t* __restrict__ a, uint32_t n) {
@@ -131,6 +154,31 @@ hipError_t launch_iota(uint32_t* a, uint32_t n, hipStream_t st) {
 hipError_t launch_fill(uint32_t* a, uint32_t n, uint32_t v, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, a, n, v);
+  return hipGetLastError();
+}
+
+hipError_t count_static(const uint32_t* idx, uint32_t ntri, const uint32_t* vgroup,
+                        uint32_t* n_static, hipStream_t st) {
+  *n_static = 0;
+  if (ntri == 0) return hipSuccess;
+  uint32_t* d = nullptr;
+  hipError_t e = hipMalloc(&d, sizeof(uint32_t));
+  if (e != hipSuccess) return e;
+  if ((e = hipMemsetAsync(d, 0, sizeof(uint32_t), st)) == hipSuccess) {
+    hipLaunchKernelGGL(count_static_kernel, dim3(cdiv(ntri, 256)), dim3(256), 0, st, idx, ntri,
+                       vgroup, d);
+    if ((e = hipGetLastError()) == hipSuccess)
+      e = hipMemcpyAsync(n_static, d, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+  }
+  const hipError_t e2 = hipStreamSynchronize(st);
+  (void)hipFree(d);
+  return e != hipSuccess ? e : e2;
+}
+
+hipError_t launch_soup(const uint32_t* idx, const float4* v, uint32_t n, float4* soup,
+                       hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(soup_kernel, dim3(cdiv(3ull * n, 256)), dim3(256), 0, st, idx, v, n, soup);
   return hipGetLastError();
 }
 

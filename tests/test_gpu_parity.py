@@ -334,6 +334,36 @@ def test_fov_edges_all_pairs(ctx):
     assert np.count_nonzero(t != grca.GRCA_MISS_TRI) > len(ids) * n1 // 2
 
 
+def test_vertex_only_update(ctx):
+    _say("vertex-only scene update (every vertex moved): cast vs a fresh upload of the moved "
+         "scene (bitwise), vs all-pairs, and the oracle on a sample")
+    wl = synth.config1()
+    v, f = wl.scene.vertices, wl.scene.indices
+    s = wl.sensors[0]
+    ctx.scene_update(0, v, f)
+    ctx.sensor_config(0, s, 0)
+    n = len(s["elevation"]) * s["rays_per_channel"]
+    d1, t1 = _cast(ctx, [0], n)
+    a = 0.3
+    rot = np.array([[math.cos(a), -math.sin(a), 0.0], [math.sin(a), math.cos(a), 0.0],
+                    [0.0, 0.0, 1.0]])
+    v2 = (v.astype(np.float64) @ rot.T + np.array([0.7, -0.3, 0.2])).astype(np.float32)
+    ctx.scene_update(0, v2, f, flags=grca.GRCA_UPDATE_VERTICES_ONLY)
+    assert np.array_equal(ctx.scene_download(0, v2.shape[0]), v2)
+    d2, t2 = _cast(ctx, [0], n)
+    assert not np.array_equal(t1, t2)
+    d3, t3 = _cast(ctx, [0], n, grca.GRCA_CAST_ALL_PAIRS)
+    assert np.array_equal(t2, t3) and np.array_equal(d2.view(np.uint32), d3.view(np.uint32))
+    ctx.scene_update(1, v2, f)
+    ctx.sensor_config(1, s, 1)
+    d4, t4 = _cast(ctx, [1], n)
+    assert np.array_equal(t2, t4) and np.array_equal(d2.view(np.uint32), d4.view(np.uint32))
+    orc = O.cast(s, v2, f, rays=np.arange(0, n, 11))
+    sel = orc["rays"]
+    rep = parity.check(s, v2, f, orc, d2[sel], t2[sel])
+    parity.assert_parity(rep, "vertex-only update")
+
+
 def test_colocated_heads(ctx):
     _say("co-located heads: 2 rigs of 4 x 90-degree heads (one head with a shorter range), "
          "one cast vs all-pairs per head and the oracle")
