@@ -399,7 +399,7 @@ DevSensor sensor_record(const SensorData& S) {
   d.cull_dmax = d.dmax * (1.0f + 1e-5f) + 1e-6f;
   d.in_dmax = d.dmax * (1.0f - 1e-5f);
   d.in_dmin = d.dmin * (1.0f + 1e-5f);
-  d.elev_m = 2e-5f + d.elev_tol;
+  d.elev_m = 3e-5f + d.elev_tol;
   d.last_chan = (float)(d.gamma - 1u);
   d.elev0_g = d.elev0 * d.inv_delev;
   d.az_noise = S.az_noise;

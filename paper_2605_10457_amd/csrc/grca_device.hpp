@@ -73,7 +73,7 @@ struct alignas(16) DevSensor {
   float elev0, inv_delev, elev_tol;
   // the sphere tests' per-sensor constants: range thresholds with their
   // margins (cull beyond dmax (1 + 1e-5) + 1e-6; wholly inside
-  // (dmin (1 + 1e-5), dmax (1 - 1e-5))), the elevation margin 2e-5 +
+  // (dmin (1 + 1e-5), dmax (1 - 1e-5))), the elevation margin 3e-5 +
   // elev_tol, the last channel index gamma - 1 and elev0 * inv_delev
   float cull_dmax, in_dmax, in_dmin, elev_m, last_chan, elev0_g;
   float eps_area;  // the apparent-area threshold epsilon_A of GRCA_LOSSY_AREA

@@ -247,13 +247,27 @@ __device__ inline float atan2_bounded(float y, float x) {
   return y < 0.0f ? -r : r;
 }
 
-// atan2_bounded for x >= 0 (the right half-plane, e.g. an elevation from a
-// horizontal distance): the same steps without the reflection for x < 0 and
-// without the guard for x = y = 0, which gives NaN here.
+// atan(t), t in [0, 1], to 1.8e-6 rad (a 6-term odd polynomial fitted for
+// this file): for the sphere tests, whose elevation margin is 3e-5 rad.
+__device__ inline float atan_unit_coarse(float t) {
+  const float u = t * t;
+  float p = -0.0116878422f;
+  p = fmaf(p, u, 0.0525693297f);
+  p = fmaf(p, u, -0.116357207f);
+  p = fmaf(p, u, 0.193514258f);
+  p = fmaf(p, u, -0.332618982f);
+  p = fmaf(p, u, 0.999977052f);
+  return p * t;
+}
+
+// atan2 for x >= 0 (the right half-plane: an elevation from a horizontal
+// distance), for the sphere tests: atan2_bounded's steps with the coarse
+// polynomial, without the reflection for x < 0 and without the guard for
+// x = y = 0, which gives NaN here.
 __device__ inline float atan2_right(float y, float x) {
   const float ay = fabsf(y);
   const float mx = fmaxf(x, ay), mn = fminf(x, ay);
-  float r = atan_unit(mn * __builtin_amdgcn_rcpf(mx));
+  float r = atan_unit_coarse(mn * __builtin_amdgcn_rcpf(mx));
   if (ay > x) r = 1.57079637f - r;
   return y < 0.0f ? -r : r;
 }
@@ -826,7 +840,7 @@ __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float r
   const bool beyond = D - r > s.cull_dmax;
   const float sa = r * invD;
   const float m = fmaf(sa * sa * (1.0f / 3.0f), sa, sa) + s.elev_m;
-  // elevation of c (in [-pi/2, pi/2], |error| <= 5e-7; NaN only at D = 0,
+  // elevation of c (in [-pi/2, pi/2], |error| <= 2e-6; NaN only at D = 0,
   // where the sphere is near)
   const float hc = __builtin_amdgcn_sqrtf(h2);
   const float el = atan2_right(lu, hc);
@@ -1031,14 +1045,14 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
   // than it saves.
   float gs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   if (group_cull) {
-    // centre: the mean of the triangles' centres (3 sums instead of the 6
-    // extrema of a box); radius: the largest vertex distance
+    // centre: the mean of the 128 slots' triangle centres (3 sums instead
+    // of the 6 extrema of a box; any centre will do, and a slot past the
+    // scene's end holds a copy of the tile's first triangle, so no masks);
+    // radius: the largest vertex distance, over the same slots
     float g[3];
-    const float inv_n = __builtin_amdgcn_rcpf((float)n_active);  // any centre will do
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      g[c] = first_lane(wave_sum_dpp((active[0] ? tc[0][c] : 0.0f) + (active[1] ? tc[1][c] : 0.0f)) *
-                        inv_n);
+      g[c] = first_lane(wave_sum_dpp(tc[0][c] + tc[1][c]) * (1.0f / 128.0f));
     float gr2 = 0.0f;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -1046,8 +1060,7 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
       for (int k = 0; k < 3; ++k) {
         const float ex = v[h][3 * k] - g[0], ey = v[h][3 * k + 1] - g[1],
                     ez = v[h][3 * k + 2] - g[2];
-        const float d2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-        if (active[h]) gr2 = fmaxf(gr2, d2);
+        gr2 = fmaxf(gr2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
       }
     }
     gs[0] = g[0];

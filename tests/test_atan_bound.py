@@ -1,6 +1,8 @@
 """CPU check of the bounds pass's FP32 atan2 (``atan2_bounded`` and ``atan_unit`` in
 grca_kernels.hip): its error bound of 5e-7 rad feeds the azimuth margin of the
 conservative candidate spans (section 3.3's angular bounding of a triangle).
+The sphere tests' elevation (``atan2_right`` with ``atan_unit_coarse``) is
+checked against its own bound of 2e-6 rad, inside their 3e-5 rad margin.
 
 The coefficients are read from the kernel source, and the FP32 evaluation is
 replayed step by step in numpy (each fmaf rounded once, the hardware
@@ -21,8 +23,8 @@ def _body(name):
     return body[:body.index("\n}\n")]
 
 
-def _coefficients():
-    poly = _body("atan_unit")
+def _coefficients(fn="atan_unit"):
+    poly = _body(fn)
     first = re.search(r"float p = (-?[0-9.e-]+)f;", poly).group(1)
     rest = re.findall(r"p = fmaf\(p, u, (-?[0-9.e-]+)f\);", poly)
     consts = re.findall(r"r = (\d\.\d+)f - r;", _body("atan2_bounded"))
@@ -76,13 +78,32 @@ def test_atan2_error_bound():
         assert err.max() <= BOUND, (ulps, err.max())
 
 
+COARSE_BOUND = 2e-6
+
+
 def test_right_half_plane_variant():
-    # atan2_right (elevations: x >= 0) takes atan2_bounded's steps minus the
-    # x < 0 reflection, so the bound above covers it; check that the source
-    # still says so: the shared polynomial, the same quarter-turn constant,
-    # no other reflection
+    # atan2_right (elevations of the sphere tests: x >= 0) takes
+    # atan2_bounded's steps with the coarse polynomial and without the x < 0
+    # reflection; check that the source still says so, then replay it
     body = _body("atan2_right")
     quarter = re.findall(r"r = (\d\.\d+)f - r;", _body("atan2_bounded"))[0]
-    assert "atan_unit(" in body and "__builtin_amdgcn_rcpf(mx)" in body
+    assert "atan_unit_coarse(" in body and "__builtin_amdgcn_rcpf(mx)" in body
     assert re.findall(r"r = (\d\.\d+)f - r;", body) == [quarter]
     assert "x < 0.0f" not in body
+    coef, consts = _coefficients("atan_unit_coarse")
+    assert len(coef) == 6
+    rng = np.random.default_rng(4321)
+    th = np.concatenate([rng.uniform(-np.pi / 2, np.pi / 2, 1_000_000),
+                         np.arange(-4, 5) * (np.pi / 8), np.arange(-4, 5) * (np.pi / 8) + 1e-6])
+    rad = 10.0 ** rng.uniform(-3, 4, th.size)
+    x = _f32(np.abs(rad * np.cos(th)))
+    y = _f32(rad * np.sin(th))
+    ref = np.arctan2(y.astype(np.float64), x.astype(np.float64))
+    for ulps in (-1.0, 0.0, 1.0):
+        got = _atan2(y, x, coef, consts, ulps).astype(np.float64)
+        err = np.abs(got - ref).max()
+        assert err <= COARSE_BOUND, (ulps, err)
+    # a planted error: the bound is tight enough to see a dropped term
+    worse = list(coef[:-2]) + [coef[-1]]
+    got = _atan2(y, x, worse, consts, 0.0).astype(np.float64)
+    assert np.abs(got - ref).max() > COARSE_BOUND
