@@ -1734,16 +1734,20 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
       a = first_lane(a);
       if (a >= n_cand) break;
       const uint32_t b = n_cand - a > ticket_cands ? a + ticket_cands : n_cand;
-      for (uint32_t ib = find_owner(qcs, n_items, a); ib < n_items; ib += 64u) {
+      uint32_t ib = find_owner(qcs, n_items, a);
+      // the stage's items and their first candidate indices; each stage
+      // issues the next stage's reads before its candidate windows
+      uint32_t nc0 = 0xFFFFFFFFu;
+      Item nit{};
+      if (ib + lane < n_items) {
+        nc0 = qcs[ib + lane];
+        nit = q[ib + lane];
+      }
+      for (; ib < n_items; ib += 64u) {
         const uint32_t i = ib + lane;
         uint32_t count = 0, skip = 0;
-        // the item and its first candidate index, both loads in flight together
-        uint32_t c0 = 0xFFFFFFFFu;
-        Item it{};
-        if (i < n_items) {
-          c0 = qcs[i];
-          it = q[i];
-        }
+        const uint32_t c0 = nc0;
+        const Item it = nit;
         const bool past = i >= n_items || c0 >= b;  // this lane's item starts at or after b
         if (!past) {
           const uint32_t rc = it.rays >> 16;
@@ -1788,6 +1792,12 @@ __global__ __launch_bounds__(WPB * 64) void isect_kernel(
           }
         }
         const bool last = __ballot(past) != 0ull;
+        nc0 = 0xFFFFFFFFu;
+        nit = Item{};
+        if (!last && i + 64u < n_items) {
+          nc0 = qcs[i + 64u];
+          nit = q[i + 64u];
+        }
         const uint32_t incl = wave_incl_scan(count);
         const uint32_t excl = incl - count;  // batch position of this item's first candidate
         if (count) in_s[w][lane].bias = (int32_t)skip - (int32_t)excl;
