@@ -33,6 +33,9 @@ struct SceneData {
   float4* v = nullptr;       // vertex positions (x, y, z, 0)
   float4* soup = nullptr;    // vertex records of the all-static triangles (slots [0, n_soup))
   uint32_t n_soup = 0;
+  float4* tsph = nullptr;    // bounding spheres of the first n_pre tiles (triangles, tiles)
+  float4* gsph = nullptr;
+  uint32_t n_pre = 0;
   uint32_t* idx = nullptr;   // index triples in tile order (Morton within dynamic groups)
   uint32_t* orig = nullptr;  // caller triangle id of each stored slot
   // rigid instances
@@ -86,7 +89,7 @@ void dfree(T*& p) {
 }
 
 void free_scene(SceneData& s) {
-  dfree(s.v); dfree(s.soup); dfree(s.idx); dfree(s.orig);
+  dfree(s.v); dfree(s.soup); dfree(s.tsph); dfree(s.gsph); dfree(s.idx); dfree(s.orig);
   dfree(s.rr_x); dfree(s.rr_y); dfree(s.rr_z); dfree(s.rigid_blocks);
   dfree(s.dr_x); dfree(s.dr_y); dfree(s.dr_z);
   dfree(s.dn_x); dfree(s.dn_y); dfree(s.dn_z); dfree(s.dphase);
@@ -107,8 +110,10 @@ void free_sensor(SensorData& s) {
 // and its tile-sphere test culls more.  `orig` keeps the caller's ids.
 hipError_t reorder_scene_dev(SceneData& sc, hipStream_t st) {
   dfree(sc.soup);
-  sc.soup = nullptr;
-  sc.n_soup = 0;
+  dfree(sc.tsph);
+  dfree(sc.gsph);
+  sc.soup = sc.tsph = sc.gsph = nullptr;
+  sc.n_soup = sc.n_pre = 0;
   if (sc.ntri == 0 || sc.nv == 0) return hipSuccess;
   uint32_t* vg = nullptr;
   hipError_t e = dmalloc(&vg, sc.nv);
@@ -133,12 +138,23 @@ hipError_t reorder_scene_dev(SceneData& sc, hipStream_t st) {
     if (e == hipSuccess) e = launch_soup(sc.idx, sc.v, n_soup, sc.soup, st);
     if (e == hipSuccess) sc.n_soup = n_soup;
   }
+  // and the bounding spheres of the full tiles among them
+  const uint32_t n_pre = sc.n_soup / BOUNDS_TILE;
+  if (e == hipSuccess && n_pre) {
+    e = dmalloc(&sc.tsph, (size_t)n_pre * BOUNDS_TILE);
+    if (e == hipSuccess) e = dmalloc(&sc.gsph, n_pre);
+    if (e == hipSuccess) e = launch_spheres(sc.soup, n_pre, sc.tsph, sc.gsph, st);
+    if (e == hipSuccess) sc.n_pre = n_pre;
+  }
   return e;
 }
 
-// Rewrite the static triangles' vertex records after their vertices changed.
+// Rewrite the static triangles' vertex records and spheres after their
+// vertices changed.
 hipError_t refresh_soup(SceneData& sc, hipStream_t st) {
-  return launch_soup(sc.idx, sc.v, sc.n_soup, sc.soup, st);
+  hipError_t e = launch_soup(sc.idx, sc.v, sc.n_soup, sc.soup, st);
+  if (e == hipSuccess) e = launch_spheres(sc.soup, sc.n_pre, sc.tsph, sc.gsph, st);
+  return e;
 }
 
 }  // namespace
@@ -469,6 +485,7 @@ grca_status make_plan(grca_context* ctx, const uint32_t* ids, uint32_t n, uint32
       const SceneData& sc = ctx->scenes.at(sid);
       DevScene ds{};
       ds.v = sc.v; ds.soup = sc.soup; ds.n_soup = sc.n_soup; ds.idx = sc.idx; ds.orig = sc.orig;
+      ds.tsph = sc.tsph; ds.gsph = sc.gsph; ds.n_pre = sc.n_pre;
       ds.ntri = sc.ntri;
       ds.tile_start = tiles;
       ds.sensor_begin = k;

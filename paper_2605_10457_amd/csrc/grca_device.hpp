@@ -104,6 +104,12 @@ struct DevScene {
   // intersection reads a static triangle here in one round trip instead of
   // its indices and then its vertices
   const float4* soup;
+  // bounding spheres of the first n_pre tiles (all-static, full tiles),
+  // computed at scene setup as the bounds pass would: per triangle (tsph,
+  // 128 per tile) and per tile (gsph)
+  const float4* tsph;
+  const float4* gsph;
+  uint32_t n_pre;
   const uint32_t* idx;   // index triples in tile order
   const uint32_t* orig;  // caller triangle id of each stored slot (keys and outputs use it)
   uint32_t ntri;

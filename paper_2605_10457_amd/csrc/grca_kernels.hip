@@ -957,6 +957,85 @@ __device__ inline uint32_t item_candidates(const Item& it) {
 // the spills cost more than the extra wave gains).
 constexpr int BOUNDS_WAVES_PER_SIMD = 7;
 
+// Bounding spheres of a lane's two triangles (AABB centre, largest vertex
+// distance) and of the wave's 128-triangle tile (wave-uniform: the mean of
+// the 128 slots' triangle centres, the largest vertex distance from it; any
+// centre will do, and a slot past the scene's end holds a copy of the tile's
+// first triangle, so no masks).  The same arithmetic at scene setup and in
+// the bounds pass.
+__device__ inline void tri_spheres(const float (&v)[2][9], float (&tc)[2][4]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float mn[3], mx[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      mn[c] = fminf(v[h][c], fminf(v[h][3 + c], v[h][6 + c]));
+      mx[c] = fmaxf(v[h][c], fmaxf(v[h][3 + c], v[h][6 + c]));
+      tc[h][c] = 0.5f * (mn[c] + mx[c]);
+    }
+    float r2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float ex = v[h][3 * k] - tc[h][0], ey = v[h][3 * k + 1] - tc[h][1],
+                  ez = v[h][3 * k + 2] - tc[h][2];
+      r2 = fmaxf(r2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+    }
+    // hardware square root (1 ulp; a denormal r2 may give 0): the sphere
+    // tests widen every radius by 1e-4 relative and 1e-6 m
+    tc[h][3] = __builtin_amdgcn_sqrtf(r2);
+  }
+}
+__device__ inline void tile_sphere(const float (&v)[2][9], const float (&tc)[2][4],
+                                   float (&gs)[4]) {
+  float g[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    g[c] = first_lane(wave_sum_dpp(tc[0][c] + tc[1][c]) * (1.0f / 128.0f));
+  float gr2 = 0.0f;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float ex = v[h][3 * k] - g[0], ey = v[h][3 * k + 1] - g[1],
+                  ez = v[h][3 * k + 2] - g[2];
+      gr2 = fmaxf(gr2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+    }
+  }
+  gs[0] = g[0];
+  gs[1] = g[1];
+  gs[2] = g[2];
+  gs[3] = first_lane(__builtin_amdgcn_sqrtf(wave_max_dpp(gr2)));
+}
+
+// Scene setup: the spheres of the n_pre leading tiles, one wave per tile,
+// from the static triangles' vertex records.
+__global__ __launch_bounds__(256) void sphere_kernel(const float4* __restrict__ soup,
+                                                     uint32_t n_pre, float4* __restrict__ tsph,
+                                                     float4* __restrict__ gsph) {
+  const uint32_t tile = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (tile >= n_pre) return;  // wave-uniform
+  const uint32_t lane = lane_id();
+  float v[2][9];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t t = tile * BOUNDS_TILE + 64u * h + lane;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float4 p = soup[3ull * t + k];
+      v[h][3 * k] = p.x;
+      v[h][3 * k + 1] = p.y;
+      v[h][3 * k + 2] = p.z;
+    }
+  }
+  float tc[2][4], gs[4];
+  tri_spheres(v, tc);
+  tile_sphere(v, tc, gs);
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    tsph[(size_t)tile * BOUNDS_TILE + 64u * h + lane] = make_float4(tc[h][0], tc[h][1], tc[h][2], tc[h][3]);
+  if (lane == 0) gsph[tile] = make_float4(gs[0], gs[1], gs[2], gs[3]);
+}
+
 template <int WPB, bool INLINE, bool LOSSY>
 __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SIMD) void bounds_kernel(
     const DevScene* __restrict__ scenes, uint32_t nscenes, uint32_t total_tiles,
@@ -990,84 +1069,52 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
   // the lane's two triangles; lanes past the scene's last triangle load the
   // tile's first one (no branch) and are masked.  Loads take the arrays'
   // scalar bases and 32-bit byte offsets (the library keeps every scene
-  // under 2^28 triangles and 2^28 vertices).
-  float v[2][9];
+  // under 2^28 triangles and 2^28 vertices).  A leading all-static tile
+  // reads its spheres as computed at scene setup, and the span phase reads
+  // its vertices from the record copies; other tiles gather their vertices,
+  // park them in LDS for the span phase and compute the spheres here.
+  const bool pre = first_lane(tile - S.tile_start) < first_lane(S.n_pre);
   bool active[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const uint32_t t = tri0 + 64u * h + lane;
-    active[h] = t < ntri;
-    const uint32_t tt = active[h] ? t : tri0;
-    // (indices, then the vertex records: reading the static triangles'
-    // record copies instead fetches 48 B per triangle where neighbouring
-    // triangles share vertices, and was slower here)
-    const Tri3 ti = gload_tri(S.idx, 12u * tt);
-    const float4 p[3] = {gload_v(S.v, ti.a * 16u), gload_v(S.v, ti.b * 16u),
-                         gload_v(S.v, ti.c * 16u)};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      v[h][3 * k] = p[k].x;
-      v[h][3 * k + 1] = p[k].y;
-      v[h][3 * k + 2] = p[k].z;
-    }
-  }
-  // bounding spheres (AABB centre, largest vertex distance) of the lane's
-  // triangles and of the tile; the span phase reads vertices from LDS
   float tc[2][4];  // centre x, y, z and radius, per triangle
+  float gs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (pre) {
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    float mn[3], mx[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      mn[c] = fminf(v[h][c], fminf(v[h][3 + c], v[h][6 + c]));
-      mx[c] = fmaxf(v[h][c], fmaxf(v[h][3 + c], v[h][6 + c]));
-      tc[h][c] = 0.5f * (mn[c] + mx[c]);
+    for (int h = 0; h < 2; ++h) {
+      active[h] = true;
+      const float4 q = gload_v(S.tsph, 16u * (tri0 + 64u * h + lane));
+      tc[h][0] = q.x; tc[h][1] = q.y; tc[h][2] = q.z; tc[h][3] = q.w;
     }
-    float r2 = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const float ex = v[h][3 * k] - tc[h][0], ey = v[h][3 * k + 1] - tc[h][1],
-                  ez = v[h][3 * k + 2] - tc[h][2];
-      r2 = fmaxf(r2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+    if (group_cull) {
+      typedef float v4f __attribute__((ext_vector_type(4)));
+      typedef const v4f __attribute__((address_space(4))) CT4;
+      const v4f g = *(CT4*)(S.gsph + (tile - S.tile_start));
+      gs[0] = first_lane(g.x); gs[1] = first_lane(g.y);
+      gs[2] = first_lane(g.z); gs[3] = first_lane(g.w);
     }
-    // hardware square root (1 ulp; a denormal r2 may give 0): the sphere
-    // tests widen every radius by 1e-4 relative and 1e-6 m
-    tc[h][3] = __builtin_amdgcn_sqrtf(r2);
+  } else {
+    float v[2][9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) vtx[c][64 * h + lane] = v[h][c];
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t t = tri0 + 64u * h + lane;
+      active[h] = t < ntri;
+      const uint32_t tt = active[h] ? t : tri0;
+      const Tri3 ti = gload_tri(S.idx, 12u * tt);
+      const float4 p[3] = {gload_v(S.v, ti.a * 16u), gload_v(S.v, ti.b * 16u),
+                           gload_v(S.v, ti.c * 16u)};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        v[h][3 * k] = p[k].x;
+        v[h][3 * k + 1] = p[k].y;
+        v[h][3 * k + 2] = p[k].z;
+      }
+#pragma unroll
+      for (int c = 0; c < 9; ++c) vtx[c][64 * h + lane] = v[h][c];
+    }
+    tri_spheres(v, tc);
+    if (group_cull) tile_sphere(v, tc, gs);
   }
   const uint32_t n_active = first_lane((uint32_t)(__popcll(__ballot(active[0])) +
                                                   __popcll(__ballot(active[1]))));
-  // the tile's sphere (wave-uniform: scalar registers).  One sphere for both
-  // halves: the halves' own spheres would skip 1-2% fewer sensor steps for
-  // twice the reductions; the centre of the box of the vertices gives a
-  // slightly tighter test for 6 reductions instead of 3, which costs more
-  // than it saves.
-  float gs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  if (group_cull) {
-    // centre: the mean of the 128 slots' triangle centres (3 sums instead
-    // of the 6 extrema of a box; any centre will do, and a slot past the
-    // scene's end holds a copy of the tile's first triangle, so no masks);
-    // radius: the largest vertex distance, over the same slots
-    float g[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      g[c] = first_lane(wave_sum_dpp(tc[0][c] + tc[1][c]) * (1.0f / 128.0f));
-    float gr2 = 0.0f;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const float ex = v[h][3 * k] - g[0], ey = v[h][3 * k + 1] - g[1],
-                    ez = v[h][3 * k + 2] - g[2];
-        gr2 = fmaxf(gr2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
-      }
-    }
-    gs[0] = g[0];
-    gs[1] = g[1];
-    gs[2] = g[2];
-    gs[3] = first_lane(__builtin_amdgcn_sqrtf(wave_max_dpp(gr2)));
-  }
   unsigned long long rtic = 0ull;  // candidates tested inline by this lane
   unsigned long long g_cull = 0ull, g_range = ~0ull, g_pole = ~0ull, g_fov = 0ull;
   uint32_t tested = 0;     // triangle sphere tests of this wave (wave-uniform statistic)
@@ -1140,11 +1187,21 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
     const uint32_t src = e & 127u;
     const uint32_t pn = live ? (e >> 9) : s_begin;
     float px[3], py[3], pz[3];
+    if (pre) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      px[k] = vtx[3 * k][src];
-      py[k] = vtx[3 * k + 1][src];
-      pz[k] = vtx[3 * k + 2][src];
+      for (int k = 0; k < 3; ++k) {
+        const float4 q = gload_v(S.soup, 48u * (tri0 + src) + 16u * (uint32_t)k);
+        px[k] = q.x;
+        py[k] = q.y;
+        pz[k] = q.z;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        px[k] = vtx[3 * k][src];
+        py[k] = vtx[3 * k + 1][src];
+        pz[k] = vtx[3 * k + 2][src];
+      }
     }
     const uint32_t ptri = tri0 + src;
     // (at most 4096 sensor slots per cast: a 32-bit offset)
@@ -2206,6 +2263,14 @@ hipError_t launch_validate(const float* xyz, uint32_t nv, const uint32_t* idx, u
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(validate_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, xyz, nv, idx, nidx,
                      bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_spheres(const float4* soup, uint32_t n_pre, float4* tsph, float4* gsph,
+                          hipStream_t st) {
+  if (n_pre == 0) return hipSuccess;
+  hipLaunchKernelGGL(sphere_kernel, dim3(cdiv(n_pre, 4)), dim3(256), 0, st, soup, n_pre, tsph,
+                     gsph);
   return hipGetLastError();
 }
 

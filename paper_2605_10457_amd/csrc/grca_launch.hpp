@@ -66,6 +66,10 @@ hipError_t launch_sensor_tables(const float* elev, const float* el_off, uint32_t
                                 ChanBin* lut, hipStream_t st);
 hipError_t launch_validate(const float* xyz, uint32_t nv, const uint32_t* idx, uint64_t nidx,
                            uint32_t* bad, hipStream_t st);
+// the bounding spheres of the first n_pre tiles from their triangles' vertex
+// records (soup): 128 per tile into tsph, one per tile into gsph
+hipError_t launch_spheres(const float4* soup, uint32_t n_pre, float4* tsph, float4* gsph,
+                          hipStream_t st);
 // caller's packed xyz -> padded (x, y, z, 0) vertices
 hipError_t launch_pad(const float* xyz, uint32_t nv, float4* v, hipStream_t st);
 // padded vertices -> three coordinate arrays (rest positions of the pose step)
