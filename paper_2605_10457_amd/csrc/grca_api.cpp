@@ -965,12 +965,12 @@ std::vector<PoseBlock> pose_blocks(uint32_t kind, const std::vector<uint32_t>& s
   std::vector<PoseBlock> out;
   uint32_t rest = 0;
   for (size_t g = 0; g < starts.size(); ++g) {
-    for (uint32_t o = 0; o < counts[g]; o += 256) {
+    for (uint32_t o = 0; o < counts[g]; o += POSE_BLOCK_VERTS) {
       PoseBlock b{};
       b.kind = kind;
       b.group = (uint32_t)g;
       b.v_begin = starts[g] + o;
-      b.count = std::min(256u, counts[g] - o);
+      b.count = std::min(POSE_BLOCK_VERTS, counts[g] - o);
       b.rest_begin = rest + o;
       out.push_back(b);
     }

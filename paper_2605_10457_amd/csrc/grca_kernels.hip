@@ -2035,7 +2035,8 @@ __global__ void resolve_kernel(const unsigned long long* __restrict__ keys, uint
 
 // ------------------------------------------------------------------ pose
 // One launch for both kinds: blocks [0, n_rigid) are rigid-instance blocks,
-// the rest deform-group blocks; each handles up to 256 vertices.
+// the rest deform-group blocks; each thread poses the block's vertices
+// i, i + 256, i + 512 and i + 768 (their loads in flight together).
 __global__ __launch_bounds__(256) void pose_kernel(
     const PoseBlock* __restrict__ rblocks, uint32_t n_rigid, const float* __restrict__ rrx,
     const float* __restrict__ rry, const float* __restrict__ rrz,
@@ -2044,27 +2045,47 @@ __global__ __launch_bounds__(256) void pose_kernel(
     const float* __restrict__ ny, const float* __restrict__ nz, const float* __restrict__ phase,
     const DeformParam* __restrict__ groups, const double* __restrict__ pose_in,
     float4* __restrict__ out) {
+  constexpr uint32_t PER = POSE_BLOCK_VERTS / 256;
   const bool rigid = blockIdx.x < n_rigid;
   const PoseBlock pb = rigid ? rblocks[blockIdx.x] : dblocks[blockIdx.x - n_rigid];
-  const uint32_t i = threadIdx.x;
-  if (i >= pb.count) return;
-  const uint32_t v = pb.v_begin + i;
-  const uint32_t r = pb.rest_begin + i;
   if (rigid) {
-    const double px = rrx[r], py = rry[r], pz = rrz[r];
     const float* M = reinterpret_cast<const float*>(pose_in + 1) + 12ull * pb.group;
-    out[v] = make_float4(
-        (float)((double)M[0] * px + (double)M[1] * py + (double)M[2] * pz + (double)M[3]),
-        (float)((double)M[4] * px + (double)M[5] * py + (double)M[6] * pz + (double)M[7]),
-        (float)((double)M[8] * px + (double)M[9] * py + (double)M[10] * pz + (double)M[11]),
-        0.0f);
+    float x[PER], y[PER], z[PER];
+#pragma unroll
+    for (uint32_t k = 0; k < PER; ++k) {  // (clamped: every load in bounds, all in flight)
+      const uint32_t r = pb.rest_begin + min(threadIdx.x + 256u * k, pb.count - 1u);
+      x[k] = rrx[r]; y[k] = rry[r]; z[k] = rrz[r];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < PER; ++k) {
+      const uint32_t i = threadIdx.x + 256u * k;
+      if (i >= pb.count) break;
+      const double px = x[k], py = y[k], pz = z[k];
+      out[pb.v_begin + i] = make_float4(
+          (float)((double)M[0] * px + (double)M[1] * py + (double)M[2] * pz + (double)M[3]),
+          (float)((double)M[4] * px + (double)M[5] * py + (double)M[6] * pz + (double)M[7]),
+          (float)((double)M[8] * px + (double)M[9] * py + (double)M[10] * pz + (double)M[11]),
+          0.0f);
+    }
   } else {
-    const double px = drx[r], py = dry[r], pz = drz[r];
     const DeformParam g = groups[pb.group];
     const double time = pose_in[0];
-    const double wv = (double)g.amplitude * sin((double)g.omega * time + (double)phase[r]);
-    out[v] = make_float4((float)(px + wv * (double)nx[r]), (float)(py + wv * (double)ny[r]),
-                         (float)(pz + wv * (double)nz[r]), 0.0f);
+    float x[PER], y[PER], z[PER], ux[PER], uy[PER], uz[PER], ph[PER];
+#pragma unroll
+    for (uint32_t k = 0; k < PER; ++k) {  // (clamped: every load in bounds, all in flight)
+      const uint32_t r = pb.rest_begin + min(threadIdx.x + 256u * k, pb.count - 1u);
+      x[k] = drx[r]; y[k] = dry[r]; z[k] = drz[r];
+      ux[k] = nx[r]; uy[k] = ny[r]; uz[k] = nz[r]; ph[k] = phase[r];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < PER; ++k) {
+      const uint32_t i = threadIdx.x + 256u * k;
+      if (i >= pb.count) break;
+      const double wv = (double)g.amplitude * sin((double)g.omega * time + (double)ph[k]);
+      out[pb.v_begin + i] = make_float4((float)((double)x[k] + wv * (double)ux[k]),
+                                        (float)((double)y[k] + wv * (double)uy[k]),
+                                        (float)((double)z[k] + wv * (double)uz[k]), 0.0f);
+    }
   }
 }
 

@@ -9,13 +9,17 @@
 
 namespace grca {
 
-// One block of the pose kernel: up to 256 vertices of one rigid instance
-// (kind 0, `group` = instance index) or one deform group (kind 1).
+// Vertices per block of the pose kernel (256 threads, four vertices each,
+// whose loads are in flight together).
+constexpr uint32_t POSE_BLOCK_VERTS = 1024;
+
+// One block of the pose kernel: up to POSE_BLOCK_VERTS vertices of one rigid
+// instance (kind 0, `group` = instance index) or one deform group (kind 1).
 struct PoseBlock {
   uint32_t kind;
   uint32_t group;
   uint32_t v_begin;    // first scene vertex of this block
-  uint32_t count;      // vertices in this block (<= 256)
+  uint32_t count;      // vertices in this block (<= POSE_BLOCK_VERTS)
   uint32_t rest_begin; // first entry in the rest / normal / phase arrays
   uint32_t pad[3];
 };
