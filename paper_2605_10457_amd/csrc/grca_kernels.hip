@@ -1456,20 +1456,32 @@ __global__ __launch_bounds__(WPB * 64) void expand_kernel(
   Item* const q_items = items + (size_t)out_shard * item_scap;
   uint32_t* const q_cs = item_cs + (size_t)out_shard * item_scap;
   uint32_t rows = 0;  // row items this wave appended (statistic)
+  // records dealt statically: the waves walking a shard take every
+  // walkers-th record from their rank (no ticket round trip; a record's
+  // work varies little)
+  const uint32_t gw = blockIdx.x * WPB + wave_id();
+  const uint32_t rank = gw / sw.step;
+  const uint32_t walkers = (gridDim.x * WPB - sw.first + sw.step - 1u) / sw.step;
   for (uint32_t sh = sw.first; sh < NSHARD; sh += sw.step) {
     const uint32_t n_large = min((uint32_t)cnt->large[sh].nc, large_scap);
     const Item* const q_large = large + (size_t)sh * large_scap;
-    for (;;) {
-      uint32_t rec = 0;
-      if (lane == 0) rec = atomicAdd(&cnt->large[sh].tk, 1u);
-      rec = first_lane(rec);
-      if (rec >= n_large) break;
+    for (uint32_t rec = rank; rec < n_large; rec += walkers) {
       const Item L = q_large[rec];
       const DevSensor& s = sens[L.sensor];
       const DevScene& S = scenes[s.scene];
       const uint32_t t = L.tri;
-      const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
-      const float4 p0 = S.v[i0], p1 = S.v[i1], p2 = S.v[i2];
+      // a static triangle's vertex records in one round trip
+      float4 p0, p1, p2;
+      if (t < S.n_soup) {
+        p0 = S.soup[3ull * t];
+        p1 = S.soup[3ull * t + 1];
+        p2 = S.soup[3ull * t + 2];
+      } else {
+        const uint32_t i0 = S.idx[3ull * t], i1 = S.idx[3ull * t + 1], i2 = S.idx[3ull * t + 2];
+        p0 = S.v[i0];
+        p1 = S.v[i1];
+        p2 = S.v[i2];
+      }
       Statics st;
       double nrm[3][3];
       if (!make_statics(p0.x, p0.y, p0.z, p1.x, p1.y, p1.z, p2.x, p2.y, p2.z, s, st, nrm))
