@@ -941,11 +941,13 @@ __device__ inline uint32_t item_candidates(const Item& it) {
 // two triangles.  Two phases over the sensors observing the tile's scene:
 //  1. one bounding-sphere test of the whole tile (lane k tests sensor k of
 //     each run of 64 sensors) skips a sensor; otherwise each lane tests its
-//     triangles' own bounding spheres against the sensor (elevation band and
-//     range only) and the surviving (triangle, sensor) pairs are queued in
-//     the wave's LDS ring;
+//     triangles' own bounding spheres against the sensor (elevation band,
+//     range, and the field of view where the tile straddles its edge) and
+//     the surviving (triangle, sensor) pairs are queued in the wave's LDS
+//     ring;
 //  2. whenever 64 pairs are queued, and at the end, every lane takes one
-//     pair, reads the triangle's vertices from LDS and computes the pair's
+//     pair, reads the triangle's vertices (from LDS, or from the record
+//     copies for a tile of static triangles) and computes the pair's
 //     candidate span, with the sensor read per lane.
 // Most pairs that pass the tile's test fail their triangle's own test (small
 // triangles between two channels), so the span, the costly part, runs on
