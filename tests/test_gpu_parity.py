@@ -133,7 +133,9 @@ def test_batch_equals_alone_bitwise(ctx):
                                   dict(small_channels=255, small_rays=4096, row_chunk=7),
                                   dict(bounds_block=64, persist_waves_cu=1),
                                   dict(bounds_block=1024, row_chunk=4096),
-                                  dict(group_cull=0)])
+                                  dict(group_cull=0),
+                                  dict(isect_ticket=64),
+                                  dict(isect_ticket=192, row_chunk=3)])
 def test_options_do_not_change_results(ctx, opts):
     _say(f"tuning options {opts}")
     wl = synth.config1()
