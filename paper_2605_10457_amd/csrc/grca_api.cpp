@@ -1,7 +1,8 @@
 // grca_api.cpp -- host runtime behind the C ABI of include/grca.h.
 //
-// Owns the device-resident scenes (SoA vertices + indices, rest geometry of
-// dynamic ranges), the sensor tables, the per-cast workspaces (ray keys, work
+// Owns the device-resident scenes (16-byte vertex records + indices, the
+// static triangles' record copies and spheres, rest geometry of dynamic
+// ranges), the sensor tables, the per-cast workspaces (ray keys, work
 // queues, counters) and the hipGraph frames.  Every step of a cast runs in
 // the HIP kernels of grca_kernels.hip; this file validates inputs, sizes
 // buffers, enqueues launches and handles queue overflow by growing and
