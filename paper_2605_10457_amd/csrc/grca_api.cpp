@@ -745,7 +745,7 @@ extern "C" grca_status grca_create(int hip_device, grca_context** out) {
   ctx->opt.persist_waves_cu = 16;
   ctx->opt.group_cull = 1;
   ctx->opt.inline_max = 0;
-  ctx->opt.isect_ticket = 2048;
+  ctx->opt.isect_ticket = 4096;
   ctx->opt.eps_area = 1e-6f;
   ctx->opt.item_capacity = 1u << 20;
   ctx->opt.large_capacity = 1u << 16;

@@ -132,7 +132,7 @@ struct alignas(256) Shard {
   // 64-bit atomic keeps both in the same order.  Large-record shards use the
   // low word only.
   unsigned long long nc;
-  uint32_t tk;              // consumer ticket (candidates for items, records for large)
+  uint32_t tk;              // tickets handed out by the intersection (item shards)
   uint32_t rows;            // row items appended by the expansion (statistic)
   unsigned long long rtic;  // candidate pairs executed from this shard (statistic)
   unsigned long long pairs; // (triangle, origin) spans computed (statistic)
