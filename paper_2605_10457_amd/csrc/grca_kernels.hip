@@ -1775,7 +1775,7 @@ __device__ inline uint32_t find_owner(const uint32_t* __restrict__ cs, uint32_t 
 // the same whatever the sizes of the items in it.  Invalid pairs (degenerate,
 // or back-facing under single-sided casting) contribute no candidates.
 // Candidates per lane per window of the intersection's flattened loop: 4
-// keeps it at 114 VGPRs (4 waves per SIMD) and measured 0.259 ms against
+// keeps it under 128 VGPRs (4 waves per SIMD) and measured 0.259 ms against
 // 0.263 ms for 2 and 0.282 ms for 6 (3 waves per SIMD) on the ring workload.
 constexpr int ISECT_SLOTS = 4;
 // A shard's last (waves serving it) x ticket_cands candidates are handed out
