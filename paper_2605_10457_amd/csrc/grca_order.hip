@@ -118,15 +118,18 @@ __global__ void order_gather_kernel(const uint32_t* __restrict__ idx_in,
 
 // Triangles whose three vertices are all static (group 0), counted with one
 // atomic per wave.
+// Grid-stride count, one atomic per wave at the end: the waves of a
+// one-per-triangle grid (344k on 22M triangles) had queued on the one
+// counter for 3 ms.
 __global__ void count_static_kernel(const uint32_t* __restrict__ idx, uint32_t ntri,
                                     const uint32_t* __restrict__ vgroup,
                                     uint32_t* __restrict__ out) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  bool st = false;
-  if (t < ntri)
-    st = (vgroup[idx[3ull * t]] | vgroup[idx[3ull * t + 1]] | vgroup[idx[3ull * t + 2]]) == 0u;
-  const unsigned long long m = __ballot(st);
-  if ((threadIdx.x & 63u) == 0u && m) atomicAdd(out, (uint32_t)__popcll(m));
+  uint32_t c = 0;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntri; t += gridDim.x * blockDim.x)
+    c += (vgroup[idx[3ull * t]] | vgroup[idx[3ull * t + 1]] | vgroup[idx[3ull * t + 2]]) == 0u;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63u) == 0u && c) atomicAdd(out, c);
 }
 
 // The vertex records of slots [0, n): soup[3 t + k] = v[idx[3 t + k]].
@@ -165,8 +168,8 @@ hipError_t count_static(const uint32_t* idx, uint32_t ntri, const uint32_t* vgro
   hipError_t e = hipMalloc(&d, sizeof(uint32_t));
   if (e != hipSuccess) return e;
   if ((e = hipMemsetAsync(d, 0, sizeof(uint32_t), st)) == hipSuccess) {
-    hipLaunchKernelGGL(count_static_kernel, dim3(cdiv(ntri, 256)), dim3(256), 0, st, idx, ntri,
-                       vgroup, d);
+    hipLaunchKernelGGL(count_static_kernel, dim3((uint32_t)std::min<uint64_t>(cdiv(ntri, 256), 2048)),
+                       dim3(256), 0, st, idx, ntri, vgroup, d);
     if ((e = hipGetLastError()) == hipSuccess)
       e = hipMemcpyAsync(n_static, d, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
   }
