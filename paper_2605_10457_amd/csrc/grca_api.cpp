@@ -433,6 +433,8 @@ DevSensor sensor_record(const SensorData& S) {
       d.fov_n[3] = (float)-std::cos(hi);
     }
   }
+  d.upright = std::fabs(d.u[0]) + std::fabs(d.u[1]) <= 1e-4f && d.u[2] > 0.0f ? 1u : 0u;
+  d.pad_[0] = d.pad_[1] = d.pad_[2] = 0u;
   d.key_offset = 0;
   d.scene = 0;
   d.cull_back = 0;

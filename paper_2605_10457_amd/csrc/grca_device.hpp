@@ -86,6 +86,10 @@ struct alignas(16) DevSensor {
   // plus the azimuth noise
   uint32_t fov_mode;
   float fov_n[4];
+  // 1: the up axis is the world z axis within 1e-4 (|u_x| + |u_y|), so that
+  // the triangle tests may bound a triangle by an upright cylinder
+  uint32_t upright;
+  uint32_t pad_[3];
 };
 
 static_assert(sizeof(DevSensor) % 16 == 0 && offsetof(DevSensor, dmin) % 16 == 0 &&

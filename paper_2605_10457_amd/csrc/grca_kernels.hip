@@ -806,6 +806,18 @@ __device__ inline FovVerdict fov_verdict(float lf, float lr, float D, float r,
   return v;
 }
 
+// A non-negative float as the bits of the next FP16 value at or above it
+// (+inf above the FP16 range), and back.
+__device__ inline uint32_t half_up(float x) {
+  const _Float16 h = (_Float16)x;
+  uint32_t b = (uint32_t)__builtin_bit_cast(uint16_t, h);
+  if ((float)h < x) ++b;
+  return b;
+}
+__device__ inline float unpack_half(uint32_t b) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)b);
+}
+
 // A bounding sphere (centre c, radius rad) against sensor `s`, without
 // memory access besides the sensor's fields and without branches (so that
 // the fields are read together); about 70 FP32 operations, 80 with AZ.
@@ -822,27 +834,61 @@ __device__ inline FovVerdict fov_verdict(float lf, float lr, float D, float r,
 // and for single triangles.  want_range / want_pole / want_fov (wave-uniform)
 // skip the parts whose verdict the caller will not use: false gives
 // need_range = need_pole = false and no field-of-view test.
-template <bool AZ>
+//
+// TRI: a triangle's test, `rad` holding the bits of its packed cylinder
+// (pack_cylinder): horizontal radius rh and vertical half-height hz about c,
+// both already widened.  The sphere radius is then sqrt(rh^2 + hz^2), and for
+// a sensor whose up axis is the world z axis the angular margin is the
+// cylinder's instead of the sphere's: every point of the triangle has height
+// z within hz of c's and horizontal distance rho within rh of c's, and on that
+// box in the (z, rho) plane the elevation atan2(z, rho) has
+// |d/dz| = rho / D^2 <= (rho_c + rh) / D_min^2 and |d/drho| = |z| / D^2 <=
+// (|z_c| + hz) / D_min^2, with D_min >= D - r, so that (mean value theorem)
+// its elevation is within ((rho_c + rh) hz + (|z_c| + hz) rh) / (D - r)^2 of
+// c's.  For a ground triangle at a shallow angle (hz ~ 0) that is sin|el|
+// times the sphere's margin.
+template <bool AZ, bool TRI = false>
 __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float rad,
                                            const DevSensor& s, bool want_range = true,
                                            bool want_pole = true, bool want_fov = true) {
+  float r, rh = 0.0f, hz = 0.0f;
+  if (TRI) {
+    uint32_t pk = __float_as_uint(rad);
+    // (an empty asm that the compiler must take as changing pk: the unpacked
+    // values are recomputed per test rather than hoisted out of the caller's
+    // sensor loop, where they would hold three more registers per triangle)
+    asm volatile("" : "+v"(pk));
+    rh = unpack_half(pk & 0xFFFFu);
+    hz = unpack_half(pk >> 16);
+    r = __builtin_amdgcn_sqrtf(fmaf(rh, rh, hz * hz));
+  } else {
+    r = rad * 1.0001f + 1e-6f;
+  }
   const float dx = cx - s.o[0], dy = cy - s.o[1], dz = cz - s.o[2];
   const float lf = fmaf(dx, s.f[0], fmaf(dy, s.f[1], dz * s.f[2]));
   const float lr = fmaf(dx, s.r[0], fmaf(dy, s.r[1], dz * s.r[2]));
   const float lu = fmaf(dx, s.u[0], fmaf(dy, s.u[1], dz * s.u[2]));
   const float h2 = fmaf(lf, lf, lr * lr);
   const float D2 = fmaf(lu, lu, h2);
-  const float r = rad * 1.0001f + 1e-6f;
   const float r2 = r * r;
   const bool near = D2 <= 4.0f * r2;  // the origin is within 2r: keep
   const float invD = __builtin_amdgcn_rsqf(D2);
   const float D = D2 * invD;
   const bool beyond = D - r > s.cull_dmax;
-  const float sa = r * invD;
-  const float m = fmaf(sa * sa * (1.0f / 3.0f), sa, sa) + s.elev_m;
   // elevation of c (in [-pi/2, pi/2], |error| <= 2e-6; NaN only at D = 0,
   // where the sphere is near)
   const float hc = __builtin_amdgcn_sqrtf(h2);
+  float m;
+  if (TRI && s.upright) {
+    // (used only when far: D > 2 r, so D - r > r > 0; the factor 1.0001
+    // covers the FP32 error of D - r)
+    const float inv = __builtin_amdgcn_rcpf(D - r);
+    const float num = fmaf(hc + rh, hz, (fabsf(lu) + hz) * rh);
+    m = fmaf(num * inv, inv * 1.0001f, s.elev_m);
+  } else {
+    const float sa = r * invD;
+    m = fmaf(sa * sa * (1.0f / 3.0f), sa, sa) + s.elev_m;
+  }
   const float el = atan2_right(lu, hc);
   // grid coordinates of el -+ m: (el - elev0) / delev -+ m / delev (the
   // roundings are a few ulps of a channel index, far inside the margin)
@@ -965,6 +1011,18 @@ constexpr int BOUNDS_WAVES_PER_SIMD = 7;
 // centre will do, and a slot past the scene's end holds a copy of the tile's
 // first triangle, so no masks).  The same arithmetic at scene setup and in
 // the bounds pass.
+// A triangle's cylinder about its AABB centre, widened and packed into one
+// word: horizontal radius rh (low half) and vertical half-height hz (high
+// half), each widened by 1e-4 relative, 2e-4 of the other (a sensor up axis
+// up to 1e-4 off the z axis mixes the two) and 1e-6 m, rounded up to FP16.
+__device__ inline uint32_t pack_cylinder(float rh, float hz) {
+  const float a = fmaf(rh, 1.0001f, fmaf(hz, 2e-4f, 1e-6f));
+  const float b = fmaf(hz, 1.0001f, fmaf(rh, 2e-4f, 1e-6f));
+  return half_up(a) | (half_up(b) << 16);
+}
+
+// Each of a lane's two triangles: AABB centre in tc[h][0..2], the bits of
+// its packed cylinder in tc[h][3].
 __device__ inline void tri_spheres(const float (&v)[2][9], float (&tc)[2][4]) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -975,16 +1033,17 @@ __device__ inline void tri_spheres(const float (&v)[2][9], float (&tc)[2][4]) {
       mx[c] = fmaxf(v[h][c], fmaxf(v[h][3 + c], v[h][6 + c]));
       tc[h][c] = 0.5f * (mn[c] + mx[c]);
     }
-    float r2 = 0.0f;
+    float rh2 = 0.0f, hz = 0.0f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const float ex = v[h][3 * k] - tc[h][0], ey = v[h][3 * k + 1] - tc[h][1],
                   ez = v[h][3 * k + 2] - tc[h][2];
-      r2 = fmaxf(r2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+      rh2 = fmaxf(rh2, fmaf(ex, ex, ey * ey));
+      hz = fmaxf(hz, fabsf(ez));
     }
-    // hardware square root (1 ulp; a denormal r2 may give 0): the sphere
-    // tests widen every radius by 1e-4 relative and 1e-6 m
-    tc[h][3] = __builtin_amdgcn_sqrtf(r2);
+    // hardware square root (1 ulp; a denormal rh2 may give 0): covered by
+    // the widening
+    tc[h][3] = __uint_as_float(pack_cylinder(__builtin_amdgcn_sqrtf(rh2), hz));
   }
 }
 __device__ inline void tile_sphere(const float (&v)[2][9], const float (&tc)[2][4],
@@ -1156,9 +1215,9 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
         const bool gr = (g_range >> ln) & 1ull, gp = (g_pole >> ln) & 1ull;
         const bool gf = (g_fov >> ln) & 1ull;
         const GroupVerdict v0 =
-            sphere_test<true>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s, gr, gp, gf);
+            sphere_test<true, true>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s, gr, gp, gf);
         const GroupVerdict v1 =
-            sphere_test<true>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s, gr, gp, gf);
+            sphere_test<true, true>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s, gr, gp, gf);
         tested += n_active;
         const bool keep0 = active[0] && !v0.culled;
         const bool keep1 = active[1] && !v1.culled;

@@ -433,3 +433,59 @@ def test_degenerate_inputs(ctx):
         # exact duplicates have bitwise equal distances: the smaller id must win
         assert not np.any(t == dup[1]), "the larger id of a duplicated triangle won"
         print(f"degenerate sensor {k}", rep["counts"], flush=True)
+
+
+def _tilted(s, tau, axis_yaw):
+    """Sensor `s` with its frame turned by tau about a horizontal axis at
+    azimuth axis_yaw (Rodrigues), so that its up vector leaves the z axis by
+    tau."""
+    k = np.array([math.cos(axis_yaw), math.sin(axis_yaw), 0.0])
+    def rot(x):
+        x = np.asarray(x, np.float64)
+        return (x * math.cos(tau) + np.cross(k, x) * math.sin(tau)
+                + k * np.dot(k, x) * (1 - math.cos(tau)))
+    t = dict(s)
+    for key in ("forward", "right", "up"):
+        t[key] = rot(s[key]).astype(np.float32)
+    return t
+
+
+def test_cylinder_bound_all_pairs(ctx):
+    _say("triangle tests with the upright-cylinder margin: a bumpy fine ground grid seen at "
+         "grazing angles plus walls, upright / nearly upright (tilt 5e-5) / tilted sensors, "
+         "one cast vs all-pairs per sensor")
+    n = 240
+    xs = np.linspace(-30.0, 30.0, n + 1)
+    gx, gy = np.meshgrid(xs, xs, indexing="ij")
+    gz = 0.03 * np.sin(1.7 * gx) * np.cos(1.3 * gy) - 0.5
+    gv = np.stack([gx, gy, gz], -1).reshape(-1, 3)
+    i = np.arange(n)[:, None] * (n + 1)
+    j = np.arange(n)[None, :]
+    a, b = i + j, i + j + 1
+    c, d = a + n + 1, b + n + 1
+    gf = np.stack([np.stack([a, b, c], -1), np.stack([b, d, c], -1)], 2).reshape(-1, 3)
+    wv, wf = _cylinders([12.0, 26.0], 180, 8, 6.0)
+    v = np.concatenate([gv, wv]).astype(np.float32)
+    f = np.concatenate([gf, wf + len(gv)]).astype(np.uint32)
+    ctx.scene_update(0, v, f)
+    chans = synth.elevations_uniform(-30, 12, 48)
+    base = [synth.sensor((0.37, -0.21, h), yaw, chans, 512, fov, 0.05, 100.0)
+            for h, yaw, fov in ((-0.2, 0.3, 360.0), (1.8, -1.1, 360.0), (0.4, 2.0, 180.0),
+                                (1.1, 0.7, 360.0), (2.5, -2.4, 360.0))]
+    sens = [base[0], base[1], base[2], _tilted(base[3], 5e-5, 0.4),
+            _tilted(base[4], 0.25, 1.9)]
+    ids = list(range(60, 60 + len(sens)))
+    for k, s in zip(ids, sens):
+        ctx.sensor_config(k, s, 0)
+    n1 = 48 * 512
+    dd, tt = _cast(ctx, ids, len(ids) * n1)
+    for k, i_ in enumerate(ids):
+        d2, t2 = _cast(ctx, [i_], n1, grca.GRCA_CAST_ALL_PAIRS)
+        sl = slice(k * n1, (k + 1) * n1)
+        assert np.array_equal(tt[sl], t2), f"sensor {k}: culled != all-pairs"
+        assert np.array_equal(dd[sl].view(np.uint32), d2.view(np.uint32))
+    orc = O.cast(sens[1], v, f, rays=np.arange(0, n1, 29))
+    sel = orc["rays"]
+    rep = parity.check(sens[1], v, f, orc, dd[n1:2 * n1][sel], tt[n1:2 * n1][sel])
+    parity.assert_parity(rep, "cylinder bound")
+    assert np.count_nonzero(tt != grca.GRCA_MISS_TRI) > len(ids) * n1 // 3
