@@ -45,16 +45,16 @@ FLOPS_PER_RTIC = 22               # ray test: 2 mul (direction) + 4 dot products
 #   angular margin 11 (the cylinder bound of an upright sensor; 6 for the
 #   sphere's otherwise), sqrt 1, elevation atan2 19, channel-grid indices 6:
 #   68 (63 for a sensor that is not upright);
-# * the sphere test of a 128-triangle tile against one origin: 59 (its radius
-#   per tile, the sphere's margin), plus, for a partial field of view, the
-#   wedge test (two signed plane distances 3 + 3, margin 3): 68;
+# * the same test of a 128-triangle tile against one origin (its own packed
+#   cylinder): 68 (63), plus, for a partial field of view, the wedge test (two
+#   signed plane distances 3 + 3, margin 3): 9;
 # * candidate span of one pair on the common path (no range or pole test,
 #   azimuth offsets by the series bound): transform 54, |p|^2 15, sines 6,
 #   edge bulge 27, margins 2, channel bins 4, atan2 of vertex 0 20, offsets of
 #   vertices 1-2 28, full-turn test 1, azimuth margin 6, ray-index range 12.
 FLOPS_PER_SPHERE = 68           # upright sensors
 FLOPS_PER_SPHERE_TILTED = 63
-FLOPS_PER_TILE_TEST = 59
+FLOPS_PER_TILE_TEST = 68         # upright sensors (63 otherwise, as for triangles)
 FLOPS_PER_WEDGE = 9
 FLOPS_PER_SPAN = 175
 
@@ -351,14 +351,15 @@ def main():
         upright = all(abs(float(s["up"][0])) + abs(float(s["up"][1])) <= 1e-4
                       and float(s["up"][2]) > 0 for s in wl.sensors)
         per_tri = FLOPS_PER_SPHERE if upright else FLOPS_PER_SPHERE_TILTED
-        flops = (FLOPS_PER_TILE_TEST * tile_tests + FLOPS_PER_WEDGE * wedge_tests +
+        per_tile = FLOPS_PER_TILE_TEST if upright else FLOPS_PER_SPHERE_TILTED
+        flops = (per_tile * tile_tests + FLOPS_PER_WEDGE * wedge_tests +
                  per_tri * stats["sphere_tests"] +
                  FLOPS_PER_SPAN * stats["pairs_evaluated"])
         achieved = flops / (stage_ms["bounds"] * 1e-3) / 1e12
         roof = {"kernel": "bounds_kernel", "bound": "alu", "achieved": achieved,
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                 "traffic": load_traffic("bounds_kernel"),
-                "work": f"{FLOPS_PER_TILE_TEST} FP32 flops x {tile_tests} tile tests + "
+                "work": f"{per_tile} FP32 flops x {tile_tests} tile tests + "
                         f"{FLOPS_PER_WEDGE} x {wedge_tests} tile wedge tests + "
                         f"{per_tri} x {stats['sphere_tests']} triangle tests + "
                         f"{FLOPS_PER_SPAN} x {stats['pairs_evaluated']} (triangle, origin) spans "

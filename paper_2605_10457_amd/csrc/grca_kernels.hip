@@ -818,9 +818,10 @@ __device__ inline float unpack_half(uint32_t b) {
   return (float)__builtin_bit_cast(_Float16, (uint16_t)b);
 }
 
-// A bounding sphere (centre c, radius rad) against sensor `s`, without
-// memory access besides the sensor's fields and without branches (so that
-// the fields are read together); about 70 FP32 operations, 80 with AZ.
+// The bounds of a triangle or a tile (centre c; an upright cylinder about c
+// packed in `rad`, and the sphere about c that holds the cylinder) against
+// sensor `s`, without memory access besides the sensor's fields (read
+// together); about 80 FP32 operations, 90 with AZ.
 // Culled when the sphere lies beyond range_max, when no channel elevation
 // lies within alpha of the elevation of c, or (AZ, partial field of view)
 // when it lies outside the field of view's wedge.  For
@@ -835,8 +836,8 @@ __device__ inline float unpack_half(uint32_t b) {
 // skip the parts whose verdict the caller will not use: false gives
 // need_range = need_pole = false and no field-of-view test.
 //
-// TRI: a triangle's test, `rad` holding the bits of its packed cylinder
-// (pack_cylinder): horizontal radius rh and vertical half-height hz about c,
+// `rad` holds the bits of a packed cylinder (pack_cylinder) of the triangle
+// or tile: horizontal radius rh and vertical half-height hz about c,
 // both already widened.  The sphere radius is then sqrt(rh^2 + hz^2), and for
 // a sensor whose up axis is the world z axis the angular margin is the
 // cylinder's instead of the sphere's: every point of the triangle has height
@@ -847,12 +848,12 @@ __device__ inline float unpack_half(uint32_t b) {
 // its elevation is within ((rho_c + rh) hz + (|z_c| + hz) rh) / (D - r)^2 of
 // c's.  For a ground triangle at a shallow angle (hz ~ 0) that is sin|el|
 // times the sphere's margin.
-template <bool AZ, bool TRI = false>
+template <bool AZ>
 __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float rad,
                                            const DevSensor& s, bool want_range = true,
                                            bool want_pole = true, bool want_fov = true) {
-  float r, rh = 0.0f, hz = 0.0f;
-  if (TRI) {
+  float r, rh, hz;
+  {
     uint32_t pk = __float_as_uint(rad);
     // (an empty asm that the compiler must take as changing pk: the unpacked
     // values are recomputed per test rather than hoisted out of the caller's
@@ -861,8 +862,6 @@ __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float r
     rh = unpack_half(pk & 0xFFFFu);
     hz = unpack_half(pk >> 16);
     r = __builtin_amdgcn_sqrtf(fmaf(rh, rh, hz * hz));
-  } else {
-    r = rad * 1.0001f + 1e-6f;
   }
   const float dx = cx - s.o[0], dy = cy - s.o[1], dz = cz - s.o[2];
   const float lf = fmaf(dx, s.f[0], fmaf(dy, s.f[1], dz * s.f[2]));
@@ -879,7 +878,7 @@ __device__ inline GroupVerdict sphere_test(float cx, float cy, float cz, float r
   // where the sphere is near)
   const float hc = __builtin_amdgcn_sqrtf(h2);
   float m;
-  if (TRI && s.upright) {
+  if (s.upright) {
     // (used only when far: D > 2 r, so D - r > r > 0; the factor 1.0001
     // covers the FP32 error of D - r)
     const float inv = __builtin_amdgcn_rcpf(D - r);
@@ -1005,14 +1004,12 @@ __device__ inline uint32_t item_candidates(const Item& it) {
 // the spills cost more than the extra wave gains).
 constexpr int BOUNDS_WAVES_PER_SIMD = 7;
 
-// Bounding spheres of a lane's two triangles (AABB centre, largest vertex
-// distance) and of the wave's 128-triangle tile (wave-uniform: the mean of
-// the 128 slots' triangle centres, the largest vertex distance from it; any
-// centre will do, and a slot past the scene's end holds a copy of the tile's
-// first triangle, so no masks).  The same arithmetic at scene setup and in
-// the bounds pass.
-// A triangle's cylinder about its AABB centre, widened and packed into one
-// word: horizontal radius rh (low half) and vertical half-height hz (high
+// Bounding cylinders of a lane's two triangles (about the AABB centre) and
+// of the wave's 128-triangle tile (wave-uniform: about the mean of the 128
+// slots' triangle centres; any centre will do, and a slot past the scene's
+// end holds a copy of the tile's first triangle, so no masks).  The same
+// arithmetic at scene setup and in the bounds pass.
+// A cylinder about a centre, widened and packed into one word: horizontal radius rh (low half) and vertical half-height hz (high
 // half), each widened by 1e-4 relative, 2e-4 of the other (a sensor up axis
 // up to 1e-4 off the z axis mixes the two) and 1e-6 m, rounded up to FP16.
 __device__ inline uint32_t pack_cylinder(float rh, float hz) {
@@ -1052,20 +1049,22 @@ __device__ inline void tile_sphere(const float (&v)[2][9], const float (&tc)[2][
 #pragma unroll
   for (int c = 0; c < 3; ++c)
     g[c] = first_lane(wave_sum_dpp(tc[0][c] + tc[1][c]) * (1.0f / 128.0f));
-  float gr2 = 0.0f;
+  float rh2 = 0.0f, hz = 0.0f;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const float ex = v[h][3 * k] - g[0], ey = v[h][3 * k + 1] - g[1],
                   ez = v[h][3 * k + 2] - g[2];
-      gr2 = fmaxf(gr2, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+      rh2 = fmaxf(rh2, fmaf(ex, ex, ey * ey));
+      hz = fmaxf(hz, fabsf(ez));
     }
   }
   gs[0] = g[0];
   gs[1] = g[1];
   gs[2] = g[2];
-  gs[3] = first_lane(__builtin_amdgcn_sqrtf(wave_max_dpp(gr2)));
+  gs[3] = __uint_as_float(first_lane(
+      pack_cylinder(__builtin_amdgcn_sqrtf(wave_max_dpp(rh2)), wave_max_dpp(hz))));
 }
 
 // Scene setup: the spheres of the n_pre leading tiles, one wave per tile,
@@ -1215,9 +1214,9 @@ __global__ __launch_bounds__(WPB * 64, INLINE || LOSSY ? 1 : BOUNDS_WAVES_PER_SI
         const bool gr = (g_range >> ln) & 1ull, gp = (g_pole >> ln) & 1ull;
         const bool gf = (g_fov >> ln) & 1ull;
         const GroupVerdict v0 =
-            sphere_test<true, true>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s, gr, gp, gf);
+            sphere_test<true>(tc[0][0], tc[0][1], tc[0][2], tc[0][3], s, gr, gp, gf);
         const GroupVerdict v1 =
-            sphere_test<true, true>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s, gr, gp, gf);
+            sphere_test<true>(tc[1][0], tc[1][1], tc[1][2], tc[1][3], s, gr, gp, gf);
         tested += n_active;
         const bool keep0 = active[0] && !v0.culled;
         const bool keep1 = active[1] && !v1.culled;
